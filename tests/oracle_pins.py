@@ -1,0 +1,482 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each function returns a non-negative error; the pin holds when it is below the stated
+tolerance.  ``test_oracle_*.py`` asserts the tolerances, and ``test_oracle_mutations.py``
+plants plausible mistakes in the oracle and checks that some pin then fails.
+None of these re-types the oracle's formula: they compare with numpy.fft, with exact
+orthogonality of rank-1 lattices, with independent enumeration rules, with the dense
+d-dimensional matrix built from full frequency vectors, with scipy's LSQR, with dense
+linear algebra and with finite differences.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+
+from oracle import fista as ofista
+from oracle import index_set as oidx
+from oracle import lsqr as olsqr
+from oracle import transform as otr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+# ---------------------------------------------------------------- index set
+def pin_printed_counts() -> float:
+    """|I_N(U)| and |U| printed in the paper (tests/golden/cardinalities.json)."""
+    with open(os.path.join(GOLDEN, "cardinalities.json")) as fh:
+        cases = json.load(fh)["cases"]
+    err = 0
+    for c in cases:
+        if "coeffs" in c:
+            iset = oidx.grouped_index_set(c["d"], c["ds"], c["N"])
+            err += abs(iset.n_coeffs - c["coeffs"])
+            err += abs(oidx.count_coeffs(c["d"], c["ds"], c["N"]) - c["coeffs"])
+        if "terms" in c:
+            err += abs(len(oidx.anova_terms(c["d"], c["ds"])) - c["terms"])
+    return float(err)
+
+
+def pin_ordering(d=4, ds=3, N=(6, 4, 4)) -> float:
+    """Coefficient order equals the rule stated in the oracle header, enumerated independently."""
+    iset = oidx.grouped_index_set(d, ds, N)
+    expect = []
+    for t in range(ds + 1):
+        for u in itertools.combinations(range(d), t):
+            band = [k for k in range(-N[t - 1] // 2, N[t - 1] // 2) if k != 0] if t else []
+            for ell in itertools.product(band, repeat=t):
+                k = [0] * d
+                for c, v in zip(u, ell):
+                    k[c] = v
+                expect.append(k)
+    got = iset.full_frequencies()
+    if got.shape != (len(expect), d):
+        return 1.0
+    return float(np.abs(got - np.array(expect)).sum())
+
+
+# ---------------------------------------------------------------- transform
+def pin_dense_matrix(seed=1, d=4, ds=3, N=(6, 4, 4), M=37) -> float:
+    """Forward and adjoint equal products with the d-dimensional matrix of eq. FM (k in Z^d)."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    # independent construction: full frequency vectors from the ordering rule
+    K = []
+    for t in range(ds + 1):
+        for u in itertools.combinations(range(d), t):
+            band = [k for k in range(-N[t - 1] // 2, N[t - 1] // 2) if k != 0] if t else []
+            for ell in itertools.product(band, repeat=t):
+                k = np.zeros(d)
+                k[list(u)] = ell
+                K.append(k)
+    K = np.array(K)
+    A = np.cos(2 * np.pi * x @ K.T) + 1j * np.sin(2 * np.pi * x @ K.T)
+    return max(rel(otr.forward(iset, x, fh), A @ fh), rel(otr.adjoint(iset, x, y), A.conj().T @ y))
+
+
+def pin_hypercube_fft(d=3, N=6) -> float:
+    """U = P(D), N_u = N, nodes on the grid l/N: the grouped transform is a d-dim inverse FFT.
+
+    The groups of P(D) partition I_N^d (eq. hypercube), so F fhat on the grid equals
+    N^d * numpy.fft.ifftn of the coefficients placed at k mod N, and F^H y equals
+    numpy.fft.fftn of the samples read at k mod N.
+    """
+    iset = oidx.grouped_index_set(d, d, [N] * d)
+    grid = np.array(list(itertools.product(range(N), repeat=d)))       # l in {0..N-1}^d
+    x = grid / N
+    x = np.where(x >= 0.5, x - 1.0, x)                                   # same torus points
+    g = np.random.default_rng(7)
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    K = iset.full_frequencies()
+    if len(K) != N ** d:
+        return 1.0
+    C = np.zeros((N,) * d, dtype=complex)
+    for val, k in zip(fh, K):
+        C[tuple(np.mod(k, N))] += val
+    ref = (N ** d) * np.fft.ifftn(C)
+    got = otr.forward(iset, x, fh)
+    e1 = rel(got, np.array([ref[tuple(l)] for l in grid]))
+    y = g.standard_normal(len(grid)) + 1j * g.standard_normal(len(grid))
+    Y = np.zeros((N,) * d, dtype=complex)
+    for val, l in zip(y, grid):
+        Y[tuple(l)] = val
+    F = np.fft.fftn(Y)
+    e2 = rel(otr.adjoint(iset, x, y), np.array([F[tuple(np.mod(k, N))] for k in K]))
+    return max(e1, e2)
+
+
+def lattice(iset, M, seed=3, tries=20000):
+    """Rank-1 lattice x_j = (j z / M) mod 1 whose Fourier matrix has orthogonal columns.
+
+    F^H F = M I holds exactly when the values <k, z> mod M are distinct over the index set
+    (character orthogonality on Z_M); z is searched at random and checked by brute force.
+    """
+    K = iset.full_frequencies()
+    g = np.random.default_rng(seed)
+    for _ in range(tries):
+        z = g.integers(1, M, size=iset.d)
+        r = np.mod(K @ z, M)
+        if len(np.unique(r)) == len(r):
+            j = np.arange(M)[:, None]
+            x = np.mod(j * z[None, :], M) / M
+            return np.where(x >= 0.5, x - 1.0, x), z
+    raise RuntimeError("no lattice generator found")
+
+
+def pin_lattice_orthogonality(d=3, ds=2, N=(8, 4), M=211) -> float:
+    """F^H F fhat = M fhat on a reconstructing rank-1 lattice (pins forward and adjoint together)."""
+    iset = oidx.grouped_index_set(d, ds, N)
+    x, _ = lattice(iset, M)
+    g = np.random.default_rng(5)
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    return rel(otr.adjoint(iset, x, otr.forward(iset, x, fh)), M * fh)
+
+
+def pin_adjoint_identity(seed=2, d=5, ds=3, N=(10, 6, 4), M=50) -> float:
+    """<F fhat, y> = <fhat, F^H y>."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    a = np.vdot(y, otr.forward(iset, x, fh))
+    b = np.vdot(otr.adjoint(iset, x, y), fh)
+    return abs(a - b) / abs(a)
+
+
+def pin_modulation(seed=4, d=4, ds=2, N=(8, 6), M=30, j=2, shift=0.137) -> float:
+    """Shifting x_j by s multiplies every coefficient with u containing j by e^{2 pi i l_j s}."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    K = iset.full_frequencies()
+    mod = fh * np.exp(2j * np.pi * K[:, j] * shift)
+    xs = x.copy()
+    xs[:, j] += shift
+    return rel(otr.forward(iset, xs, fh), otr.forward(iset, x, mod))
+
+
+def pin_group_isolation(seed=6, d=5, ds=2, N=(8, 6), M=25) -> float:
+    """A coefficient vector supported on one group u depends only on x_u; the empty set is constant."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    err = 0.0
+    for ti in (0, 3, iset.n_terms - 1):
+        u = iset.terms[ti]
+        fh = np.zeros(iset.n_coeffs, dtype=complex)
+        sl = iset.term_slice(ti)
+        fh[sl] = g.standard_normal(sl.stop - sl.start)
+        x2 = x.copy()
+        others = [c for c in range(d) if c not in u]
+        x2[:, others] = g.random((M, len(others))) - 0.5
+        err = max(err, rel(otr.forward(iset, x2, fh), otr.forward(iset, x, fh)))
+        if not u:
+            err = max(err, float(np.abs(otr.forward(iset, x, fh) - fh[0]).max()))
+    return err
+
+
+def pin_single_frequency(seed=8, d=4, ds=3, N=(6, 4, 4), M=20) -> float:
+    """fhat = unit vector at (u, l) gives exactly e^{2 pi i <l, x_u>} (closed form by cos/sin)."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    K = iset.full_frequencies()
+    err = 0.0
+    for p in g.choice(iset.n_coeffs, size=6, replace=False):
+        e = np.zeros(iset.n_coeffs)
+        e[p] = 1.0
+        ang = 2 * math.pi * (x @ K[p])
+        err = max(err, float(np.abs(otr.forward(iset, x, e) - (np.cos(ang) + 1j * np.sin(ang))).max()))
+    return err
+
+
+def pin_gradient_fd(seed=9, d=4, ds=2, N=(8, 6), M=12, h=1e-5) -> float:
+    """Node gradient against central finite differences of the forward transform."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) * 0.8 - 0.4
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    D = otr.node_gradient(iset, x, fh)
+    FD = np.zeros_like(D)
+    for j in range(d):
+        xp, xm = x.copy(), x.copy()
+        xp[:, j] += h
+        xm[:, j] -= h
+        FD[:, j] = (otr.forward(iset, xp, fh) - otr.forward(iset, xm, fh)) / (2 * h)
+    return rel(D, FD)
+
+
+# ---------------------------------------------------------------- LSQR
+def _small_problem(seed, d=3, ds=2, N=(8, 4), M=120):
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    return iset, x, y, g
+
+
+def pin_lsqr_dense(seed=11, lam=0.3, weighted=True) -> float:
+    """Converged LSQR equals the dense solve of (F^H F + 2 lambda W) fhat = F^H y."""
+    iset, x, y, g = _small_problem(seed)
+    A = otr.dense_matrix(iset, x)
+    omega = (1.0 + g.random(iset.n_coeffs) * 3.0) if weighted else None
+    W = np.diag(omega if omega is not None else np.ones(iset.n_coeffs))
+    ref = np.linalg.solve(A.conj().T @ A + 2 * lam * W, A.conj().T @ y)
+    res = olsqr.lsqr(lambda v: otr.forward(iset, x, v), lambda r: otr.adjoint(iset, x, r),
+                     y, iset.n_coeffs, lam, omega, iters=4 * iset.n_coeffs)
+    return rel(res.fhat, ref)
+
+
+def pin_lsqr_scipy(seed=12, lam=0.05, iters=7) -> float:
+    """The K-th iterate equals scipy.sparse.linalg.lsqr's K-th iterate (same damping sqrt(2 lambda))."""
+    from scipy.sparse.linalg import lsqr as sp_lsqr
+    iset, x, y, _ = _small_problem(seed)
+    A = otr.dense_matrix(iset, x)
+    ref = sp_lsqr(A, y, damp=math.sqrt(2 * lam), iter_lim=iters, atol=0, btol=0, conlim=0)[0]
+    res = olsqr.lsqr(lambda v: otr.forward(iset, x, v), lambda r: otr.adjoint(iset, x, r),
+                     y, iset.n_coeffs, lam, None, iters=iters)
+    return rel(res.fhat, ref)
+
+
+def pin_lsqr_lattice(lam=0.7) -> float:
+    """Orthogonal F (F^H F = M I): fhat = F^H y / (M + 2 lambda), reached in one step."""
+    iset = oidx.grouped_index_set(3, 2, (8, 4))
+    M = 211
+    x, _ = lattice(iset, M)
+    g = np.random.default_rng(13)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    ref = otr.adjoint(iset, x, y) / (M + 2 * lam)
+    res = olsqr.lsqr(lambda v: otr.forward(iset, x, v), lambda r: otr.adjoint(iset, x, r),
+                     y, iset.n_coeffs, lam, None, iters=3)
+    return rel(res.fhat, ref)
+
+
+# ---------------------------------------------------------------- prox / FISTA
+def pin_prox_soft_threshold(seed=21) -> float:
+    """omega = 1: the prox is block soft-thresholding x_u = (1 - tau/||z_u||)_+ z_u."""
+    g = np.random.default_rng(seed)
+    offsets = [0, 1, 8, 15, 64]
+    z = g.standard_normal(64) + 1j * g.standard_normal(64)
+    tau = 2.5
+    ref = np.zeros_like(z)
+    for a, b in zip(offsets[:-1], offsets[1:]):
+        nrm = np.linalg.norm(z[a:b])
+        ref[a:b] = max(0.0, 1.0 - tau / nrm) * z[a:b]
+    return rel(ofista.prox(z, offsets, tau), ref)
+
+
+def pin_prox_minimises(seed=22) -> float:
+    """Weighted prox output minimises its objective: compare with scipy.optimize on tiny groups."""
+    from scipy.optimize import minimize
+    g = np.random.default_rng(seed)
+    offsets = [0, 3, 7]
+    n = 7
+    z = g.standard_normal(n) + 1j * g.standard_normal(n)
+    omega = 1.0 + 4.0 * g.random(n)
+    err = 0.0
+    for tau in (0.3, 1.1, 2.0):
+        x = ofista.prox(z, offsets, tau, omega)
+
+        def obj(v):
+            c = v[:n] + 1j * v[n:]
+            val = 0.5 * np.sum(np.abs(c - z) ** 2)
+            for a, b in zip(offsets[:-1], offsets[1:]):
+                val += tau * np.sqrt(np.sum(omega[a:b] * np.abs(c[a:b]) ** 2) + 1e-300)
+            return val
+        v0 = np.concatenate([x.real, x.imag])
+        best = minimize(obj, np.concatenate([z.real, z.imag]), method="Nelder-Mead",
+                        options=dict(maxiter=40000, xatol=1e-12, fatol=1e-14))
+        # the oracle's value must not exceed the numerical optimum
+        err = max(err, max(0.0, obj(v0) - best.fun))
+        # and random perturbations must not improve it (convexity)
+        for _ in range(50):
+            dv = g.standard_normal(2 * n) * 1e-3
+            err = max(err, max(0.0, obj(v0) - obj(v0 + dv)))
+    return err
+
+
+def pin_prox_zero_threshold(seed=23) -> float:
+    """Lemma (iii): a group is zero exactly when tau >= (sum |z_k|^2 / omega_k)^{1/2}."""
+    g = np.random.default_rng(seed)
+    z = g.standard_normal(9) + 1j * g.standard_normal(9)
+    omega = 1.0 + g.random(9)
+    lvl = math.sqrt(float(np.sum(np.abs(z) ** 2 / omega)))
+    above = ofista.prox(z, [0, 9], lvl * 1.0001, omega)
+    below = ofista.prox(z, [0, 9], lvl * 0.999, omega)
+    return float(np.abs(above).max()) + (1.0 if np.abs(below).max() == 0 else 0.0)
+
+
+def pin_prox_ridge_link(seed=24) -> float:
+    """Lemma (i)/(ii): the prox equals the ridge minimiser y/(1 + 2 xi' omega) at the matching xi'.
+
+    Pick xi' > 0, set lambda = ||(y_k / (1/(2 xi') + omega_k))||_W (Lemma (ii)); then the
+    group prox at tau = lambda must return diag(1/(1 + 2 xi' omega)) y (Lemma (i)).
+    """
+    g = np.random.default_rng(seed)
+    y = g.standard_normal(11) + 1j * g.standard_normal(11)
+    omega = 1.0 + 3.0 * g.random(11)
+    err = 0.0
+    for xi2 in (0.05, 0.7, 4.0, 40.0):
+        lam = math.sqrt(float(np.sum(omega * np.abs(y / (1.0 / (2 * xi2) + omega)) ** 2)))
+        ridge = y / (1.0 + 2 * xi2 * omega)
+        err = max(err, rel(ofista.prox(y, [0, 11], lam, omega), ridge))
+    return err
+
+
+def _fista_problem(seed=31, d=3, ds=2, N=(8, 4), M=150):
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    A = otr.dense_matrix(iset, x)
+    return iset, x, y, A
+
+
+def _kkt(iset, A, y, f, lam) -> float:
+    """Group-lasso optimality: (F^H(y - F f))_u = lam f_u/||f_u|| if f_u != 0, else its norm <= lam."""
+    gr = A.conj().T @ (y - A @ f)
+    err = 0.0
+    for i in range(iset.n_terms):
+        sl = iset.term_slice(i)
+        nf = np.linalg.norm(f[sl])
+        if nf > 1e-12:
+            err = max(err, np.linalg.norm(gr[sl] - lam * f[sl] / nf) / lam)
+        else:
+            err = max(err, max(0.0, np.linalg.norm(gr[sl]) - lam) / lam)
+    return float(err)
+
+
+def pin_fista_kkt(lam=6.0, iters=600) -> float:
+    """KKT certificate at the FISTA output (constant step L = ||F||^2)."""
+    iset, x, y, A = _fista_problem()
+    L = np.linalg.norm(A, 2) ** 2
+    res = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, lam, L, iters)
+    return _kkt(iset, A, y, res.fhat, lam)
+
+
+def pin_fista_zero_above_lambda_max() -> float:
+    """lambda >= max_u ||(F^H y)_u|| gives the zero solution from a zero start."""
+    iset, x, y, A = _fista_problem()
+    gy = A.conj().T @ y
+    lmax = max(np.linalg.norm(gy[iset.term_slice(i)]) for i in range(iset.n_terms))
+    L = np.linalg.norm(A, 2) ** 2
+    res = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, lmax * 1.001, L, 50)
+    return float(np.abs(res.fhat).max())
+
+
+def pin_fista_lattice(lam=9.0) -> float:
+    """Orthogonal F: the group-lasso solution is (1 - lam/||(F^H y)_u||)_+ (F^H y)_u / M."""
+    iset = oidx.grouped_index_set(3, 2, (8, 4))
+    M = 211
+    x, _ = lattice(iset, M)
+    A = otr.dense_matrix(iset, x)
+    g = np.random.default_rng(33)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    gy = A.conj().T @ y
+    ref = np.zeros_like(gy)
+    for i in range(iset.n_terms):
+        sl = iset.term_slice(i)
+        nrm = np.linalg.norm(gy[sl])
+        ref[sl] = max(0.0, 1.0 - lam / nrm) * gy[sl] / M
+    res = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, lam, float(M), 40)
+    return rel(res.fhat, ref)
+
+
+def pin_fista_backtracking(lam=6.0) -> float:
+    """Backtracking from a too-small L0 (it must backtrack) reaches a KKT point as well."""
+    iset, x, y, A = _fista_problem()
+    L = np.linalg.norm(A, 2) ** 2
+    b = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, lam, L / 50, 600, eta=2.0)
+    return _kkt(iset, A, y, b.fhat, lam) + (0.0 if b.backtracks > 0 else 1.0)
+
+
+def pin_power_iteration() -> float:
+    """Power-iteration estimate against the dense spectral norm ||F||_2^2."""
+    iset, x, y, A = _fista_problem()
+    est = ofista.power_iteration(lambda v: A @ v, lambda r: A.conj().T @ r, iset.n_coeffs, 300)
+    ref = np.linalg.norm(A, 2) ** 2
+    return abs(est - ref) / ref
+
+
+def pin_fista_first_steps() -> float:
+    """t_1 = 1 makes the first momentum coefficient zero: with a negligible lambda the
+    first two FISTA iterates are two plain gradient steps f <- f - F^H(F f - y)/L."""
+    iset, x, y, A = _fista_problem()
+    L = np.linalg.norm(A, 2) ** 2
+    f1 = np.zeros(iset.n_coeffs, dtype=complex)
+    f1 = f1 - A.conj().T @ (A @ f1 - y) / L
+    f2 = f1 - A.conj().T @ (A @ f1 - y) / L
+    r1 = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, 1e-300, L, 1)
+    r2 = ofista.fista(lambda v: A @ v, lambda r: A.conj().T @ r, y, iset.offsets, 1e-300, L, 2)
+    return max(rel(r1.fhat, f1), rel(r2.fhat, f2))
+
+
+def pin_fista_rate(lam=3.0, K=60) -> float:
+    """Beck-Teboulle bound F(f_k) - F* <= 2 L ||f_0 - f*||^2 / (k+1)^2 for every k <= K.
+
+    Returns the largest ratio (gap / bound) minus 1, clipped at 0."""
+    iset, x, y, A = _fista_problem()
+    L = np.linalg.norm(A, 2) ** 2
+    mv, rmv = (lambda v: A @ v), (lambda r: A.conj().T @ r)
+    star = ofista.fista(mv, rmv, y, iset.offsets, lam, L, 1500).fhat
+    Fs = ofista.objective(mv, y, star, iset.offsets, lam)
+    worst = 0.0
+    for k in range(1, K + 1):
+        fk = ofista.fista(mv, rmv, y, iset.offsets, lam, L, k).fhat
+        gap = ofista.objective(mv, y, fk, iset.offsets, lam) - Fs
+        bound = 2 * L * np.linalg.norm(star) ** 2 / (k + 1) ** 2
+        worst = max(worst, gap / bound)
+    return max(0.0, worst - 1.0)
+
+
+# ---------------------------------------------------------------- pin table
+# (name, function, keyword arguments, tolerance): the pin holds when error <= tolerance.
+PINS = [
+    ("printed_counts", pin_printed_counts, {}, 0.0),
+    ("ordering", pin_ordering, {}, 0.0),
+    ("dense_matrix", pin_dense_matrix, {}, 1e-12),
+    ("hypercube_fft_1d", pin_hypercube_fft, dict(d=1, N=8), 1e-12),
+    ("hypercube_fft_2d", pin_hypercube_fft, dict(d=2, N=6), 1e-12),
+    ("hypercube_fft_3d", pin_hypercube_fft, dict(d=3, N=4), 1e-12),
+    ("lattice_orthogonality", pin_lattice_orthogonality, {}, 1e-12),
+    ("adjoint_identity", pin_adjoint_identity, {}, 1e-12),
+    ("modulation", pin_modulation, {}, 1e-12),
+    ("group_isolation", pin_group_isolation, {}, 1e-12),
+    ("single_frequency", pin_single_frequency, {}, 1e-12),
+    # central differences, h = 1e-5: truncation ~ (2 pi 8 h)^2/6, rounding ~ 1e-16/h
+    ("gradient_fd", pin_gradient_fd, {}, 1e-8),
+    ("lsqr_dense", pin_lsqr_dense, dict(weighted=False), 1e-9),
+    ("lsqr_dense_weighted", pin_lsqr_dense, dict(weighted=True), 1e-9),
+    ("lsqr_scipy_1", pin_lsqr_scipy, dict(iters=1), 1e-10),
+    ("lsqr_scipy_3", pin_lsqr_scipy, dict(iters=3), 1e-10),
+    ("lsqr_scipy_7", pin_lsqr_scipy, dict(iters=7), 1e-10),
+    ("lsqr_scipy_15", pin_lsqr_scipy, dict(iters=15), 1e-10),
+    ("lsqr_lattice", pin_lsqr_lattice, {}, 1e-12),
+    ("prox_soft_threshold", pin_prox_soft_threshold, {}, 1e-13),
+    ("prox_minimises", pin_prox_minimises, {}, 1e-9),
+    ("prox_zero_threshold", pin_prox_zero_threshold, {}, 0.0),
+    ("prox_ridge_link", pin_prox_ridge_link, {}, 1e-12),
+    ("fista_kkt", pin_fista_kkt, {}, 1e-12),
+    ("fista_zero_above_lambda_max", pin_fista_zero_above_lambda_max, {}, 0.0),
+    ("fista_lattice", pin_fista_lattice, {}, 1e-12),
+    ("fista_backtracking", pin_fista_backtracking, {}, 1e-12),
+    ("fista_first_steps", pin_fista_first_steps, {}, 1e-13),
+    ("fista_rate", pin_fista_rate, {}, 0.0),
+    ("power_iteration", pin_power_iteration, {}, 1e-6),
+]

@@ -1,0 +1,72 @@
+"""Plant plausible mistakes in copies of the oracle modules; some pin must fail for each.
+
+Each mutation edits one line of an oracle module's source, executes the edited source
+as a fresh module and swaps it into the pin module for the duration of the check.
+"""
+import importlib
+import inspect
+import sys
+import types
+
+import pytest
+
+from tests import oracle_pins as P
+
+# (module, attribute of oracle_pins holding it, old text, new text, what the mistake is)
+MUTATIONS = [
+    ("oracle.transform", "otr", "return np.exp(2j * np.pi * theta)", "return np.exp(-2j * np.pi * theta)",
+     "wrong sign of the exponent"),
+    ("oracle.transform", "otr", "out += c[:, :1]", "out += 0 * c[:, :1]", "dropped empty-set term"),
+    ("oracle.transform", "otr", "acc += Y[:, a:b] @ E.conj()", "acc += Y[:, a:b] @ E", "adjoint without conjugate"),
+    ("oracle.transform", "otr", "E = _phase_matrix(x[a:b][:, list(u)], ell)    # (chunk, G)",
+     "E = _phase_matrix(x[a:b][:, list(u)[::-1]], ell)", "coordinates of a term swapped"),
+    ("oracle.transform", "otr", "2j * np.pi * ell[:, pos] * c", "2j * np.pi * ell[:, pos - 1] * c",
+     "gradient uses the wrong frequency component"),
+    ("oracle.index_set", "oidx", "[k for k in range(-N // 2, N // 2) if k != 0]",
+     "[k for k in range(-N // 2 + 1, N // 2 + 1) if k != 0]", "band shifted by one"),
+    ("oracle.index_set", "oidx", "out.extend(itertools.combinations(range(d), t))",
+     "out.extend(sorted(itertools.combinations(range(d), t), reverse=True))", "term order reversed"),
+    ("oracle.lsqr", "olsqr", "damp = np.sqrt(2.0 * lam)", "damp = np.sqrt(lam)", "damping without the factor 2"),
+    ("oracle.lsqr", "olsqr", "rhobar = -c * alpha", "rhobar = c * alpha", "sign of rhobar"),
+    ("oracle.lsqr", "olsqr", "s = 1.0 / np.sqrt(omega)", "s = 1.0 / omega", "weights applied as W^-1"),
+    ("oracle.fista", "ofista", "x[sl] = zu / (1.0 + xi * wu)", "x[sl] = zu / (1.0 + 2.0 * xi * wu)",
+     "Lemma's 2 xi used with the Theorem's xi"),
+    ("oracle.fista", "ofista", "zero_level = np.sqrt(np.sum(np.abs(zu) ** 2 / wu))",
+     "zero_level = np.sqrt(np.sum(np.abs(zu) ** 2 * wu))", "zero threshold with omega instead of 1/omega"),
+    ("oracle.fista", "ofista", "h = f + ((t - 1.0) / t_next) * (f - f_prev)", "h = f + (t / t_next) * (f - f_prev)",
+     "momentum coefficient"),
+    ("oracle.fista", "ofista", "grad = rmatvec(Fh - y)", "grad = rmatvec(y - Fh)", "gradient sign"),
+]
+
+
+def _mutated(modname, old, new):
+    mod = importlib.import_module(modname)
+    src = inspect.getsource(mod)
+    assert old in src, f"mutation anchor not found in {modname}: {old!r}"
+    src = src.replace(old, new, 1)
+    name = modname + "_mutant"
+    m = types.ModuleType(name)
+    m.__package__ = "oracle"
+    sys.modules[name] = m          # dataclasses look their module up here
+    try:
+        exec(compile(src, name, "exec"), m.__dict__)
+    finally:
+        del sys.modules[name]
+    return m
+
+
+@pytest.mark.parametrize("modname,attr,old,new,what", MUTATIONS, ids=[m[4] for m in MUTATIONS])
+def test_mutation_is_caught(monkeypatch, modname, attr, old, new, what):
+    mutant = _mutated(modname, old, new)
+    monkeypatch.setattr(P, attr, mutant)
+    caught = []
+    for name, fn, kw, tol in P.PINS:
+        try:
+            err = fn(**kw)
+        except Exception:          # a crash also exposes the mistake
+            caught.append(name)
+            break
+        if not err <= tol:
+            caught.append(name)
+            break
+    assert caught, f"no pin caught: {what}"
