@@ -1,0 +1,185 @@
+"""Benchmark of the grouped Fourier transform hot path on one MI355X.
+
+Workload: d = 10, d_s = 2, bandwidths N = 64 (1-D terms) / 16 (2-D terms), 56 ANOVA terms,
+10,756 coefficients, M = 50,000 nodes uniform on [-1/2, 1/2)^10, complex coefficients and
+samples CN(0, 1), Kaiser-Bessel window m = 6, oversampling 2.  One step = one forward and
+one adjoint transform on a plan built once for the node set (inputs resident in HBM).
+
+metric: node-terms/s = 2 * M * |U| / (time of forward + adjoint), FP32 bulk arithmetic.
+Prints one JSON line.  Per-kernel durations come from HIP events the library records around
+every launch on the benchmark's stream during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+D, DS, NB, M, M_WIN, SIGMA = 10, 2, (64, 16), 50000, 6, 2.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA) x 2 (packed)
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_node_term(order: int, m: int) -> int:
+    """Algorithmic FLOPs of one node-term gather or spread: w^t real x complex MACs plus the
+    lower-dimensional partial sums (w = 2m), 4 flops per real x complex MAC."""
+    w = 2 * m
+    return 4 * sum(w ** k for k in range(1, order + 1))
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels_impl.h", "gt_internal.h"):
+        with open(os.path.join(ROOT, "paper_2010_10199_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    code = lib.GT_C64 if precision == "f32" else lib.GT_C128
+    ncoef = lib.gt_num_coeffs(D, DS, NB)
+    nterms = lib.gt_num_terms(D, DS)
+    x, fhat, y = W.trafo_inputs(2, D, DS, M, ncoef, 1, precision)
+    cdt = torch.complex64 if precision == "f32" else torch.complex128
+    xd = torch.from_numpy(x).cuda()
+    fd = torch.from_numpy(fhat.reshape(-1)).cuda()
+    yd = torch.from_numpy(y).cuda()
+    f_out = torch.empty(M, dtype=cdt, device="cuda")
+    a_out = torch.empty(ncoef, dtype=cdt, device="cuda")
+    stream = torch.cuda.current_stream()
+    prob, keep = lib.make_problem(D, DS, NB, M=M, R=1, dtype=code, m=M_WIN, sigma=SIGMA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = lib.Plan(prob, xd, keepalive=keep)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(warmup):
+        plan.trafo(fd, f_out)
+        plan.adjoint(yd, a_out)
+    torch.cuda.synchronize()
+    if profile:
+        lib.prof_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.trafo(fd, f_out)
+        plan.adjoint(yd, a_out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kern = {}
+    if profile:
+        kern = lib.prof_report()
+        lib.prof_enable(False)
+    plan.close()
+    return dict(ms=ms, plan_ms=plan_ms, nterms=nterms, ncoef=ncoef, kernels=kern)
+
+
+def cpu_baseline(sample_nodes: int):
+    """The FP64 oracle (direct sums) on the first `sample_nodes` nodes, forward + adjoint."""
+    import workloads as W
+    from oracle import index_set as oidx
+    from oracle import transform as otr
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    iset = oidx.grouped_index_set(D, DS, NB)
+    x, fhat, y = W.trafo_inputs(2, D, DS, M, iset.n_coeffs, 1, "f32")
+    xs, ys = x[:sample_nodes], y[:sample_nodes]
+    t0 = time.perf_counter()
+    otr.forward(iset, xs, fhat[0])
+    otr.adjoint(iset, xs, ys)
+    dt = time.perf_counter() - t0
+    return dict(value=2 * sample_nodes * iset.n_terms / dt, unit="node-terms/s", cores=int(threads), kind="oracle",
+                sample=f"forward + adjoint of the FP64 direct-sum oracle on the first {sample_nodes} of the "
+                       f"{M} nodes (all {iset.n_terms} terms), {dt:.1f} s on {os.cpu_count()} visible host cores; "
+                       "BLAS threads as counted, exponentials single-threaded")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="nodes for the oracle baseline (0 = skip)")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not run", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    print(f"[bench] fp32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    r32 = run_gpu("f32", args.steps, args.warmup, profile=True)
+    node_terms = 2 * M * r32["nterms"]
+    value = node_terms * args.steps / (r32["ms"] * 1e-3)
+    out = {
+        "metric": "grouped NFFT fwd+adj node-terms/s",
+        "value": value,
+        "unit": "node-terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "trafo-d10: grouped transform forward + adjoint, d=10, d_s=2, N=64/16, "
+                               "56 terms, 10,756 coefficients, M=50,000 uniform nodes, Kaiser-Bessel m=6, sigma=2",
+                   "d": D, "ds": DS, "N": list(NB), "M": M, "m": M_WIN, "sigma": SIGMA,
+                   "plan_ms": round(r32["plan_ms"], 3)},
+    }
+    # dominant kernel and its roofline
+    kern = r32["kernels"]
+    if kern:
+        name, (count, total) = max(kern.items(), key=lambda kv: kv[1][1])
+        avg_s = total / count * 1e-3
+        order = 2 if "2d" in name else (1 if "1d" in name else 3)
+        nterms_order = {1: D, 2: D * (D - 1) // 2, 3: D * (D - 1) * (D - 2) // 6}[order]
+        fl = M * nterms_order * flops_per_node_term(order, M_WIN)
+        achieved = fl / avg_s / 1e12
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tf):
+            with open(tf) as fh:
+                tj = json.load(fh)
+            ent = tj.get(name)
+            if ent and ent.get("kernel_hash") == kernel_hash():
+                traffic = ent.get("bytes_per_launch")
+        out["roofline"] = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                           "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl}
+        out["kernels_ms"] = {k: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3} for k, v in sorted(kern.items())}
+    if not args.no_fp64:
+        print("[bench] fp64", file=sys.stderr, flush=True)
+        r64 = run_gpu("f64", args.steps, args.warmup, profile=False)
+        out["fp64"] = {"value": node_terms * args.steps / (r64["ms"] * 1e-3), "unit": "node-terms/s",
+                       "ms_per_step": r64["ms"] / args.steps}
+    if args.cpu_sample > 0:
+        print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

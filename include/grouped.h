@@ -1,0 +1,185 @@
+/*
+ * grouped.h - C ABI of the MI355X (gfx950) grouped Fourier transform library.
+ *
+ * The operation (Bartel, Potts, Schmischke, "Grouped Transformations and Regularization
+ * in High-Dimensional Explainable ANOVA Approximation"):
+ *
+ *   forward  f_x   = sum_{u in U} sum_{k in I_{N_u}^{u,d}} fhat_k e^{2 pi i <k, x>}
+ *                    (Sec. 3, Definition def:skatoons), computed per term as a
+ *                    |u|-dimensional nonequispaced FFT of the projected nodes x_u
+ *                    (eq. somafm and the sum after it);
+ *   adjoint  fhat_u = F(X_u, I_{N_u}^{|u|})^H y, stacked over u (Sec. 3, adjoint display);
+ *   LSQR     min 1/2 ||y - F fhat||^2 + lambda ||fhat||_W^2        (Sec. 4.1, eq. new_min_prob);
+ *   FISTA    min 1/2 ||y - F fhat||^2 + lambda sum_u ||fhat_u||_W  (Sec. 4.2, eq. alligatoah,
+ *            Algorithm algo:fista, Theorem theorem:projection).
+ *
+ * U = U_{d_s} = {u subset {0..d-1} : |u| <= d_s} (eq. pizmosch), N_u = N[|u|-1] (one even
+ * bandwidth per order), I_N = {-N/2, ..., N/2-1} (eq. metallica).
+ *
+ * Coefficient order (the paper leaves it open, Sec. 3 before eq. bananarama): terms by order
+ * |u|, then lexicographically by the sorted coordinate tuple, the empty set first; inside a
+ * group the reduced frequency l = k_u runs row-major over (I_N minus {0})^{|u|}, last
+ * coordinate fastest, each ascending -N/2..-1, 1..N/2-1.  gt_term_table() exports it.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" are device memory of the current HIP device; "host" pointers are
+ *    ordinary host memory.  The library never frees, retains or writes caller memory other
+ *    than the documented outputs, and never keeps a caller pointer past the call (a plan keeps
+ *    its own copy of the nodes).
+ *  - Complex arrays are interleaved (re, im): float2 for GT_C64, double2 for GT_C128, which is
+ *    the memory layout of torch.complex64 / torch.complex128.  Real arrays use the matching
+ *    real type (float / double).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *    asynchronous unless stated otherwise.  Plan creation and the solvers synchronise the
+ *    stream where documented.
+ *  - Return value: GT_OK (0) or a negative gt_status.  Nothing aborts or throws across the
+ *    ABI.  gt_last_error() returns a thread-local description of the last failure.
+ *  - Nodes may be any finite reals; each coordinate is reduced modulo 1 into [-1/2, 1/2)
+ *    (the torus T = R/Z, Sec. 2).  NaN or Inf nodes give GT_EINVAL.
+ */
+#ifndef GROUPED_H
+#define GROUPED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GT_OK = 0,
+  GT_EINVAL = -1,        /* invalid argument (message in gt_last_error) */
+  GT_ENOMEM = -2,        /* device or host allocation failed */
+  GT_EHIP = -3,          /* a HIP runtime call failed */
+  GT_EUNSUPPORTED = -4   /* valid but outside what this build implements (e.g. d_s > 3) */
+} gt_status;
+
+enum { GT_C64 = 1, GT_C128 = 2 };   /* complex float (FP32 path) / complex double (FP64 path) */
+enum { GT_MAX_ORDER = 3 };          /* largest |u| the GPU path implements */
+
+/* Problem description (Sec. 2-4).  Plain data; copied by every call. */
+typedef struct gt_problem {
+  int32_t d;                   /* spatial dimension, >= 1 */
+  int32_t ds;                  /* superposition threshold, 0 <= ds <= min(d, 3) */
+  int32_t N[GT_MAX_ORDER];     /* N[k-1]: even bandwidth >= 2 of every term with |u| = k; unused entries ignored */
+  int64_t M;                   /* nodes (shared by all R right-hand sides); ignored when offsets != NULL */
+  int32_t R;                   /* batch: right-hand sides (lambda values) or ragged datasets, >= 1 */
+  const int64_t *offsets;      /* host, NULL or R+1 non-decreasing prefix offsets starting at 0: dataset b owns
+                                  nodes offsets[b]..offsets[b+1]-1 of the node array and has its own coefficients */
+  int32_t dtype;               /* GT_C64 or GT_C128 */
+  int32_t m;                   /* window half-width (Kaiser-Bessel support 2m grid points), 0 = chosen per order
+                                  from the precision; otherwise 2..8 */
+  double sigma;                /* oversampling factor n/N >= 1.5 of the FFT grids, 0 = 2.0 */
+} gt_problem;
+
+/* Solver report, one entry per right-hand side. */
+typedef struct gt_solve_info {
+  int32_t iters;               /* iterations done */
+  int32_t flags;               /* GT_SOLVE_* bits */
+  double resid;                /* LSQR: estimate of ||F^H(y - F fhat) - 2 lambda W fhat|| (normal equations);
+                                  FISTA: relative change ||f_k - f_{k-1}|| / ||f_k|| of the last step */
+  double t_k;                  /* FISTA momentum scalar t_{K+1} (resume); LSQR: phibar */
+  double L;                    /* FISTA step constant used last (after backtracking); LSQR: 0 */
+} gt_solve_info;
+
+enum {
+  GT_SOLVE_CONVERGED = 1,      /* tolerance reached */
+  GT_SOLVE_MAX_ITER = 2,       /* stopped at max_iter */
+  GT_SOLVE_BREAKDOWN = 4,      /* LSQR: alpha or beta became 0 (exact solution in the Krylov space) */
+  GT_SOLVE_BACKTRACK_CAP = 8   /* FISTA: a step hit the backtracking cap (30 increases of L) */
+};
+
+typedef struct gt_plan gt_plan;   /* opaque */
+
+/* ------------------------------------------------------------------ index set
+ * |U_{d_s}| = sum_{t<=ds} C(d, t) (eq. pizmosch).  Returns -1 on invalid d, ds. */
+int64_t gt_num_terms(int32_t d, int32_t ds);
+
+/* |I_N(U_{d_s})| = 1 + sum_{t=1..ds} C(d,t) (N[t-1]-1)^t (Remark rem:cardinality, eq. groupedset).
+ * N: host, ds entries.  Returns -1 on invalid arguments. */
+int64_t gt_num_coeffs(int32_t d, int32_t ds, const int32_t *N);
+
+/* Term table in coefficient order.  coords: host, |U| x 3 int32, coordinates of each term
+ * ascending, -1 padded; offsets: host, |U|+1 coefficient offsets.  Either may be NULL. */
+int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets);
+
+/* ------------------------------------------------------------------ one-shot transforms
+ * Each call builds a plan for (p, x), runs, and releases it in stream order.
+ *
+ * grouped_trafo   (Definition def:skatoons via eq. somafm):  f = F fhat.
+ *   x    device, real, Mtot x d row-major (Mtot = M, or offsets[R] when ragged)
+ *   fhat device, complex, R x |I|
+ *   f    device, complex, R x M (shared nodes) or Mtot (ragged, dataset b at offsets[b])
+ * grouped_adjoint (Sec. 3, adjoint display):  fhat = F^H y, same layouts with roles swapped. */
+int grouped_trafo(const gt_problem *p, const void *x, const void *fhat, void *f, void *stream);
+int grouped_adjoint(const gt_problem *p, const void *x, const void *y, void *fhat, void *stream);
+
+/* ------------------------------------------------------------------ plans
+ * A plan holds the index set, FFT grid sizes, window and deconvolution tables, the wrapped
+ * nodes (its own copy, transposed), the work lists and all scratch memory for (p, x).
+ * Creation synchronises `stream` once (to validate the nodes).  A plan may be used from one
+ * stream at a time; calls on the same plan must not overlap. */
+int gt_plan_create(const gt_problem *p, const void *x, void *stream, gt_plan **out);
+int gt_plan_destroy(gt_plan *plan);            /* synchronises the plan's last stream */
+int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream);
+int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream);
+
+/* Node gradient for reverse-mode differentiation (not in the paper; derivative of
+ * Definition def:skatoons).  With upstream gradient g = dL/d(conj f) (complex, layout of f)
+ * it writes gx[v][j] = Re( conj(d f_v / d x_{v,j}) * g_v ), real, Mtot x d row-major
+ * (per right-hand side summed over the R right-hand sides when nodes are shared). */
+int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, void *stream);
+
+/* Window half-width m and FFT grid size n chosen for order t (1..ds); for reports. */
+int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n);
+
+/* ------------------------------------------------------------------ solvers
+ * lsqr_solve: R independent weighted Tikhonov problems (eq. new_min_prob), one per
+ * right-hand side r with its own lambda[r] >= 0 (lambda = 0: eq. min_prob), solved by
+ * LSQR (Paige & Saunders) on A = F W^{-1/2} with damping sqrt(2 lambda); fhat = W^{-1/2} x.
+ *   y      device, complex, R x M (or ragged)
+ *   lambda host, R doubles >= 0
+ *   omega  device, real (dtype's), |I| weights > 0 shared by all r, or NULL (omega = 1)
+ *   max_iter >= 1; tol > 0: stop when every r has resid <= tol * resid_0 (checked every
+ *   8 iterations with one stream synchronisation), tol <= 0: run exactly max_iter.
+ *   fhat   device, complex, R x |I| (output)
+ *   info   host, R entries (output); the call synchronises `stream` before returning.
+ * Bulk vectors are in the dtype's precision; alpha, beta, norms and rotations are FP64. */
+int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *lambda,
+               const void *omega, int32_t max_iter, double tol, void *fhat,
+               gt_solve_info *info, void *stream);
+
+/* fista_group_lasso: R group-lasso problems (eq. alligatoah), lambda[r] > 0, every ANOVA
+ * term (the empty set included) one group, Algorithm algo:fista from fhat (in: start
+ * f_0, out: f_K).
+ *   L > 0: step constant; L <= 0: 1.05 x a 50-step power-iteration estimate of ||F||_2^2.
+ *   eta <= 1: constant step (the variant in the remark after the algorithm);
+ *   eta > 1: backtracking with factor eta (one host synchronisation per trial step).
+ *   tol > 0: stop when every r has relative step ||f_k - f_{k-1}|| / ||f_k|| <= tol (checked
+ *   every 8 iterations); tol <= 0: exactly max_iter iterations.
+ * Group norms, the proximal scale (closed form for omega = NULL, otherwise bisection +
+ * Newton for xi as in the remark after Theorem theorem:projection), t_k and the momentum
+ * are FP64. */
+int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda,
+                      const void *omega, int32_t max_iter, double L, double eta, double tol,
+                      void *fhat, gt_solve_info *info, void *stream);
+
+/* Power-iteration estimate of ||F||_2^2 (50 steps from the all-ones vector, FP64 scalars);
+ * synchronises `stream`.  Uses right-hand side 0 of the plan. */
+int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *stream);
+
+/* ------------------------------------------------------------------ diagnostics
+ * gt_last_error: thread-local message of the last failing call ("" if none).
+ * gt_prof_enable(1): record HIP events around every kernel launch (same stream);
+ * gt_prof_report: synchronises, writes a JSON object {kernel: [launches, total_ms]} into
+ * buf (truncated to len), clears the records and returns the needed length. */
+const char *gt_last_error(void);
+int gt_prof_enable(int32_t on);
+int64_t gt_prof_report(char *buf, int64_t len);
+const char *gt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GROUPED_H */

@@ -24,7 +24,7 @@ class LsqrResult:
     fhat: np.ndarray
     iters: int
     phibar: float         # last phibar of the recurrences (residual estimate of the damped system)
-    normal_est: float     # phibar * alpha * |c|: estimate of the normal-equation residual in x
+    normal_est: float     # |phibar| * alpha * |c|: estimate of the normal-equation residual in x
     breakdown: bool
 
 
@@ -90,7 +90,7 @@ def lsqr(matvec: Callable[[np.ndarray], np.ndarray],
         # update solution and search direction
         x = x + (phi / rho) * w
         w = v - (theta / rho) * w
-        normal = phibar * alpha * abs(c)
+        normal = abs(phibar) * alpha * abs(c)      # phibar carries a sign
         if beta == 0.0 or alpha == 0.0:
             breakdown = True
             break

@@ -101,3 +101,19 @@ def node_gradient(iset: GroupedIndexSet, x: np.ndarray, fhat: np.ndarray) -> np.
             for pos, j in enumerate(u):
                 D[a:b, j] += E @ (2j * np.pi * ell[:, pos] * c)
     return D
+
+
+def adjoint_at(iset: GroupedIndexSet, x: np.ndarray, y: np.ndarray, idx) -> np.ndarray:
+    """Selected entries of F^H y: fhat_k = sum_x y_x e^{-2 pi i <k, x>} for k = K[idx] (eq. FM).
+
+    Used to check full-size adjoints on a sample of coefficients; y of shape (M,)."""
+    K = iset.full_frequencies()[np.asarray(idx)].astype(np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.complex128)
+    out = np.zeros(K.shape[0], dtype=np.complex128)
+    for a in range(0, x.shape[0], _CHUNK):
+        b = min(x.shape[0], a + _CHUNK)
+        theta = x[a:b] @ K.T
+        theta = theta - np.round(theta)
+        out += y[a:b] @ np.exp(-2j * np.pi * theta)
+    return out

@@ -1,0 +1,156 @@
+// Internal declarations of the grouped Fourier transform library (not part of the ABI).
+//
+// Data layout in HBM (per plan):
+//   xT     d x Mtot real       nodes wrapped into [-1/2, 1/2), coordinate-major so that a
+//                              wavefront reads one coordinate of 64 consecutive nodes coalesced
+//   grids  R x grid_total      forward FFT grids of all terms, complex; a term of order t with
+//                              grid size n and window half-width m occupies
+//                              t=1: [P], t=2: [n][P], t=3: [n][n][P] with P = n + 2m - 1:
+//                              the innermost axis carries a periodic halo so that a window of
+//                              2m points never wraps there; outer axes wrap by index
+//   gpart  per order: items x (sum of that order's term grid sizes)   adjoint partial grids,
+//                              one region per node chunk (spread work item)
+//   fpart  blocks x Vtot       forward partial sums per term block (Vtot = R*M or sum M_b)
+//
+// "Virtual node" v runs over Vtot = R * M (right-hand side r = v / M on node v % M) or over
+// the concatenated ragged datasets; f, y and fpart are indexed by v.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/grouped.h"
+
+namespace gt {
+
+constexpr int kMaxOrder = 3;
+constexpr int kMinM = 2;
+constexpr int kMaxM = 8;
+constexpr int kGatherBS = 256;    // threads per gather workgroup (one node each)
+constexpr int kSpreadBS = 512;    // threads per spread workgroup
+constexpr int kPackBS = 256;
+constexpr int kVecBS = 256;
+
+template <typename T> struct Deg;                   // window polynomial degree per precision
+template <> struct Deg<float> { static constexpr int value = 8; };
+template <> struct Deg<double> { static constexpr int value = 14; };
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+template <typename T> using cx_t = typename Cx<T>::type;
+
+struct DevTerm {
+  int32_t t, c0, c1, c2;
+  int64_t coef_off;    // offset of the group in the coefficient vector
+  int64_t grid_off;    // offset of the term's grid inside one right-hand side's grid block
+  int64_t gpart_off;   // offset inside one spread item's partial-grid block of its order
+};
+
+struct WorkItem {      // a contiguous run of virtual nodes of one right-hand side
+  int64_t v0;          // first virtual node
+  int64_t x0;          // node index of v0 in xT
+  int32_t count;
+  int32_t r;
+};
+
+template <typename T> struct OrderParams {
+  int32_t N, n, P, m, gsize, nfreq;   // nfreq = N - 1
+  int32_t term_begin, term_end;
+  const T *deconv;   // nfreq: (-1)^k / Phi_hat(k) for k = -N/2..-1, 1..N/2-1
+  const T *roots;    // 2n: cos, sin of 2 pi j / n
+  const T *poly;     // 2m x (Deg+1): window polynomial per window point, monomial in z
+};
+
+struct OrderHost {
+  int32_t N = 0, n = 0, P = 0, m = 0, gsize = 0;
+  int32_t term_begin = 0, term_end = 0;
+  double b = 0;                       // Kaiser-Bessel shape parameter
+  std::vector<double> deconv, roots, poly;
+  void *d_deconv = nullptr, *d_roots = nullptr, *d_poly = nullptr;
+  // gather term blocks of this order: [begin, end) term ranges
+  std::vector<int32_t> blocks;        // pairs
+  int32_t *d_blocks = nullptr;
+  int32_t block_base = 0;             // index of its first block among all blocks
+  // spread work items of this order
+  std::vector<WorkItem> sitems;
+  WorkItem *d_sitems = nullptr;
+  std::vector<int32_t> sitem_begin;   // per right-hand side, R+1
+  int32_t *d_sitem_begin = nullptr;
+  int64_t gpart_stride = 0;           // complex elements per spread item
+  void *d_gpart = nullptr;
+};
+
+}  // namespace gt
+
+struct gt_plan {
+  gt_problem prob{};
+  std::vector<int64_t> offs;          // ragged offsets (R+1) or empty
+  bool ragged = false;
+  int dtype = GT_C64;
+  size_t rsize = 4;                   // sizeof real
+  int32_t d = 0, ds = 0, R = 1;
+  int64_t M = 0, Mtot = 0, Vtot = 0;
+  int32_t nterms = 0;
+  int64_t ncoef = 0;
+  std::vector<gt::DevTerm> terms;
+  gt::DevTerm *d_terms = nullptr;
+  gt::OrderHost ord[gt::kMaxOrder + 1];
+  int64_t grid_total = 0;
+  void *d_x = nullptr;
+  void *d_grid = nullptr;
+  std::vector<gt::WorkItem> gitems;   // gather work items (kGatherBS virtual nodes each)
+  gt::WorkItem *d_gitems = nullptr;
+  std::vector<int32_t> gitem_begin;   // per right-hand side, R+1
+  int32_t *d_gitem_begin = nullptr;
+  int32_t nblocks = 0;
+  void *d_fpart = nullptr;
+  double *d_ysum = nullptr;           // per gather item: partial sums (re, im) for the empty set
+  int32_t *d_flag = nullptr;          // node validation flag
+  void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
+  hipStream_t stream = nullptr;
+  size_t lds_limit = 65536;
+};
+
+namespace gt {
+
+// ---- error handling (thread-local message) ----
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define GT_HIP(call)                                              \
+  do {                                                            \
+    hipError_t _e = (call);                                       \
+    if (_e != hipSuccess) return ::gt::hip_fail(_e, #call);       \
+  } while (0)
+
+// ---- profiling of launches ----
+void prof_begin(hipStream_t s, const char *name);
+void prof_end(hipStream_t s);
+
+// ---- plan construction helpers (plan.cpp) ----
+int validate_problem(const gt_problem *p);
+int choose_m(int dtype, double sigma);
+
+// ---- kernel launchers (kernels_f32.hip / kernels_f64.hip) ----
+template <typename T> int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s);
+template <typename T> int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s);
+template <typename T> int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hipStream_t s);
+template <typename T> int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s);
+
+// ---- solver drivers (solvers.hip) ----
+template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega,
+                                   int max_iter, double tol, void *fhat, gt_solve_info *info, hipStream_t s);
+template <typename T> int run_fista(gt_plan *pl, const void *y, const double *lambda, const void *omega,
+                                    int max_iter, double L, double eta, double tol, void *fhat,
+                                    gt_solve_info *info, hipStream_t s);
+template <typename T> int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s);
+
+// stream-ordered scratch allocation
+int dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+}  // namespace gt

@@ -1,0 +1,1133 @@
+// Kernels of the grouped Fourier transform (templated on the real type T).
+// Included once per precision by kernels_f32.hip and kernels_f64.hip.
+//
+// One term u of order t = |u| is a t-dimensional nonequispaced FFT (eq. somafm):
+//   forward:  K1 pack     ghat_l = fhat_l * prod_j (-1)^{l_j} / Phi_hat(l_j), zero rows dropped
+//             K2 DFT      g[l] = sum_k ghat_k e^{+2 pi i <k, l>/n}, pruned to the N-1 non-zero
+//                         input frequencies per axis, written into the halo layout
+//             K3 gather   f_v += sum_{window} g[l] prod_j Phi(n x_j - l_j), summed over all terms
+//   adjoint:  K4 spread   grid[l] += y_v prod_j Phi(n x_j - l_j) in LDS, per node chunk
+//             K2 DFT      e^{-2 pi i <k, l>/n}, only the N-1 non-zero output frequencies per axis
+//             K5 unpack   times the same deconvolution factors, written in group order
+// The empty set contributes fhat_0 to every node (forward) and sum_v y_v (adjoint).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gt_internal.h"
+
+namespace gt {
+
+template <typename T>
+__device__ __forceinline__ cx_t<T> cmake(T a, T b) {
+  cx_t<T> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+
+// ------------------------------------------------------------------ reductions (wave64)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of two doubles; result valid in thread 0.  `sh` holds >= 2*(BS/64) doubles.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0;
+    b = 0;
+    for (int i = 0; i < nw; ++i) {
+      a += sh[2 * i];
+      b += sh[2 * i + 1];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ window
+// Grid index of the first window point and the 2m window values of one coordinate.
+// s = n x + n/2 in [0, n) places grid index 0 at x = -1/2; window point j sits at
+// grid index fl - m + 1 + j, i.e. at halo index fl + j, with tau = (m - 1 + fr) - j.
+template <typename T>
+__device__ __forceinline__ T frac_offset(T x, int n, int &fl) {
+  const T nf = (T)n;
+  int f = (int)floor(fma(nf, x, (T)(n / 2)));
+  f = f < 0 ? 0 : (f > n - 1 ? n - 1 : f);
+  fl = f;
+  return fma(nf, x, (T)(n / 2 - f));   // exact product, one rounding: fractional offset
+}
+
+template <typename T, int MH>
+__device__ __forceinline__ void window_values(T z, const T *__restrict__ poly, T (&psi)[2 * MH]) {
+  constexpr int D = Deg<T>::value;
+#pragma unroll
+  for (int j = 0; j < 2 * MH; ++j) {
+    const T *c = poly + j * (D + 1);
+    T acc = c[D];
+#pragma unroll
+    for (int q = D - 1; q >= 0; --q) acc = fma(acc, z, c[q]);
+    psi[j] = acc;
+  }
+}
+
+// Value and d/dz of window point j's polynomial.
+template <typename T>
+__device__ __forceinline__ void window_point_d(T z, const T *__restrict__ c, T &val, T &der) {
+  constexpr int D = Deg<T>::value;
+  T p = c[D], dp = (T)0;
+#pragma unroll
+  for (int q = D - 1; q >= 0; --q) {
+    dp = fma(dp, z, p);
+    p = fma(p, z, c[q]);
+  }
+  val = p;
+  der = dp;
+}
+
+template <typename T>
+__device__ __forceinline__ T window_point(T z, const T *__restrict__ c) {
+  constexpr int D = Deg<T>::value;
+  T acc = c[D];
+#pragma unroll
+  for (int q = D - 1; q >= 0; --q) acc = fma(acc, z, c[q]);
+  return acc;
+}
+
+__device__ __forceinline__ int wrap_start(int fl, int mh, int n) {
+  int r = (fl - mh + 1) % n;
+  return r < 0 ? r + n : r;
+}
+
+// ------------------------------------------------------------------ node preparation
+template <typename T>
+__global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T *__restrict__ xT,
+                                int32_t *__restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mtot * d) return;
+  const int64_t node = i / d;
+  const int c = (int)(i - node * d);
+  T v = x[i];
+  if (!isfinite(v)) {
+    atomicOr(flag, 1);
+    v = (T)0;
+  }
+  if (!(v >= (T)-0.5 && v < (T)0.5)) {   // reduce modulo 1 only when outside [-1/2, 1/2)
+    v = v - floor(v + (T)0.5);
+    if (v >= (T)0.5 || v < (T)-0.5) v = (T)-0.5;
+  }
+  xT[(int64_t)c * Mtot + node] = v;
+}
+
+static __global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
+// ------------------------------------------------------------------ K1 + K2 forward
+// One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
+// (N-1)^t non-zero frequencies onto the n^t grid, written in the halo layout.
+template <typename T, int ORDER>
+__global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict__ fhat, const T *__restrict__ colscale,
+                                                      int64_t ncoef, const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                      cx_t<T> *__restrict__ grids, int64_t grid_total) {
+  using C = cx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *S = reinterpret_cast<C *>(smem_raw);
+  const int tid = threadIdx.x, BS = blockDim.x;
+  const DevTerm tm = terms[op.term_begin + blockIdx.x];
+  const int r = blockIdx.y;
+  const C *src = fhat + (int64_t)r * ncoef + tm.coef_off;
+  const T *cs = colscale ? colscale + tm.coef_off : nullptr;
+  C *dst = grids + (int64_t)r * grid_total + tm.grid_off;
+  const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = op.m - 1;
+  const T *__restrict__ W = op.roots;
+  const T *__restrict__ Dc = op.deconv;
+  // exponent index (k_a * l) mod n for a = 0..K-1 stepping incrementally
+  auto phase0 = [&](int l) { return (int)(((int64_t)(n - h) * l) % n); };   // k = -h
+  auto step = [&](int e, int a, int l) {                                   // k_a -> k_{a+1}
+    e += (a == h - 1) ? 2 * l : l;
+    while (e >= n) e -= n;
+    return e;
+  };
+  auto unpad = [&](int p) {
+    int l = (p - mm1) % n;
+    return l < 0 ? l + n : l;
+  };
+
+  if (ORDER == 1) {
+    for (int a = tid; a < K; a += BS) {
+      C v = src[a];
+      T sc = Dc[a] * (cs ? cs[a] : (T)1);
+      S[a] = cmake<T>(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    for (int p = tid; p < P; p += BS) {
+      const int l = unpad(p);
+      T re = 0, im = 0;
+      int e = phase0(l);
+      for (int a = 0; a < K; ++a) {
+        const C v = S[a];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a, l);
+      }
+      dst[p] = cmake<T>(re, im);
+    }
+  } else if (ORDER == 2) {
+    C *A = S;              // K x K
+    C *B = S + K * K;      // K x n
+    for (int i = tid; i < K * K; i += BS) {
+      const int a1 = i / K, a2 = i - a1 * K;
+      C v = src[i];
+      T sc = Dc[a1] * Dc[a2] * (cs ? cs[i] : (T)1);
+      A[i] = cmake<T>(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    for (int i = tid; i < K * n; i += BS) {
+      const int a1 = i / n, l2 = i - a1 * n;
+      T re = 0, im = 0;
+      int e = phase0(l2);
+      for (int a2 = 0; a2 < K; ++a2) {
+        const C v = A[a1 * K + a2];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a2, l2);
+      }
+      B[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < n * P; i += BS) {
+      const int l1 = i / P, p2 = i - l1 * P, l2 = unpad(p2);
+      T re = 0, im = 0;
+      int e = phase0(l1);
+      for (int a1 = 0; a1 < K; ++a1) {
+        const C v = B[a1 * n + l2];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a1, l1);
+      }
+      dst[i] = cmake<T>(re, im);
+    }
+  } else {
+    C *A = S;                          // K^3
+    C *B = A + K * K * K;              // K x K x n
+    C *Cc = B + K * K * n;             // K x n x n
+    for (int i = tid; i < K * K * K; i += BS) {
+      const int a1 = i / (K * K), rem = i - a1 * K * K, a2 = rem / K, a3 = rem - a2 * K;
+      C v = src[i];
+      T sc = Dc[a1] * Dc[a2] * Dc[a3] * (cs ? cs[i] : (T)1);
+      A[i] = cmake<T>(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    for (int i = tid; i < K * K * n; i += BS) {
+      const int a12 = i / n, l3 = i - a12 * n;
+      T re = 0, im = 0;
+      int e = phase0(l3);
+      for (int a3 = 0; a3 < K; ++a3) {
+        const C v = A[a12 * K + a3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a3, l3);
+      }
+      B[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < K * n * n; i += BS) {
+      const int a1 = i / (n * n), rem = i - a1 * n * n, l2 = rem / n, l3 = rem - l2 * n;
+      T re = 0, im = 0;
+      int e = phase0(l2);
+      for (int a2 = 0; a2 < K; ++a2) {
+        const C v = B[(a1 * K + a2) * n + l3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a2, l2);
+      }
+      Cc[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < n * n * P; i += BS) {
+      const int l1 = i / (n * P), rem = i - l1 * n * P, l2 = rem / P, p3 = rem - l2 * P, l3 = unpad(p3);
+      T re = 0, im = 0;
+      int e = phase0(l1);
+      for (int a1 = 0; a1 < K; ++a1) {
+        const C v = Cc[(a1 * n + l2) * n + l3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(-v.y, s, re));
+        im = fma(v.x, s, fma(v.y, c, im));
+        e = step(e, a1, l1);
+      }
+      dst[i] = cmake<T>(re, im);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ K3 gather
+// Workgroup = (256 virtual nodes of one right-hand side) x (a block of terms of one order).
+// Each term's grid is staged in LDS; each thread accumulates its node's sum over the block.
+template <typename T, int ORDER, int MH>
+__device__ __forceinline__ cx_t<T> gather_term(const cx_t<T> *__restrict__ G, const T *__restrict__ xT, int64_t Mx,
+                                               int64_t xi, const DevTerm &tm, const OrderParams<T> &op) {
+  constexpr int W = 2 * MH;
+  const int n = op.n, P = op.P;
+  T re = 0, im = 0;
+  if (ORDER == 1) {
+    int f0;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    T p0[W];
+    window_values<T, MH>(z0, op.poly, p0);
+    const cx_t<T> *g = G + f0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const cx_t<T> v = g[j];
+      re = fma(p0[j], v.x, re);
+      im = fma(p0[j], v.y, im);
+    }
+  } else if (ORDER == 2) {
+    int f0, f1;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+    T p0[W], p1[W];
+    window_values<T, MH>(z0, op.poly, p0);
+    window_values<T, MH>(z1, op.poly, p1);
+    int r = wrap_start(f0, MH, n);
+#pragma unroll
+    for (int j1 = 0; j1 < W; ++j1) {
+      const cx_t<T> *row = G + r * P + f1;
+      T br = 0, bi = 0;
+#pragma unroll
+      for (int j2 = 0; j2 < W; ++j2) {
+        const cx_t<T> v = row[j2];
+        br = fma(p1[j2], v.x, br);
+        bi = fma(p1[j2], v.y, bi);
+      }
+      re = fma(p0[j1], br, re);
+      im = fma(p0[j1], bi, im);
+      r = (r + 1 == n) ? 0 : r + 1;
+    }
+  } else {
+    int f0, f1, f2;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+    const T z2 = frac_offset<T>(xT[(int64_t)tm.c2 * Mx + xi], n, f2) * (T)2 - (T)1;
+    T p1[W], p2[W];
+    window_values<T, MH>(z1, op.poly, p1);
+    window_values<T, MH>(z2, op.poly, p2);
+    int r0 = wrap_start(f0, MH, n);
+    const int r1s = wrap_start(f1, MH, n);
+    constexpr int D = Deg<T>::value;
+#pragma unroll 1
+    for (int j1 = 0; j1 < W; ++j1) {
+      const T w0 = window_point<T>(z0, op.poly + j1 * (D + 1));
+      const cx_t<T> *plane = G + (int64_t)r0 * n * P + f2;
+      int r1 = r1s;
+      T br = 0, bi = 0;
+#pragma unroll
+      for (int j2 = 0; j2 < W; ++j2) {
+        const cx_t<T> *row = plane + r1 * P;
+        T cr = 0, ci = 0;
+#pragma unroll
+        for (int j3 = 0; j3 < W; ++j3) {
+          const cx_t<T> v = row[j3];
+          cr = fma(p2[j3], v.x, cr);
+          ci = fma(p2[j3], v.y, ci);
+        }
+        br = fma(p1[j2], cr, br);
+        bi = fma(p1[j2], ci, bi);
+        r1 = (r1 + 1 == n) ? 0 : r1 + 1;
+      }
+      re = fma(w0, br, re);
+      im = fma(w0, bi, im);
+      r0 = (r0 + 1 == n) ? 0 : r0 + 1;
+    }
+  }
+  return cmake<T>(re, im);
+}
+
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(kGatherBS) void k_gather(const T *__restrict__ xT, int64_t Mx,
+                                                      const WorkItem *__restrict__ items, const int32_t *__restrict__ blocks,
+                                                      int32_t block_base, const DevTerm *__restrict__ terms,
+                                                      OrderParams<T> op, const cx_t<T> *__restrict__ grids,
+                                                      int64_t grid_total, cx_t<T> *__restrict__ fpart, int64_t Vtot) {
+  using C = cx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *G = reinterpret_cast<C *>(smem_raw);
+  const WorkItem it = items[blockIdx.x];
+  const int tb = blocks[2 * blockIdx.y], te = blocks[2 * blockIdx.y + 1];
+  const int tid = threadIdx.x;
+  const bool active = tid < it.count;
+  const int64_t xi = it.x0 + tid;
+  const C *gbase = grids + (int64_t)it.r * grid_total;
+  T re = 0, im = 0;
+  for (int term = tb; term < te; ++term) {
+    const DevTerm tm = terms[term];
+    const C *src = gbase + tm.grid_off;
+    __syncthreads();
+    for (int i = tid; i < op.gsize; i += kGatherBS) G[i] = src[i];
+    __syncthreads();
+    if (active) {
+      const C v = gather_term<T, ORDER, MH>(G, xT, Mx, xi, tm, op);
+      re += v.x;
+      im += v.y;
+    }
+  }
+  if (active) fpart[(int64_t)(block_base + blockIdx.y) * Vtot + it.v0 + tid] = cmake<T>(re, im);
+}
+
+// f_v = fhat_empty(r) + sum over term blocks of the partial sums.
+template <typename T>
+__global__ __launch_bounds__(kGatherBS) void k_reduce_f(const cx_t<T> *__restrict__ fhat, int64_t ncoef,
+                                                        const WorkItem *__restrict__ items,
+                                                        const cx_t<T> *__restrict__ fpart, int nblocks, int64_t Vtot,
+                                                        cx_t<T> *__restrict__ f) {
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid >= it.count) return;
+  const int64_t v = it.v0 + tid;
+  cx_t<T> acc = fhat[(int64_t)it.r * ncoef];
+  for (int b = 0; b < nblocks; ++b) {
+    const cx_t<T> p = fpart[(int64_t)b * Vtot + v];
+    acc.x += p.x;
+    acc.y += p.y;
+  }
+  f[v] = acc;
+}
+
+// ------------------------------------------------------------------ K4 spread
+// Workgroup = (a chunk of virtual nodes of one right-hand side) x (one term).  The grid
+// lives in LDS as FP64 for both precisions (FP64 LDS atomics measured ~5x faster than FP32
+// ones on gfx950, and the sum of up to ~1e5 contributions per grid point stays exact to
+// FP32 output precision); nodes add y_v * window with LDS atomics.  The result is this
+// chunk's partial grid (halo layout), summed over chunks by the adjoint DFT.
+template <typename T, int ORDER, int MH>
+__device__ __forceinline__ void spread_node(double2 *__restrict__ G, const T *__restrict__ xT, int64_t Mx, int64_t xi,
+                                            cx_t<T> yv, const DevTerm &tm, const OrderParams<T> &op) {
+  constexpr int W = 2 * MH;
+  const int n = op.n, P = op.P;
+  if (ORDER == 1) {
+    int f0;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    T p0[W];
+    window_values<T, MH>(z0, op.poly, p0);
+    double2 *g = G + f0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      atomicAdd(&g[j].x, (double)(p0[j] * yv.x));
+      atomicAdd(&g[j].y, (double)(p0[j] * yv.y));
+    }
+  } else if (ORDER == 2) {
+    int f0, f1;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+    T p0[W], p1[W];
+    window_values<T, MH>(z0, op.poly, p0);
+    window_values<T, MH>(z1, op.poly, p1);
+    int r = wrap_start(f0, MH, n);
+#pragma unroll
+    for (int j1 = 0; j1 < W; ++j1) {
+      double2 *row = G + r * P + f1;
+      const T wr = p0[j1] * yv.x, wi = p0[j1] * yv.y;
+#pragma unroll
+      for (int j2 = 0; j2 < W; ++j2) {
+        atomicAdd(&row[j2].x, (double)(p1[j2] * wr));
+        atomicAdd(&row[j2].y, (double)(p1[j2] * wi));
+      }
+      r = (r + 1 == n) ? 0 : r + 1;
+    }
+  } else {
+    int f0, f1, f2;
+    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+    const T z2 = frac_offset<T>(xT[(int64_t)tm.c2 * Mx + xi], n, f2) * (T)2 - (T)1;
+    T p1[W], p2[W];
+    window_values<T, MH>(z1, op.poly, p1);
+    window_values<T, MH>(z2, op.poly, p2);
+    int r0 = wrap_start(f0, MH, n);
+    const int r1s = wrap_start(f1, MH, n);
+    constexpr int D = Deg<T>::value;
+#pragma unroll 1
+    for (int j1 = 0; j1 < W; ++j1) {
+      const T w0 = window_point<T>(z0, op.poly + j1 * (D + 1));
+      const T ar = w0 * yv.x, ai = w0 * yv.y;
+      double2 *plane = G + (int64_t)r0 * n * P + f2;
+      int r1 = r1s;
+#pragma unroll
+      for (int j2 = 0; j2 < W; ++j2) {
+        double2 *row = plane + r1 * P;
+        const T br = p1[j2] * ar, bi = p1[j2] * ai;
+#pragma unroll
+        for (int j3 = 0; j3 < W; ++j3) {
+          atomicAdd(&row[j3].x, (double)(p2[j3] * br));
+          atomicAdd(&row[j3].y, (double)(p2[j3] * bi));
+        }
+        r1 = (r1 + 1 == n) ? 0 : r1 + 1;
+      }
+      r0 = (r0 + 1 == n) ? 0 : r0 + 1;
+    }
+  }
+}
+
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(kSpreadBS) void k_spread(const T *__restrict__ xT, int64_t Mx,
+                                                      const WorkItem *__restrict__ items, const DevTerm *__restrict__ terms,
+                                                      OrderParams<T> op, const cx_t<T> *__restrict__ y,
+                                                      cx_t<T> *__restrict__ gpart, int64_t gstride) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *G = reinterpret_cast<double2 *>(smem_raw);
+  const WorkItem it = items[blockIdx.x];
+  const DevTerm tm = terms[op.term_begin + blockIdx.y];
+  const int tid = threadIdx.x;
+  const int gsize = op.gsize;
+  for (int i = tid; i < gsize; i += kSpreadBS) G[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int i = tid; i < it.count; i += kSpreadBS) spread_node<T, ORDER, MH>(G, xT, Mx, it.x0 + i, y[it.v0 + i], tm, op);
+  __syncthreads();
+  cx_t<T> *out = gpart + (int64_t)blockIdx.x * gstride + tm.gpart_off;
+  for (int i = tid; i < gsize; i += kSpreadBS) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
+}
+
+// Partial sums of y over each gather item (for the empty-set coefficient).
+template <typename T>
+__global__ __launch_bounds__(kGatherBS) void k_ysum(const WorkItem *__restrict__ items, const cx_t<T> *__restrict__ y,
+                                                    double *__restrict__ ysum) {
+  __shared__ double sh[2 * (kGatherBS / 64)];
+  const WorkItem it = items[blockIdx.x];
+  double a = 0, b = 0;
+  if ((int)threadIdx.x < it.count) {
+    const cx_t<T> v = y[it.v0 + threadIdx.x];
+    a = v.x;
+    b = v.y;
+  }
+  block_sum2(a, b, sh);
+  if (threadIdx.x == 0) {
+    ysum[2 * blockIdx.x] = a;
+    ysum[2 * blockIdx.x + 1] = b;
+  }
+}
+
+template <typename T>
+__global__ void k_empty_adj(const int32_t *__restrict__ item_begin, const double *__restrict__ ysum, int R,
+                            int64_t ncoef, cx_t<T> *__restrict__ fhat) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double a = 0, b = 0;
+  for (int i = item_begin[r]; i < item_begin[r + 1]; ++i) {
+    a += ysum[2 * i];
+    b += ysum[2 * i + 1];
+  }
+  fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
+}
+
+// ------------------------------------------------------------------ K2 + K5 adjoint
+// One workgroup per (term, right-hand side): fold the halo and sum the chunk partial grids
+// (FP64), pruned forward DFT to the (N-1)^t non-zero frequencies, deconvolve, write.
+template <typename T, int ORDER>
+__global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gpart, int64_t gstride,
+                                                     const int32_t *__restrict__ item_begin,
+                                                     const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                     const T *__restrict__ colscale, int64_t ncoef,
+                                                     cx_t<T> *__restrict__ fhat) {
+  using C = cx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *S = reinterpret_cast<C *>(smem_raw);
+  const int tid = threadIdx.x, BS = blockDim.x;
+  const DevTerm tm = terms[op.term_begin + blockIdx.x];
+  const int r = blockIdx.y;
+  const int s0 = item_begin[r], s1 = item_begin[r + 1];
+  const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = op.m - 1;
+  const T *__restrict__ W = op.roots;
+  const T *__restrict__ Dc = op.deconv;
+  C *dst = fhat + (int64_t)r * ncoef + tm.coef_off;
+  const T *cs = colscale ? colscale + tm.coef_off : nullptr;
+  auto phase0 = [&](int l) { return (int)(((int64_t)(n - h) * l) % n); };
+  auto step = [&](int e, int a, int l) {
+    e += (a == h - 1) ? 2 * l : l;
+    while (e >= n) e -= n;
+    return e;
+  };
+  // G[..][l] = sum over chunks and over halo copies p of l (p = l + m - 1 mod n, + n, ...)
+  const int outer = ORDER == 1 ? 1 : (ORDER == 2 ? n : n * n);
+  C *G = S;
+  for (int i = tid; i < outer * n; i += BS) {
+    const int o = i / n, l = i - o * n;
+    double re = 0, im = 0;
+    for (int s = s0; s < s1; ++s) {
+      const C *src = gpart + (int64_t)s * gstride + tm.gpart_off + (int64_t)o * P;
+      for (int p = (l + mm1) % n; p < P; p += n) {
+        const C v = src[p];
+        re += (double)v.x;
+        im += (double)v.y;
+      }
+    }
+    G[i] = cmake<T>((T)re, (T)im);
+  }
+  __syncthreads();
+  // conj twiddles: e^{-2 pi i k l / n}
+  if (ORDER == 1) {
+    for (int a = tid; a < K; a += BS) {
+      T re = 0, im = 0;
+      // walk l with exponent (k_a * l) mod n
+      const int k = a - h + (a >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      int e = 0;
+      for (int l = 0; l < n; ++l) {
+        const C v = G[l];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      const T sc = Dc[a] * (cs ? cs[a] : (T)1);
+      dst[a] = cmake<T>(re * sc, im * sc);
+    }
+  } else if (ORDER == 2) {
+    C *H = S + n * n;   // n x K
+    for (int i = tid; i < n * K; i += BS) {
+      const int l1 = i / K, a2 = i - l1 * K;
+      const int k = a2 - h + (a2 >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      T re = 0, im = 0;
+      int e = 0;
+      for (int l2 = 0; l2 < n; ++l2) {
+        const C v = G[l1 * n + l2];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      H[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < K * K; i += BS) {
+      const int a1 = i / K, a2 = i - a1 * K;
+      const int k = a1 - h + (a1 >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      T re = 0, im = 0;
+      int e = 0;
+      for (int l1 = 0; l1 < n; ++l1) {
+        const C v = H[l1 * K + a2];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      const T sc = Dc[a1] * Dc[a2] * (cs ? cs[i] : (T)1);
+      dst[i] = cmake<T>(re * sc, im * sc);
+    }
+  } else {
+    C *H1 = S + n * n * n;   // n x n x K
+    C *H2 = S;               // n x K x K (overwrites G after H1 is complete)
+    for (int i = tid; i < n * n * K; i += BS) {
+      const int l12 = i / K, a3 = i - l12 * K;
+      const int k = a3 - h + (a3 >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      T re = 0, im = 0;
+      int e = 0;
+      for (int l3 = 0; l3 < n; ++l3) {
+        const C v = G[l12 * n + l3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      H1[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < n * K * K; i += BS) {
+      const int l1 = i / (K * K), rem = i - l1 * K * K, a2 = rem / K, a3 = rem - a2 * K;
+      const int k = a2 - h + (a2 >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      T re = 0, im = 0;
+      int e = 0;
+      for (int l2 = 0; l2 < n; ++l2) {
+        const C v = H1[(l1 * n + l2) * K + a3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      H2[i] = cmake<T>(re, im);
+    }
+    __syncthreads();
+    for (int i = tid; i < K * K * K; i += BS) {
+      const int a1 = i / (K * K), rem = i - a1 * K * K, a2 = rem / K, a3 = rem - a2 * K;
+      const int k = a1 - h + (a1 >= h ? 1 : 0);
+      const int km = k < 0 ? k + n : k;
+      T re = 0, im = 0;
+      int e = 0;
+      for (int l1 = 0; l1 < n; ++l1) {
+        const C v = H2[(l1 * K + a2) * K + a3];
+        const T c = W[2 * e], s = W[2 * e + 1];
+        re = fma(v.x, c, fma(v.y, s, re));
+        im = fma(v.y, c, fma(-v.x, s, im));
+        e += km;
+        if (e >= n) e -= n;
+      }
+      const T sc = Dc[a1] * Dc[a2] * Dc[a3] * (cs ? cs[i] : (T)1);
+      dst[i] = cmake<T>(re * sc, im * sc);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ K9 node gradient
+// Workgroup = 256 virtual nodes x all terms of one order.  Derivative of the gathered sum
+// with respect to each coordinate of the term (window derivative d/dx = 2 n d/dz); the
+// contribution Re(conj(D) g_v) is accumulated per node and coordinate in LDS.
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(kGatherBS) void k_node_grad(const T *__restrict__ xT, int64_t Mx, int d,
+                                                         const WorkItem *__restrict__ items,
+                                                         const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                         const cx_t<T> *__restrict__ grids, int64_t grid_total,
+                                                         const cx_t<T> *__restrict__ gup, T *__restrict__ gxp) {
+  using C = cx_t<T>;
+  constexpr int W = 2 * MH;
+  constexpr int D = Deg<T>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *G = reinterpret_cast<C *>(smem_raw);
+  T *acc = reinterpret_cast<T *>(smem_raw + (size_t)op.gsize * sizeof(C));   // d x 256
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const bool active = tid < it.count;
+  const int64_t xi = it.x0 + tid;
+  for (int c = 0; c < d; ++c) acc[c * kGatherBS + tid] = (T)0;
+  C gv = cmake<T>(0, 0);
+  if (active) gv = gup[it.v0 + tid];
+  const C *gbase = grids + (int64_t)it.r * grid_total;
+  const int n = op.n, P = op.P;
+  const T dscale = (T)(2 * n);
+  for (int term = op.term_begin; term < op.term_end; ++term) {
+    const DevTerm tm = terms[term];
+    const C *src = gbase + tm.grid_off;
+    __syncthreads();
+    for (int i = tid; i < op.gsize; i += kGatherBS) G[i] = src[i];
+    __syncthreads();
+    if (!active) continue;
+    if (ORDER == 1) {
+      int f0;
+      const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+      T dr = 0, di = 0;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        T w, dw;
+        window_point_d<T>(z0, op.poly + j * (D + 1), w, dw);
+        const C v = G[f0 + j];
+        dr = fma(dw, v.x, dr);
+        di = fma(dw, v.y, di);
+      }
+      acc[tm.c0 * kGatherBS + tid] += dscale * (dr * gv.x + di * gv.y);
+    } else if (ORDER == 2) {
+      int f0, f1;
+      const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+      const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+      T p0[W], d0[W], p1[W], d1[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        window_point_d<T>(z0, op.poly + j * (D + 1), p0[j], d0[j]);
+        window_point_d<T>(z1, op.poly + j * (D + 1), p1[j], d1[j]);
+      }
+      int r = wrap_start(f0, MH, n);
+      T a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < W; ++j1) {
+        const C *row = G + r * P + f1;
+        T br = 0, bi = 0, cr = 0, ci = 0;
+#pragma unroll
+        for (int j2 = 0; j2 < W; ++j2) {
+          const C v = row[j2];
+          br = fma(p1[j2], v.x, br);
+          bi = fma(p1[j2], v.y, bi);
+          cr = fma(d1[j2], v.x, cr);
+          ci = fma(d1[j2], v.y, ci);
+        }
+        a0r = fma(d0[j1], br, a0r);
+        a0i = fma(d0[j1], bi, a0i);
+        a1r = fma(p0[j1], cr, a1r);
+        a1i = fma(p0[j1], ci, a1i);
+        r = (r + 1 == n) ? 0 : r + 1;
+      }
+      acc[tm.c0 * kGatherBS + tid] += dscale * (a0r * gv.x + a0i * gv.y);
+      acc[tm.c1 * kGatherBS + tid] += dscale * (a1r * gv.x + a1i * gv.y);
+    } else {
+      int f0, f1, f2;
+      const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
+      const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
+      const T z2 = frac_offset<T>(xT[(int64_t)tm.c2 * Mx + xi], n, f2) * (T)2 - (T)1;
+      T p1[W], d1[W], p2[W], d2[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        window_point_d<T>(z1, op.poly + j * (D + 1), p1[j], d1[j]);
+        window_point_d<T>(z2, op.poly + j * (D + 1), p2[j], d2[j]);
+      }
+      int r0 = wrap_start(f0, MH, n);
+      const int r1s = wrap_start(f1, MH, n);
+      T a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+#pragma unroll 1
+      for (int j1 = 0; j1 < W; ++j1) {
+        T w0, dw0;
+        window_point_d<T>(z0, op.poly + j1 * (D + 1), w0, dw0);
+        const C *plane = G + (int64_t)r0 * n * P + f2;
+        int r1 = r1s;
+        T br = 0, bi = 0, b1r = 0, b1i = 0, b2r = 0, b2i = 0;
+#pragma unroll
+        for (int j2 = 0; j2 < W; ++j2) {
+          const C *row = plane + r1 * P;
+          T cr = 0, ci = 0, er = 0, ei = 0;
+#pragma unroll
+          for (int j3 = 0; j3 < W; ++j3) {
+            const C v = row[j3];
+            cr = fma(p2[j3], v.x, cr);
+            ci = fma(p2[j3], v.y, ci);
+            er = fma(d2[j3], v.x, er);
+            ei = fma(d2[j3], v.y, ei);
+          }
+          br = fma(p1[j2], cr, br);
+          bi = fma(p1[j2], ci, bi);
+          b1r = fma(d1[j2], cr, b1r);
+          b1i = fma(d1[j2], ci, b1i);
+          b2r = fma(p1[j2], er, b2r);
+          b2i = fma(p1[j2], ei, b2i);
+          r1 = (r1 + 1 == n) ? 0 : r1 + 1;
+        }
+        a0r = fma(dw0, br, a0r);
+        a0i = fma(dw0, bi, a0i);
+        a1r = fma(w0, b1r, a1r);
+        a1i = fma(w0, b1i, a1i);
+        a2r = fma(w0, b2r, a2r);
+        a2i = fma(w0, b2i, a2i);
+        r0 = (r0 + 1 == n) ? 0 : r0 + 1;
+      }
+      acc[tm.c0 * kGatherBS + tid] += dscale * (a0r * gv.x + a0i * gv.y);
+      acc[tm.c1 * kGatherBS + tid] += dscale * (a1r * gv.x + a1i * gv.y);
+      acc[tm.c2 * kGatherBS + tid] += dscale * (a2r * gv.x + a2i * gv.y);
+    }
+  }
+  __syncthreads();
+  if (active)
+    for (int c = 0; c < d; ++c) gxp[(it.v0 + tid) * d + c] = acc[c * kGatherBS + tid];
+}
+
+// gx[i][c] = sum over orders and over right-hand sides sharing node i of the partials.
+template <typename T>
+__global__ void k_reduce_gx(const T *__restrict__ gxp, int norders, int64_t Vtot, int64_t Mtot, int R, bool ragged,
+                            int d, T *__restrict__ gx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mtot * d) return;
+  const int64_t node = i / d;
+  const int c = (int)(i - node * d);
+  T s = 0;
+  for (int o = 0; o < norders; ++o) {
+    const T *base = gxp + (int64_t)o * Vtot * d;
+    if (ragged) {
+      s += base[node * d + c];
+    } else {
+      for (int r = 0; r < R; ++r) s += base[((int64_t)r * Mtot + node) * d + c];
+    }
+  }
+  gx[i] = s;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+static OrderParams<T> order_params(const gt_plan *pl, int t) {
+  const OrderHost &o = pl->ord[t];
+  OrderParams<T> op;
+  op.N = o.N;
+  op.n = o.n;
+  op.P = o.P;
+  op.m = o.m;
+  op.gsize = o.gsize;
+  op.nfreq = o.N - 1;
+  op.term_begin = o.term_begin;
+  op.term_end = o.term_end;
+  op.deconv = (const T *)o.d_deconv;
+  op.roots = (const T *)o.d_roots;
+  op.poly = (const T *)o.d_poly;
+  return op;
+}
+
+template <typename K>
+static int set_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
+  }
+  return GT_OK;
+}
+
+static int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return GT_OK;
+}
+
+#define GT_DISPATCH_M(m, MACRO) \
+  switch (m) {                  \
+    case 2: MACRO(2); break;    \
+    case 3: MACRO(3); break;    \
+    case 4: MACRO(4); break;    \
+    case 5: MACRO(5); break;    \
+    case 6: MACRO(6); break;    \
+    case 7: MACRO(7); break;    \
+    case 8: MACRO(8); break;    \
+    default: return fail(GT_EUNSUPPORTED, "window half-width outside 2..8"); \
+  }
+
+template <typename T>
+static size_t pack_lds(const gt_plan *pl, int t) {
+  const OrderHost &o = pl->ord[t];
+  const size_t K = o.N - 1, n = o.n;
+  const size_t c = sizeof(cx_t<T>);
+  return c * (t == 1 ? K : t == 2 ? K * K + K * n : K * K * K + K * K * n + K * n * n);
+}
+
+template <typename T>
+static size_t adj_lds(const gt_plan *pl, int t) {
+  const OrderHost &o = pl->ord[t];
+  const size_t K = o.N - 1, n = o.n;
+  const size_t c = sizeof(cx_t<T>);
+  return c * (t == 1 ? n : t == 2 ? n * n + n * K : n * n * n + n * n * K);
+}
+
+template <typename T>
+static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStream_t s) {
+  using C = cx_t<T>;
+  for (int t = 1; t <= pl->ds; ++t) {
+    const OrderHost &o = pl->ord[t];
+    const int nt = o.term_end - o.term_begin;
+    if (nt == 0) continue;
+    OrderParams<T> op = order_params<T>(pl, t);
+    const size_t lds = pack_lds<T>(pl, t);
+    dim3 grid(nt, pl->R);
+    prof_begin(s, t == 1 ? "pack_fwd_1d" : t == 2 ? "pack_fwd_2d" : "pack_fwd_3d");
+    if (t == 1) {
+      if (int rc = set_lds(k_pack_fwd<T, 1>, lds)) return rc;
+      hipLaunchKernelGGL((k_pack_fwd<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+    } else if (t == 2) {
+      if (int rc = set_lds(k_pack_fwd<T, 2>, lds)) return rc;
+      hipLaunchKernelGGL((k_pack_fwd<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+    } else {
+      if (int rc = set_lds(k_pack_fwd<T, 3>, lds)) return rc;
+      hipLaunchKernelGGL((k_pack_fwd<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+    }
+    prof_end(s);
+    if (int rc = check_launch("k_pack_fwd")) return rc;
+  }
+  return GT_OK;
+}
+
+template <typename T>
+int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
+  using C = cx_t<T>;
+  if (int rc = launch_pack<T>(pl, fhat, colscale, s)) return rc;
+  const int ngi = (int)pl->gitems.size();
+  for (int t = 1; t <= pl->ds; ++t) {
+    const OrderHost &o = pl->ord[t];
+    const int nb = (int)o.blocks.size() / 2;
+    if (nb == 0 || ngi == 0) continue;
+    OrderParams<T> op = order_params<T>(pl, t);
+    const size_t lds = (size_t)o.gsize * sizeof(C);
+    dim3 grid(ngi, nb);
+    prof_begin(s, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
+#define GT_LAUNCH_GATHER(MH)                                                                                        \
+  {                                                                                                                 \
+    if (t == 1) {                                                                                                   \
+      if (int rc = set_lds(k_gather<T, 1, MH>, lds)) return rc;                                                     \
+      hipLaunchKernelGGL((k_gather<T, 1, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
+                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
+                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
+    } else if (t == 2) {                                                                                            \
+      if (int rc = set_lds(k_gather<T, 2, MH>, lds)) return rc;                                                     \
+      hipLaunchKernelGGL((k_gather<T, 2, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
+                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
+                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
+    } else {                                                                                                        \
+      if (int rc = set_lds(k_gather<T, 3, MH>, lds)) return rc;                                                     \
+      hipLaunchKernelGGL((k_gather<T, 3, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
+                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
+                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
+    }                                                                                                               \
+  }
+    GT_DISPATCH_M(o.m, GT_LAUNCH_GATHER)
+#undef GT_LAUNCH_GATHER
+    prof_end(s);
+    if (int rc = check_launch("k_gather")) return rc;
+  }
+  if (ngi > 0) {
+    prof_begin(s, "reduce_f");
+    hipLaunchKernelGGL((k_reduce_f<T>), dim3(ngi), dim3(kGatherBS), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
+                       (const C *)pl->d_fpart, pl->nblocks, pl->Vtot, (C *)f);
+    prof_end(s);
+    if (int rc = check_launch("k_reduce_f")) return rc;
+  }
+  return GT_OK;
+}
+
+template <typename T>
+int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
+  using C = cx_t<T>;
+  const int ngi = (int)pl->gitems.size();
+  for (int t = 1; t <= pl->ds; ++t) {
+    const OrderHost &o = pl->ord[t];
+    const int nt = o.term_end - o.term_begin;
+    const int nsi = (int)o.sitems.size();
+    if (nt == 0 || nsi == 0) continue;
+    OrderParams<T> op = order_params<T>(pl, t);
+    const size_t lds = (size_t)o.gsize * sizeof(double2);
+    dim3 grid(nsi, nt);
+    prof_begin(s, t == 1 ? "spread_1d" : t == 2 ? "spread_2d" : "spread_3d");
+#define GT_LAUNCH_SPREAD(MH)                                                                                         \
+  {                                                                                                                  \
+    if (t == 1) {                                                                                                    \
+      if (int rc = set_lds(k_spread<T, 1, MH>, lds)) return rc;                                                      \
+      hipLaunchKernelGGL((k_spread<T, 1, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
+                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
+    } else if (t == 2) {                                                                                             \
+      if (int rc = set_lds(k_spread<T, 2, MH>, lds)) return rc;                                                      \
+      hipLaunchKernelGGL((k_spread<T, 2, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
+                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
+    } else {                                                                                                         \
+      if (int rc = set_lds(k_spread<T, 3, MH>, lds)) return rc;                                                      \
+      hipLaunchKernelGGL((k_spread<T, 3, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
+                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
+    }                                                                                                                \
+  }
+    GT_DISPATCH_M(o.m, GT_LAUNCH_SPREAD)
+#undef GT_LAUNCH_SPREAD
+    prof_end(s);
+    if (int rc = check_launch("k_spread")) return rc;
+  }
+  for (int t = 1; t <= pl->ds; ++t) {
+    const OrderHost &o = pl->ord[t];
+    const int nt = o.term_end - o.term_begin;
+    if (nt == 0) continue;
+    OrderParams<T> op = order_params<T>(pl, t);
+    const size_t lds = adj_lds<T>(pl, t);
+    dim3 grid(nt, pl->R);
+    prof_begin(s, t == 1 ? "dft_adj_1d" : t == 2 ? "dft_adj_2d" : "dft_adj_3d");
+    if (t == 1) {
+      if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
+      hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
+                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+    } else if (t == 2) {
+      if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
+                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+    } else {
+      if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
+      hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
+                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+    }
+    prof_end(s);
+    if (int rc = check_launch("k_dft_adj")) return rc;
+  }
+  if (ngi > 0) {
+    prof_begin(s, "empty_adj");
+    hipLaunchKernelGGL((k_ysum<T>), dim3(ngi), dim3(kGatherBS), 0, s, pl->d_gitems, (const C *)y, pl->d_ysum);
+    hipLaunchKernelGGL((k_empty_adj<T>), dim3((pl->R + 63) / 64), dim3(64), 0, s, pl->d_gitem_begin, pl->d_ysum,
+                       pl->R, pl->ncoef, (C *)fhat);
+    prof_end(s);
+    if (int rc = check_launch("k_empty_adj")) return rc;
+  }
+  return GT_OK;
+}
+
+template <typename T>
+int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hipStream_t s) {
+  using C = cx_t<T>;
+  if (pl->ds == 0) {
+    // no term depends on the nodes
+    const int64_t total = pl->Mtot * pl->d;
+    hipLaunchKernelGGL((k_reduce_gx<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)nullptr, 0,
+                       pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T *)gx);
+    return check_launch("k_reduce_gx");
+  }
+  if (int rc = launch_pack<T>(pl, fhat, nullptr, s)) return rc;
+  if (!pl->d_gxp) {
+    const size_t bytes = (size_t)pl->ds * pl->Vtot * pl->d * sizeof(T);
+    if (int rc = dev_alloc(&pl->d_gxp, bytes, s)) return rc;
+  }
+  void *gxp = pl->d_gxp;
+  const int ngi = (int)pl->gitems.size();
+  int rc = GT_OK;
+  for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+    const OrderHost &o = pl->ord[t];
+    OrderParams<T> op = order_params<T>(pl, t);
+    const size_t lds = (size_t)o.gsize * sizeof(C) + (size_t)pl->d * kGatherBS * sizeof(T);
+    if (lds > pl->lds_limit) {
+      rc = fail(GT_EUNSUPPORTED, "node gradient needs more LDS than available (d too large for this grid)");
+      break;
+    }
+    T *out = (T *)gxp + (size_t)(t - 1) * pl->Vtot * pl->d;
+    prof_begin(s, t == 1 ? "node_grad_1d" : t == 2 ? "node_grad_2d" : "node_grad_3d");
+#define GT_LAUNCH_NG(MH)                                                                                              \
+  {                                                                                                                   \
+    if (t == 1) {                                                                                                     \
+      if ((rc = set_lds(k_node_grad<T, 1, MH>, lds))) break;                                                         \
+      hipLaunchKernelGGL((k_node_grad<T, 1, MH>), dim3(ngi), dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,    \
+                         pl->d, pl->d_gitems, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, (const C *)g, out); \
+    } else if (t == 2) {                                                                                              \
+      if ((rc = set_lds(k_node_grad<T, 2, MH>, lds))) break;                                                         \
+      hipLaunchKernelGGL((k_node_grad<T, 2, MH>), dim3(ngi), dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,    \
+                         pl->d, pl->d_gitems, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, (const C *)g, out); \
+    } else {                                                                                                          \
+      if ((rc = set_lds(k_node_grad<T, 3, MH>, lds))) break;                                                         \
+      hipLaunchKernelGGL((k_node_grad<T, 3, MH>), dim3(ngi), dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,    \
+                         pl->d, pl->d_gitems, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, (const C *)g, out); \
+    }                                                                                                                 \
+  }
+    switch (o.m) {
+      case 2: GT_LAUNCH_NG(2); break;
+      case 3: GT_LAUNCH_NG(3); break;
+      case 4: GT_LAUNCH_NG(4); break;
+      case 5: GT_LAUNCH_NG(5); break;
+      case 6: GT_LAUNCH_NG(6); break;
+      case 7: GT_LAUNCH_NG(7); break;
+      case 8: GT_LAUNCH_NG(8); break;
+      default: rc = fail(GT_EUNSUPPORTED, "window half-width outside 2..8");
+    }
+#undef GT_LAUNCH_NG
+    prof_end(s);
+    if (rc == GT_OK) rc = check_launch("k_node_grad");
+  }
+  if (rc == GT_OK) {
+    const int64_t total = pl->Mtot * pl->d;
+    hipLaunchKernelGGL((k_reduce_gx<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)gxp,
+                       pl->ds, pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T *)gx);
+    rc = check_launch("k_reduce_gx");
+  }
+  return rc;
+}
+
+template <typename T>
+int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s) {
+  const int64_t total = pl->Mtot * pl->d;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pl->d_flag);
+  if (total > 0)
+    hipLaunchKernelGGL((k_prepare_nodes<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)x,
+                       pl->Mtot, pl->d, (T *)pl->d_x, pl->d_flag);
+  return check_launch("k_prepare_nodes");
+}
+
+}  // namespace gt

@@ -1,0 +1,685 @@
+// Host runtime: index set, Kaiser-Bessel window tables, plans, C ABI entry points.
+//
+// Index set (Sec. 2): U_{d_s} (eq. pizmosch), groups I_N^{u,d} with (N-1)^{|u|} members
+// (eq. metallica, Remark rem:cardinality), grouped set = disjoint union (eq. groupedset).
+//
+// Fast transform of one term (eq. somafm): the paper delegates the |u|-dimensional
+// nonequispaced FFT to the NFFT literature it cites.  This library uses the textbook
+// three-step form with a Kaiser-Bessel window Phi of half-width m on an oversampled grid of
+// n = sigma N points per axis (window in grid units tau = n x - l):
+//   Phi(tau) = m sinh(b sqrt(m^2 - tau^2)) / (sqrt(m^2 - tau^2) sinh(b m)),  |tau| < m,
+//   b = pi (2 - 1/sigma),
+//   Phi_hat(k) = int_{-m}^{m} Phi(tau) e^{-2 pi i k tau / n} dtau   (Gauss-Legendre, long double),
+// forward: scale coefficients by (-1)^k / Phi_hat(k) per axis, inverse DFT onto the grid,
+// gather with the window; adjoint: spread with the window, forward DFT, same scaling.
+// The (-1)^k places grid index 0 at x = -1/2.  The window is evaluated on the GPU from
+// per-window-point polynomials in the fractional node offset (Chebyshev interpolation of
+// Phi converted to monomials), so the device never calls sinh or sqrt.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gt_internal.h"
+
+namespace gt {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+  set_error(msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? GT_ENOMEM : GT_EHIP;
+}
+
+// ------------------------------------------------------------------ profiling
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static thread_local int g_prof_open = -1;
+
+void prof_begin(hipStream_t s, const char *name) {
+  if (!g_prof_on) return;
+  ProfRec r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  g_prof_open = (int)g_prof.size() - 1;
+}
+
+void prof_end(hipStream_t s) {
+  if (!g_prof_on || g_prof_open < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  (void)hipEventRecord(g_prof[g_prof_open].b, s);
+  g_prof_open = -1;
+}
+
+// ------------------------------------------------------------------ scratch
+int dev_alloc(void **p, size_t bytes, hipStream_t) {
+  *p = nullptr;
+  if (bytes == 0) return GT_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  return GT_OK;
+}
+
+void dev_free(void *p, hipStream_t) {
+  if (p) (void)hipFree(p);
+}
+
+// ------------------------------------------------------------------ index set
+static int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+int validate_problem(const gt_problem *p) {
+  if (!p) return fail(GT_EINVAL, "problem is NULL");
+  if (p->d < 1) return fail(GT_EINVAL, "d must be >= 1");
+  if (p->ds < 0 || p->ds > p->d) return fail(GT_EINVAL, "need 0 <= ds <= d");
+  if (p->ds > kMaxOrder) return fail(GT_EUNSUPPORTED, "terms of order > 3 are not implemented on the GPU path");
+  for (int t = 1; t <= p->ds; ++t) {
+    int N = p->N[t - 1];
+    if (N < 2 || (N % 2)) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
+    if (N > 4096) return fail(GT_EUNSUPPORTED, "bandwidth above 4096");
+  }
+  if (p->R < 1) return fail(GT_EINVAL, "R must be >= 1");
+  if (p->dtype != GT_C64 && p->dtype != GT_C128) return fail(GT_EINVAL, "dtype must be GT_C64 or GT_C128");
+  if (p->m != 0 && (p->m < kMinM || p->m > kMaxM)) return fail(GT_EUNSUPPORTED, "window half-width m must be 2..8 (or 0)");
+  if (p->sigma != 0.0 && !(p->sigma >= 1.5 && p->sigma <= 8.0)) return fail(GT_EINVAL, "sigma must be in [1.5, 8] (or 0)");
+  if (p->offsets) {
+    if (p->offsets[0] != 0) return fail(GT_EINVAL, "offsets[0] must be 0");
+    for (int b = 0; b < p->R; ++b)
+      if (p->offsets[b + 1] < p->offsets[b]) return fail(GT_EINVAL, "offsets must be non-decreasing");
+    if (p->offsets[p->R] <= 0) return fail(GT_EINVAL, "ragged node total must be > 0");
+  } else if (p->M <= 0) {
+    return fail(GT_EINVAL, "M must be > 0");
+  }
+  return GT_OK;
+}
+
+// Smallest m with the Kaiser-Bessel error model 2.3 exp(-2 pi m sqrt(1 - 1/sigma)) below
+// the precision's target (1e-6 for FP32 bulk arithmetic, 1e-14 for FP64, which leaves a
+// wide margin below the 1e-12 relative error the FP64 path is held to).
+int choose_m(int dtype, double sigma) {
+  const double target = dtype == GT_C64 ? 1e-6 : 1e-14;
+  const double rate = 2.0 * M_PI * std::sqrt(1.0 - 1.0 / sigma);
+  int m = (int)std::ceil(std::log(2.3 / target) / rate);
+  return std::min(kMaxM, std::max(kMinM, m));
+}
+
+// ------------------------------------------------------------------ window maths (long double)
+static long double kb_phi(long double tau, int m, long double b) {
+  long double s2 = (long double)m * m - tau * tau;
+  if (s2 < 0) return 0.0L;
+  long double s = std::sqrt(s2);
+  long double bs = b * s;
+  long double ratio = bs < 1e-4L ? b * (1.0L + bs * bs / 6.0L) : std::sinh(bs) / s;
+  return ratio * (long double)m / std::sinh(b * (long double)m);
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_q.
+static void gauss_legendre(int q, std::vector<long double> &x, std::vector<long double> &w) {
+  x.assign(q, 0);
+  w.assign(q, 0);
+  for (int i = 0; i < q; ++i) {
+    long double z = std::cos(M_PIl * (i + 0.75L) / (q + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    x[i] = z;
+    w[i] = 2.0L / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Phi_hat(k) = 2 int_0^m Phi(tau) cos(2 pi k tau / n) dtau (Phi is even and analytic on [0, m]).
+static long double kb_phihat(int k, int m, long double b, int n) {
+  static std::vector<long double> gx, gw;
+  static std::once_flag once;
+  std::call_once(once, [] { gauss_legendre(96, gx, gw); });
+  long double acc = 0;
+  for (size_t i = 0; i < gx.size(); ++i) {
+    long double tau = 0.5L * m * (gx[i] + 1.0L);
+    acc += gw[i] * kb_phi(tau, m, b) * std::cos(2.0L * M_PIl * k * tau / n);
+  }
+  return acc * (long double)m;   // 2 * (m/2) * sum
+}
+
+// Monomial coefficients (in z in [-1, 1]) of the degree-D Chebyshev interpolant of
+// z -> Phi(m - 1 + (z + 1)/2 - j) for window point j (tau for fractional offset (z+1)/2).
+static void window_poly(int m, long double b, int D, std::vector<double> &out) {
+  const int W = 2 * m;
+  out.assign((size_t)W * (D + 1), 0.0);
+  std::vector<long double> zi(D + 1), fi(D + 1), c(D + 1), mono(D + 1), Tkm1(D + 1), Tk(D + 1), Tkp1(D + 1);
+  for (int i = 0; i <= D; ++i) zi[i] = std::cos(M_PIl * (i + 0.5L) / (D + 1));
+  for (int j = 0; j < W; ++j) {
+    for (int i = 0; i <= D; ++i) fi[i] = kb_phi((long double)(m - 1) + 0.5L * (zi[i] + 1.0L) - j, m, b);
+    for (int k = 0; k <= D; ++k) {
+      long double s = 0;
+      for (int i = 0; i <= D; ++i) s += fi[i] * std::cos(M_PIl * k * (i + 0.5L) / (D + 1));
+      c[k] = s * 2.0L / (D + 1);
+    }
+    c[0] *= 0.5L;
+    // sum_k c_k T_k(z) in monomials: T_0 = 1, T_1 = z, T_{k+1} = 2 z T_k - T_{k-1}
+    std::fill(mono.begin(), mono.end(), 0.0L);
+    std::fill(Tkm1.begin(), Tkm1.end(), 0.0L);
+    std::fill(Tk.begin(), Tk.end(), 0.0L);
+    Tkm1[0] = 1;
+    mono[0] += c[0];
+    if (D >= 1) {
+      Tk[1] = 1;
+      mono[1] += c[1];
+    }
+    for (int k = 1; k < D; ++k) {
+      std::fill(Tkp1.begin(), Tkp1.end(), 0.0L);
+      for (int q = 0; q <= D; ++q) {
+        if (q + 1 <= D) Tkp1[q + 1] += 2 * Tk[q];
+        Tkp1[q] -= Tkm1[q];
+      }
+      for (int q = 0; q <= D; ++q) mono[q] += c[k + 1] * Tkp1[q];
+      Tkm1 = Tk;
+      Tk = Tkp1;
+    }
+    for (int q = 0; q <= D; ++q) out[(size_t)j * (D + 1) + q] = (double)mono[q];
+  }
+}
+
+}  // namespace gt
+
+using namespace gt;
+
+// ------------------------------------------------------------------ plan build
+namespace {
+
+template <typename T>
+int upload(const std::vector<double> &h, void **d) {
+  std::vector<T> tmp(h.begin(), h.end());
+  int rc = dev_alloc(d, tmp.size() * sizeof(T), nullptr);
+  if (rc) return rc;
+  GT_HIP(hipMemcpy(*d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GT_OK;
+}
+
+template <typename V>
+int upload_raw(const std::vector<V> &h, V **d) {
+  int rc = dev_alloc((void **)d, h.size() * sizeof(V), nullptr);
+  if (rc) return rc;
+  if (!h.empty()) GT_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  return GT_OK;
+}
+
+void free_plan(gt_plan *pl) {
+  if (!pl) return;
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  dev_free(pl->d_terms, nullptr);
+  dev_free(pl->d_x, nullptr);
+  dev_free(pl->d_grid, nullptr);
+  dev_free(pl->d_gitems, nullptr);
+  dev_free(pl->d_gitem_begin, nullptr);
+  dev_free(pl->d_fpart, nullptr);
+  dev_free(pl->d_ysum, nullptr);
+  dev_free(pl->d_flag, nullptr);
+  dev_free(pl->d_gxp, nullptr);
+  for (auto &o : pl->ord) {
+    dev_free(o.d_deconv, nullptr);
+    dev_free(o.d_roots, nullptr);
+    dev_free(o.d_poly, nullptr);
+    dev_free(o.d_blocks, nullptr);
+    dev_free(o.d_sitems, nullptr);
+    dev_free(o.d_sitem_begin, nullptr);
+    dev_free(o.d_gpart, nullptr);
+  }
+  delete pl;
+}
+
+int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out) {
+  *out = nullptr;
+  int rc = validate_problem(p);
+  if (rc) return rc;
+  if (!x) return fail(GT_EINVAL, "node array is NULL");
+  gt_plan *pl = new (std::nothrow) gt_plan();
+  if (!pl) return fail(GT_ENOMEM, "host allocation");
+  pl->prob = *p;
+  pl->prob.offsets = nullptr;
+  pl->dtype = p->dtype;
+  pl->rsize = p->dtype == GT_C64 ? sizeof(float) : sizeof(double);
+  pl->d = p->d;
+  pl->ds = p->ds;
+  pl->R = p->R;
+  pl->stream = s;
+  if (p->offsets) {
+    pl->ragged = true;
+    pl->offs.assign(p->offsets, p->offsets + p->R + 1);
+    pl->Mtot = pl->offs.back();
+    pl->Vtot = pl->Mtot;
+    pl->M = 0;
+  } else {
+    pl->M = p->M;
+    pl->Mtot = p->M;
+    pl->Vtot = p->M * p->R;
+  }
+  const double sigma = p->sigma == 0.0 ? 2.0 : p->sigma;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int lds = 65536;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    pl->lds_limit = (size_t)lds;
+
+  // ---- terms in coefficient order
+  int64_t coef = 0, grid = 0;
+  for (int t = 0; t <= p->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    o.term_begin = (int32_t)pl->terms.size();
+    if (t > 0) {
+      o.N = p->N[t - 1];
+      o.n = 2 * (int)std::ceil(sigma * o.N / 2.0);
+      if (o.n < o.N + 2) o.n = o.N + 2;
+      o.m = p->m ? p->m : choose_m(p->dtype, (double)o.n / o.N);
+      o.P = o.n + 2 * o.m - 1;
+      o.gsize = t == 1 ? o.P : (t == 2 ? o.n * o.P : o.n * o.n * o.P);
+      o.b = M_PI * (2.0 - (double)o.N / o.n);
+    }
+    std::vector<int> c(t);
+    for (int i = 0; i < t; ++i) c[i] = i;
+    int64_t gsz = 1;
+    for (int k = 0; k < t; ++k) gsz *= (o.N - 1);
+    while (true) {
+      if (t == 0 || c[t - 1] < p->d) {
+        DevTerm dt{};
+        dt.t = t;
+        dt.c0 = t > 0 ? c[0] : -1;
+        dt.c1 = t > 1 ? c[1] : -1;
+        dt.c2 = t > 2 ? c[2] : -1;
+        dt.coef_off = coef;
+        dt.grid_off = t > 0 ? grid : 0;
+        coef += t > 0 ? gsz : 1;
+        if (t > 0) grid += o.gsize;
+        pl->terms.push_back(dt);
+      }
+      if (t == 0) break;
+      // next combination
+      int i = t - 1;
+      while (i >= 0 && c[i] == p->d - t + i) --i;
+      if (i < 0) break;
+      ++c[i];
+      for (int k = i + 1; k < t; ++k) c[k] = c[k - 1] + 1;
+    }
+    o.term_end = (int32_t)pl->terms.size();
+  }
+  pl->nterms = (int32_t)pl->terms.size();
+  pl->ncoef = coef;
+  pl->grid_total = grid;
+
+  // ---- per-order tables, LDS checks
+  const size_t csz = 2 * pl->rsize;
+  for (int t = 1; t <= p->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    const int K = o.N - 1;
+    size_t lds_gather = (size_t)o.gsize * 16;   // spread accumulates in FP64
+    size_t lds_pack = (size_t)csz * (t == 1 ? K : t == 2 ? (size_t)K * K + (size_t)K * o.n
+                                                         : (size_t)K * K * K + (size_t)K * K * o.n + (size_t)K * o.n * o.n);
+    size_t lds_adj = (size_t)csz * (t == 1 ? o.n : t == 2 ? (size_t)o.n * o.n + (size_t)o.n * K
+                                                         : (size_t)o.n * o.n * o.n + (size_t)o.n * o.n * K + (size_t)o.n * K * K);
+    size_t need = std::max(lds_gather, std::max(lds_pack, lds_adj));
+    if (need > pl->lds_limit) {
+      free_plan(pl);
+      return fail(GT_EUNSUPPORTED, "grid of order " + std::to_string(t) + " needs " + std::to_string(need) +
+                                       " bytes of LDS (limit " + std::to_string(pl->lds_limit) + ")");
+    }
+    o.deconv.resize(K);
+    for (int a = 0; a < K; ++a) {
+      int k = a - o.N / 2 + (a >= o.N / 2 ? 1 : 0);
+      long double ph = kb_phihat(k, o.m, (long double)o.b, o.n);
+      o.deconv[a] = (double)(((k & 1) ? -1.0L : 1.0L) / ph);
+    }
+    o.roots.resize(2 * o.n);
+    for (int j = 0; j < o.n; ++j) {
+      long double a = 2.0L * M_PIl * j / o.n;
+      o.roots[2 * j] = (double)std::cos(a);
+      o.roots[2 * j + 1] = (double)std::sin(a);
+    }
+    int D = p->dtype == GT_C64 ? Deg<float>::value : Deg<double>::value;
+    window_poly(o.m, (long double)o.b, D, o.poly);
+    int r1 = p->dtype == GT_C64 ? upload<float>(o.deconv, &o.d_deconv) : upload<double>(o.deconv, &o.d_deconv);
+    int r2 = p->dtype == GT_C64 ? upload<float>(o.roots, &o.d_roots) : upload<double>(o.roots, &o.d_roots);
+    int r3 = p->dtype == GT_C64 ? upload<float>(o.poly, &o.d_poly) : upload<double>(o.poly, &o.d_poly);
+    if (r1 || r2 || r3) {
+      free_plan(pl);
+      return r1 ? r1 : (r2 ? r2 : r3);
+    }
+  }
+
+  // ---- gather work items: kGatherBS virtual nodes each, grouped by right-hand side
+  auto add_items = [&](std::vector<WorkItem> &items, std::vector<int32_t> &begin, int64_t chunk) {
+    items.clear();
+    begin.assign(pl->R + 1, 0);
+    for (int r = 0; r < pl->R; ++r) {
+      begin[r] = (int32_t)items.size();
+      int64_t lo = pl->ragged ? pl->offs[r] : 0, hi = pl->ragged ? pl->offs[r + 1] : pl->M;
+      int64_t vbase = pl->ragged ? 0 : (int64_t)r * pl->M;
+      for (int64_t a = lo; a < hi; a += chunk) {
+        WorkItem w{};
+        w.v0 = vbase + a;
+        w.x0 = a;
+        w.count = (int32_t)std::min<int64_t>(chunk, hi - a);
+        w.r = r;
+        items.push_back(w);
+      }
+    }
+    begin[pl->R] = (int32_t)items.size();
+  };
+  add_items(pl->gitems, pl->gitem_begin, kGatherBS);
+  const int64_t ngi = (int64_t)pl->gitems.size();
+
+  // ---- gather term blocks per order (enough workgroups, few partial vectors)
+  int32_t nb = 0;
+  for (int t = 1; t <= p->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    int nt = o.term_end - o.term_begin;
+    int W = 2 * o.m;
+    int wt = t == 1 ? W : (t == 2 ? W * W : W * W * W);
+    int min_tpb = std::max(1, 64 / wt);
+    int64_t want = (2048 + ngi - 1) / ngi;
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (nt + min_tpb - 1) / min_tpb));
+    int tpb = (nt + blocks - 1) / blocks;
+    o.blocks.clear();
+    for (int a = o.term_begin; a < o.term_end; a += tpb) {
+      o.blocks.push_back(a);
+      o.blocks.push_back(std::min(o.term_end, a + tpb));
+    }
+    o.block_base = nb;
+    nb += (int32_t)o.blocks.size() / 2;
+  }
+  pl->nblocks = nb;
+
+  // ---- spread work items per order
+  for (int t = 1; t <= p->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    int nt = o.term_end - o.term_begin;
+    int64_t chunk = std::max<int64_t>(2048, (pl->Vtot * nt + 2047) / 2048);
+    // bound the partial-grid memory to about 1 GiB
+    int64_t per_item = (int64_t)nt * o.gsize * (int64_t)csz;
+    int64_t max_items = std::max<int64_t>(pl->R, (int64_t(1) << 30) / std::max<int64_t>(1, per_item));
+    int64_t items_est = (pl->Vtot + chunk - 1) / chunk + pl->R;
+    if (items_est > max_items) chunk = std::max<int64_t>(chunk, (pl->Vtot + max_items - 1) / std::max<int64_t>(1, max_items - pl->R));
+    add_items(o.sitems, o.sitem_begin, chunk);
+    o.gpart_stride = 0;
+    for (int i = o.term_begin; i < o.term_end; ++i) {
+      pl->terms[i].gpart_off = o.gpart_stride;
+      o.gpart_stride += o.gsize;
+    }
+  }
+
+  // ---- device memory
+  const int64_t nx = (int64_t)pl->d * pl->Mtot;
+  if ((rc = upload_raw(pl->terms, &pl->d_terms)) || (rc = dev_alloc(&pl->d_x, (size_t)nx * pl->rsize, s)) ||
+      (rc = dev_alloc(&pl->d_grid, (size_t)pl->R * pl->grid_total * csz, s)) ||
+      (rc = upload_raw(pl->gitems, &pl->d_gitems)) || (rc = upload_raw(pl->gitem_begin, &pl->d_gitem_begin)) ||
+      (rc = dev_alloc(&pl->d_fpart, (size_t)std::max(1, pl->nblocks) * pl->Vtot * csz, s)) ||
+      (rc = dev_alloc((void **)&pl->d_ysum, (size_t)ngi * 2 * sizeof(double), s)) ||
+      (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s))) {
+    free_plan(pl);
+    return rc;
+  }
+  for (int t = 1; t <= p->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    if ((rc = upload_raw(o.blocks, &o.d_blocks)) || (rc = upload_raw(o.sitems, &o.d_sitems)) ||
+        (rc = upload_raw(o.sitem_begin, &o.d_sitem_begin)) ||
+        (rc = dev_alloc(&o.d_gpart, (size_t)o.sitems.size() * o.gpart_stride * csz, s))) {
+      free_plan(pl);
+      return rc;
+    }
+  }
+
+  // ---- nodes: wrap, transpose, validate (one synchronisation)
+  rc = p->dtype == GT_C64 ? launch_prepare_nodes<float>(pl, x, s) : launch_prepare_nodes<double>(pl, x, s);
+  if (rc) {
+    free_plan(pl);
+    return rc;
+  }
+  int32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, pl->d_flag, sizeof(flag), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return hip_fail(e, "node validation");
+  }
+  if (flag) {
+    free_plan(pl);
+    return fail(GT_EINVAL, "nodes contain NaN or Inf");
+  }
+  *out = pl;
+  return GT_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char *gt_version(void) { return "grouped-nfft-gfx950 1.0"; }
+
+const char *gt_last_error(void) { return g_last_error.c_str(); }
+
+int gt_prof_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return GT_OK;
+}
+
+int64_t gt_prof_report(char *buf, int64_t len) {
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  std::vector<std::pair<std::string, std::pair<int64_t, double>>> agg;
+  for (auto &r : recs) {
+    float ms = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto it = std::find_if(agg.begin(), agg.end(), [&](auto &a) { return a.first == r.name; });
+      if (it == agg.end()) {
+        agg.push_back({r.name, {1, (double)ms}});
+      } else {
+        it->second.first += 1;
+        it->second.second += ms;
+      }
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  std::string js = "{";
+  for (size_t i = 0; i < agg.size(); ++i) {
+    char tmp[256];
+    snprintf(tmp, sizeof(tmp), "%s\"%s\": [%lld, %.6f]", i ? ", " : "", agg[i].first.c_str(),
+             (long long)agg[i].second.first, agg[i].second.second);
+    js += tmp;
+  }
+  js += "}";
+  if (buf && len > 0) {
+    size_t nc = std::min<size_t>((size_t)len - 1, js.size());
+    memcpy(buf, js.data(), nc);
+    buf[nc] = 0;
+  }
+  return (int64_t)js.size() + 1;
+}
+
+int64_t gt_num_terms(int32_t d, int32_t ds) {
+  if (d < 1 || ds < 0 || ds > d) return -1;
+  int64_t s = 0;
+  for (int t = 0; t <= ds; ++t) s += binom(d, t);
+  return s;
+}
+
+int64_t gt_num_coeffs(int32_t d, int32_t ds, const int32_t *N) {
+  if (d < 1 || ds < 0 || ds > d || (ds > 0 && !N)) return -1;
+  int64_t s = 1;
+  for (int t = 1; t <= ds; ++t) {
+    if (N[t - 1] < 2 || N[t - 1] % 2) return -1;
+    int64_t g = 1;
+    for (int i = 0; i < t; ++i) g *= (N[t - 1] - 1);
+    s += binom(d, t) * g;
+  }
+  return s;
+}
+
+int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets) {
+  if (!p) return fail(GT_EINVAL, "problem is NULL");
+  if (p->d < 1 || p->ds < 0 || p->ds > p->d) return fail(GT_EINVAL, "need d >= 1 and 0 <= ds <= d");
+  if (p->ds > kMaxOrder) return fail(GT_EUNSUPPORTED, "terms of order > 3 are not implemented");
+  int64_t i = 0, off = 0;
+  for (int t = 0; t <= p->ds; ++t) {
+    if (t > 0 && (p->N[t - 1] < 2 || p->N[t - 1] % 2)) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
+    int64_t g = 1;
+    for (int k = 0; k < t; ++k) g *= (p->N[t - 1] - 1);
+    std::vector<int> c(t);
+    for (int k = 0; k < t; ++k) c[k] = k;
+    while (true) {
+      if (coords)
+        for (int k = 0; k < 3; ++k) coords[i * 3 + k] = k < t ? c[k] : -1;
+      if (offsets) offsets[i] = off;
+      off += g;
+      ++i;
+      if (t == 0) break;
+      int q = t - 1;
+      while (q >= 0 && c[q] == p->d - t + q) --q;
+      if (q < 0) break;
+      ++c[q];
+      for (int k = q + 1; k < t; ++k) c[k] = c[k - 1] + 1;
+    }
+  }
+  if (offsets) offsets[i] = off;
+  return GT_OK;
+}
+
+int gt_plan_create(const gt_problem *p, const void *x, void *stream, gt_plan **out) {
+  if (!out) return fail(GT_EINVAL, "out is NULL");
+  return build_plan(p, x, (hipStream_t)stream, out);
+}
+
+int gt_plan_destroy(gt_plan *plan) {
+  free_plan(plan);
+  return GT_OK;
+}
+
+int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n) {
+  if (!plan || t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  if (m) *m = plan->ord[t].m;
+  if (n) *n = plan->ord[t].n;
+  return GT_OK;
+}
+
+int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream) {
+  if (!plan || !fhat || !f) return fail(GT_EINVAL, "NULL argument");
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64 ? launch_forward<float>(plan, fhat, nullptr, f, (hipStream_t)stream)
+                               : launch_forward<double>(plan, fhat, nullptr, f, (hipStream_t)stream);
+}
+
+int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream) {
+  if (!plan || !fhat || !y) return fail(GT_EINVAL, "NULL argument");
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64 ? launch_adjoint<float>(plan, y, nullptr, fhat, (hipStream_t)stream)
+                               : launch_adjoint<double>(plan, y, nullptr, fhat, (hipStream_t)stream);
+}
+
+int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, void *stream) {
+  if (!plan || !fhat || !g || !gx) return fail(GT_EINVAL, "NULL argument");
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64 ? launch_node_grad<float>(plan, fhat, g, gx, (hipStream_t)stream)
+                               : launch_node_grad<double>(plan, fhat, g, gx, (hipStream_t)stream);
+}
+
+int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *stream) {
+  if (!plan || !out || iters < 1) return fail(GT_EINVAL, "invalid argument");
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64 ? run_norm_estimate<float>(plan, iters, out, (hipStream_t)stream)
+                               : run_norm_estimate<double>(plan, iters, out, (hipStream_t)stream);
+}
+
+int grouped_trafo(const gt_problem *p, const void *x, const void *fhat, void *f, void *stream) {
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  rc = gt_plan_trafo(pl, fhat, f, stream);
+  free_plan(pl);
+  return rc;
+}
+
+int grouped_adjoint(const gt_problem *p, const void *x, const void *y, void *fhat, void *stream) {
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  rc = gt_plan_adjoint(pl, y, fhat, stream);
+  free_plan(pl);
+  return rc;
+}
+
+int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *lambda, const void *omega,
+               int32_t max_iter, double tol, void *fhat, gt_solve_info *info, void *stream) {
+  if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (p)
+    for (int r = 0; r < p->R; ++r)
+      if (!(lambda[r] >= 0.0) || !std::isfinite(lambda[r])) return fail(GT_EINVAL, "lambda must be finite and >= 0");
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  rc = pl->dtype == GT_C64 ? run_lsqr<float>(pl, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream)
+                           : run_lsqr<double>(pl, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream);
+  free_plan(pl);
+  return rc;
+}
+
+int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda, const void *omega,
+                      int32_t max_iter, double L, double eta, double tol, void *fhat, gt_solve_info *info,
+                      void *stream) {
+  if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (!std::isfinite(L) || !std::isfinite(eta)) return fail(GT_EINVAL, "L and eta must be finite");
+  if (p)
+    for (int r = 0; r < p->R; ++r)
+      if (!(lambda[r] > 0.0) || !std::isfinite(lambda[r])) return fail(GT_EINVAL, "lambda must be finite and > 0");
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  rc = pl->dtype == GT_C64
+           ? run_fista<float>(pl, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream)
+           : run_fista<double>(pl, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream);
+  free_plan(pl);
+  return rc;
+}
+
+}  // extern "C"

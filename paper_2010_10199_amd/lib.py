@@ -1,0 +1,229 @@
+"""ctypes binding of libgrouped.so (the C ABI declared in include/grouped.h).
+
+Argument marshalling only: every step of the transforms and solvers runs in the HIP
+library.  Torch tensors supply device memory (``data_ptr``) and the stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no CPU fallback: loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrouped.so")
+
+GT_OK, GT_EINVAL, GT_ENOMEM, GT_EHIP, GT_EUNSUPPORTED = 0, -1, -2, -3, -4
+GT_C64, GT_C128 = 1, 2
+GT_MAX_ORDER = 3
+GT_SOLVE_CONVERGED, GT_SOLVE_MAX_ITER, GT_SOLVE_BREAKDOWN, GT_SOLVE_BACKTRACK_CAP = 1, 2, 4, 8
+
+# every symbol include/grouped.h declares
+EXPORTS = [
+    "gt_num_terms", "gt_num_coeffs", "gt_term_table", "grouped_trafo", "grouped_adjoint",
+    "gt_plan_create", "gt_plan_destroy", "gt_plan_trafo", "gt_plan_adjoint", "gt_plan_node_grad",
+    "gt_plan_order_info", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
+    "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
+]
+
+
+class GtProblem(C.Structure):
+    _fields_ = [
+        ("d", C.c_int32), ("ds", C.c_int32), ("N", C.c_int32 * GT_MAX_ORDER), ("M", C.c_int64),
+        ("R", C.c_int32), ("offsets", C.POINTER(C.c_int64)), ("dtype", C.c_int32), ("m", C.c_int32),
+        ("sigma", C.c_double),
+    ]
+
+
+class GtSolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("flags", C.c_int32), ("resid", C.c_double), ("t_k", C.c_double),
+                ("L", C.c_double)]
+
+
+class GroupedError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built: run python -m paper_2010_10199_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER(GtProblem)
+    sig = {
+        "gt_num_terms": (i64, [i32, i32]),
+        "gt_num_coeffs": (i64, [i32, i32, C.POINTER(i32)]),
+        "gt_term_table": (C.c_int, [P, C.POINTER(i32), C.POINTER(i64)]),
+        "grouped_trafo": (C.c_int, [P, vp, vp, vp, vp]),
+        "grouped_adjoint": (C.c_int, [P, vp, vp, vp, vp]),
+        "gt_plan_create": (C.c_int, [P, vp, vp, C.POINTER(vp)]),
+        "gt_plan_destroy": (C.c_int, [vp]),
+        "gt_plan_trafo": (C.c_int, [vp, vp, vp, vp]),
+        "gt_plan_adjoint": (C.c_int, [vp, vp, vp, vp]),
+        "gt_plan_node_grad": (C.c_int, [vp, vp, vp, vp, vp]),
+        "gt_plan_order_info": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "gt_plan_norm_estimate": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
+        "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
+        "fista_group_lasso": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp,
+                                        C.POINTER(GtSolveInfo), vp]),
+        "gt_last_error": (C.c_char_p, []),
+        "gt_prof_enable": (C.c_int, [i32]),
+        "gt_prof_report": (i64, [C.c_char_p, i64]),
+        "gt_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != GT_OK:
+        raise GroupedError(rc, load().gt_last_error().decode())
+
+
+def make_problem(d: int, ds: int, N: Sequence[int], M: int = 0, R: int = 1, dtype: int = GT_C64,
+                 m: int = 0, sigma: float = 0.0, offsets: Optional[Sequence[int]] = None):
+    """Build a GtProblem; returns (problem, keepalive) - keep the second alive while in use."""
+    p = GtProblem()
+    p.d, p.ds = int(d), int(ds)
+    for i in range(GT_MAX_ORDER):
+        p.N[i] = int(N[i]) if i < len(N) else 0
+    p.M, p.R, p.dtype, p.m, p.sigma = int(M), int(R), int(dtype), int(m), float(sigma)
+    keep = None
+    if offsets is not None:
+        keep = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        p.offsets = keep.ctypes.data_as(C.POINTER(C.c_int64))
+    else:
+        p.offsets = None
+    return p, keep
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return int(stream)
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- index set
+def gt_num_terms(d: int, ds: int) -> int:
+    return int(load().gt_num_terms(d, ds))
+
+
+def gt_num_coeffs(d: int, ds: int, N: Sequence[int]) -> int:
+    arr = (C.c_int32 * max(1, len(N)))(*[int(v) for v in N])
+    return int(load().gt_num_coeffs(d, ds, arr))
+
+
+def gt_term_table(d: int, ds: int, N: Sequence[int]):
+    """(coords |U| x 3 int32 with -1 padding, offsets |U|+1 int64)."""
+    p, _ = make_problem(d, ds, N, M=1)
+    nt = gt_num_terms(d, ds)
+    coords = np.zeros((nt, 3), dtype=np.int32)
+    offs = np.zeros(nt + 1, dtype=np.int64)
+    _check(load().gt_term_table(C.byref(p), coords.ctypes.data_as(C.POINTER(C.c_int32)),
+                                offs.ctypes.data_as(C.POINTER(C.c_int64))))
+    return coords, offs
+
+
+# ---------------------------------------------------------------- one-shot transforms
+def grouped_trafo(problem, x, fhat, f, stream=None):
+    _check(load().grouped_trafo(C.byref(problem), _ptr(x), _ptr(fhat), _ptr(f), _stream(stream)))
+
+
+def grouped_adjoint(problem, x, y, fhat, stream=None):
+    _check(load().grouped_adjoint(C.byref(problem), _ptr(x), _ptr(y), _ptr(fhat), _stream(stream)))
+
+
+def lsqr_solve(problem, x, y, lambdas, omega, max_iter, tol, fhat, stream=None):
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    info = (GtSolveInfo * problem.R)()
+    _check(load().lsqr_solve(C.byref(problem), _ptr(x), _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                             _ptr(omega), int(max_iter), float(tol), _ptr(fhat), info, _stream(stream)))
+    return list(info)
+
+
+def fista_group_lasso(problem, x, y, lambdas, omega, max_iter, L, eta, tol, fhat, stream=None):
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    info = (GtSolveInfo * problem.R)()
+    _check(load().fista_group_lasso(C.byref(problem), _ptr(x), _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                    _ptr(omega), int(max_iter), float(L), float(eta), float(tol), _ptr(fhat),
+                                    info, _stream(stream)))
+    return list(info)
+
+
+# ---------------------------------------------------------------- plans
+class Plan:
+    """Owns a gt_plan for (problem, nodes); the nodes are copied into the plan."""
+
+    def __init__(self, problem, x, stream=None, keepalive=None):
+        self._lib = load()
+        self.problem = problem
+        self._keep = keepalive
+        h = C.c_void_p()
+        _check(self._lib.gt_plan_create(C.byref(problem), _ptr(x), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def trafo(self, fhat, f, stream=None):
+        _check(self._lib.gt_plan_trafo(self.handle, _ptr(fhat), _ptr(f), _stream(stream)))
+
+    def adjoint(self, y, fhat, stream=None):
+        _check(self._lib.gt_plan_adjoint(self.handle, _ptr(y), _ptr(fhat), _stream(stream)))
+
+    def node_grad(self, fhat, g, gx, stream=None):
+        _check(self._lib.gt_plan_node_grad(self.handle, _ptr(fhat), _ptr(g), _ptr(gx), _stream(stream)))
+
+    def order_info(self, t: int):
+        m, n = C.c_int32(), C.c_int32()
+        _check(self._lib.gt_plan_order_info(self.handle, int(t), C.byref(m), C.byref(n)))
+        return int(m.value), int(n.value)
+
+    def norm_estimate(self, iters=50, stream=None) -> float:
+        out = C.c_double()
+        _check(self._lib.gt_plan_norm_estimate(self.handle, int(iters), C.byref(out), _stream(stream)))
+        return float(out.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.gt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def prof_enable(on: bool = True):
+    _check(load().gt_prof_enable(1 if on else 0))
+
+
+def prof_report() -> dict:
+    import json
+    lib = load()
+    # gt_prof_report clears the records, so it is called once with a large buffer
+    buf = C.create_string_buffer(1 << 16)
+    lib.gt_prof_report(buf, len(buf))
+    return json.loads(buf.value.decode() or "{}")
