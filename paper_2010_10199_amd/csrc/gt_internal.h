@@ -29,8 +29,9 @@ namespace gt {
 constexpr int kMaxOrder = 3;
 constexpr int kMinM = 2;
 constexpr int kMaxM = 8;
-constexpr int kGatherBS = 256;    // threads per gather workgroup (one node each)
-constexpr int kSpreadBS = 512;    // threads per spread workgroup
+constexpr int kGatherBS = 256;    // threads per gather workgroup
+constexpr int kGatherNodes = 4;   // sorted nodes per gather thread
+constexpr int kSpreadWaves = 8;   // wavefronts per spread workgroup
 constexpr int kPackBS = 256;
 constexpr int kVecBS = 256;
 
@@ -48,6 +49,18 @@ struct DevTerm {
   int64_t coef_off;    // offset of the group in the coefficient vector
   int64_t grid_off;    // offset of the term's grid inside one right-hand side's grid block
   int64_t gpart_off;   // offset inside one spread item's partial-grid block of its order
+};
+
+struct GatherItem {    // a run of sorted positions of one term and right-hand side
+  int64_t q0;          // first position in the order's perm array
+  int32_t count;
+  int32_t tl;          // term index within the order
+  int32_t r;           // right-hand side (dataset when ragged)
+  int32_t pad;
+};
+
+struct SpreadItem {    // a range of grid cells of one right-hand side (dataset b of the binning)
+  int32_t r, b, c0, c1;
 };
 
 struct WorkItem {      // a contiguous run of virtual nodes of one right-hand side
@@ -71,17 +84,21 @@ struct OrderHost {
   double b = 0;                       // Kaiser-Bessel shape parameter
   std::vector<double> deconv, roots, poly;
   void *d_deconv = nullptr, *d_roots = nullptr, *d_poly = nullptr;
-  // gather term blocks of this order: [begin, end) term ranges
-  std::vector<int32_t> blocks;        // pairs
-  int32_t *d_blocks = nullptr;
-  int32_t block_base = 0;             // index of its first block among all blocks
-  // spread work items of this order
-  std::vector<WorkItem> sitems;
-  WorkItem *d_sitems = nullptr;
+  // gather work items of this order (runs of sorted nodes), grouped by term
+  std::vector<struct GatherItem> gitems;
+  struct GatherItem *d_gitems = nullptr;
+  std::vector<int32_t> gitem_begin;   // per term of the order, +1
+  // node binning of this order (per term, by cell) and spread work items
+  int64_t ncell = 0;                  // n^order
+  int32_t *d_perm = nullptr;          // terms x Mtot sorted node indices
+  int64_t *d_cstart = nullptr;        // (terms x datasets x ncell) + 1 start positions
+  std::vector<SpreadItem> sitems;
+  SpreadItem *d_sitems = nullptr;
   std::vector<int32_t> sitem_begin;   // per right-hand side, R+1
   int32_t *d_sitem_begin = nullptr;
   int64_t gpart_stride = 0;           // complex elements per spread item
   void *d_gpart = nullptr;
+  void *d_gsum = nullptr;             // folded spread grids: R x terms x n^order
 };
 
 }  // namespace gt
@@ -106,8 +123,8 @@ struct gt_plan {
   gt::WorkItem *d_gitems = nullptr;
   std::vector<int32_t> gitem_begin;   // per right-hand side, R+1
   int32_t *d_gitem_begin = nullptr;
-  int32_t nblocks = 0;
-  void *d_fpart = nullptr;
+  int32_t nslots = 0;                 // gather output slots (terms per forward block)
+  void *d_fpart = nullptr;            // nslots x Vtot
   double *d_ysum = nullptr;           // per gather item: partial sums (re, im) for the empty set
   int32_t *d_flag = nullptr;          // node validation flag
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
@@ -140,6 +157,7 @@ template <typename T> int launch_forward(gt_plan *pl, const void *fhat, const T 
 template <typename T> int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s);
 template <typename T> int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hipStream_t s);
 template <typename T> int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s);
+template <typename T> int launch_binning(gt_plan *pl, hipStream_t s);   // binning.hip
 
 // ---- solver drivers (solvers.hip) ----
 template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega,

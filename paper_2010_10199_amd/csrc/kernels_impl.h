@@ -69,16 +69,27 @@ __device__ __forceinline__ T frac_offset(T x, int n, int &fl) {
   return fma(nf, x, (T)(n / 2 - f));   // exact product, one rounding: fractional offset
 }
 
+// All 2m window values.  The window is even, so point 2m-1-j is point j at -z (the host
+// mirrors the coefficients exactly); one even part E(z^2) and one odd part z O(z^2) give
+// both values of a pair: psi_j = E + zO, psi_{2m-1-j} = E - zO.
 template <typename T, int MH>
 __device__ __forceinline__ void window_values(T z, const T *__restrict__ poly, T (&psi)[2 * MH]) {
   constexpr int D = Deg<T>::value;
+  constexpr int DE = D - (D & 1);          // highest even power
+  constexpr int DO = D - 1 + (D & 1);      // highest odd power
+  const T z2 = z * z;
 #pragma unroll
-  for (int j = 0; j < 2 * MH; ++j) {
+  for (int j = 0; j < MH; ++j) {
     const T *c = poly + j * (D + 1);
-    T acc = c[D];
+    T e = c[DE];
 #pragma unroll
-    for (int q = D - 1; q >= 0; --q) acc = fma(acc, z, c[q]);
-    psi[j] = acc;
+    for (int q = DE - 2; q >= 0; q -= 2) e = fma(e, z2, c[q]);
+    T o = c[DO];
+#pragma unroll
+    for (int q = DO - 2; q >= 1; q -= 2) o = fma(o, z2, c[q]);
+    o *= z;
+    psi[j] = e + o;
+    psi[2 * MH - 1 - j] = e - o;
   }
 }
 
@@ -357,148 +368,29 @@ __device__ __forceinline__ cx_t<T> gather_term(const cx_t<T> *__restrict__ G, co
   return cmake<T>(re, im);
 }
 
-template <typename T, int ORDER, int MH>
-__global__ __launch_bounds__(kGatherBS) void k_gather(const T *__restrict__ xT, int64_t Mx,
-                                                      const WorkItem *__restrict__ items, const int32_t *__restrict__ blocks,
-                                                      int32_t block_base, const DevTerm *__restrict__ terms,
-                                                      OrderParams<T> op, const cx_t<T> *__restrict__ grids,
-                                                      int64_t grid_total, cx_t<T> *__restrict__ fpart, int64_t Vtot) {
-  using C = cx_t<T>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *G = reinterpret_cast<C *>(smem_raw);
-  const WorkItem it = items[blockIdx.x];
-  const int tb = blocks[2 * blockIdx.y], te = blocks[2 * blockIdx.y + 1];
-  const int tid = threadIdx.x;
-  const bool active = tid < it.count;
-  const int64_t xi = it.x0 + tid;
-  const C *gbase = grids + (int64_t)it.r * grid_total;
-  T re = 0, im = 0;
-  for (int term = tb; term < te; ++term) {
-    const DevTerm tm = terms[term];
-    const C *src = gbase + tm.grid_off;
-    __syncthreads();
-    for (int i = tid; i < op.gsize; i += kGatherBS) G[i] = src[i];
-    __syncthreads();
-    if (active) {
-      const C v = gather_term<T, ORDER, MH>(G, xT, Mx, xi, tm, op);
-      re += v.x;
-      im += v.y;
-    }
-  }
-  if (active) fpart[(int64_t)(block_base + blockIdx.y) * Vtot + it.v0 + tid] = cmake<T>(re, im);
-}
-
-// f_v = fhat_empty(r) + sum over term blocks of the partial sums.
+// f_v = (accumulate ? f_v : fhat_empty(r)) + sum over the term slots, in slot order.
 template <typename T>
 __global__ __launch_bounds__(kGatherBS) void k_reduce_f(const cx_t<T> *__restrict__ fhat, int64_t ncoef,
                                                         const WorkItem *__restrict__ items,
-                                                        const cx_t<T> *__restrict__ fpart, int nblocks, int64_t Vtot,
-                                                        cx_t<T> *__restrict__ f) {
+                                                        const cx_t<T> *__restrict__ slots, int nslots, int64_t Vtot,
+                                                        int accumulate, cx_t<T> *__restrict__ f) {
   const WorkItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
   if (tid >= it.count) return;
   const int64_t v = it.v0 + tid;
-  cx_t<T> acc = fhat[(int64_t)it.r * ncoef];
-  for (int b = 0; b < nblocks; ++b) {
-    const cx_t<T> p = fpart[(int64_t)b * Vtot + v];
+  cx_t<T> acc = accumulate ? f[v] : fhat[(int64_t)it.r * ncoef];
+  for (int b = 0; b < nslots; ++b) {
+    const cx_t<T> p = slots[(int64_t)b * Vtot + v];
     acc.x += p.x;
     acc.y += p.y;
   }
   f[v] = acc;
 }
 
-// ------------------------------------------------------------------ K4 spread
-// Workgroup = (a chunk of virtual nodes of one right-hand side) x (one term).  The grid
-// lives in LDS as FP64 for both precisions (FP64 LDS atomics measured ~5x faster than FP32
-// ones on gfx950, and the sum of up to ~1e5 contributions per grid point stays exact to
-// FP32 output precision); nodes add y_v * window with LDS atomics.  The result is this
-// chunk's partial grid (halo layout), summed over chunks by the adjoint DFT.
-template <typename T, int ORDER, int MH>
-__device__ __forceinline__ void spread_node(double2 *__restrict__ G, const T *__restrict__ xT, int64_t Mx, int64_t xi,
-                                            cx_t<T> yv, const DevTerm &tm, const OrderParams<T> &op) {
-  constexpr int W = 2 * MH;
-  const int n = op.n, P = op.P;
-  if (ORDER == 1) {
-    int f0;
-    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
-    T p0[W];
-    window_values<T, MH>(z0, op.poly, p0);
-    double2 *g = G + f0;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      atomicAdd(&g[j].x, (double)(p0[j] * yv.x));
-      atomicAdd(&g[j].y, (double)(p0[j] * yv.y));
-    }
-  } else if (ORDER == 2) {
-    int f0, f1;
-    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
-    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
-    T p0[W], p1[W];
-    window_values<T, MH>(z0, op.poly, p0);
-    window_values<T, MH>(z1, op.poly, p1);
-    int r = wrap_start(f0, MH, n);
-#pragma unroll
-    for (int j1 = 0; j1 < W; ++j1) {
-      double2 *row = G + r * P + f1;
-      const T wr = p0[j1] * yv.x, wi = p0[j1] * yv.y;
-#pragma unroll
-      for (int j2 = 0; j2 < W; ++j2) {
-        atomicAdd(&row[j2].x, (double)(p1[j2] * wr));
-        atomicAdd(&row[j2].y, (double)(p1[j2] * wi));
-      }
-      r = (r + 1 == n) ? 0 : r + 1;
-    }
-  } else {
-    int f0, f1, f2;
-    const T z0 = frac_offset<T>(xT[(int64_t)tm.c0 * Mx + xi], n, f0) * (T)2 - (T)1;
-    const T z1 = frac_offset<T>(xT[(int64_t)tm.c1 * Mx + xi], n, f1) * (T)2 - (T)1;
-    const T z2 = frac_offset<T>(xT[(int64_t)tm.c2 * Mx + xi], n, f2) * (T)2 - (T)1;
-    T p1[W], p2[W];
-    window_values<T, MH>(z1, op.poly, p1);
-    window_values<T, MH>(z2, op.poly, p2);
-    int r0 = wrap_start(f0, MH, n);
-    const int r1s = wrap_start(f1, MH, n);
-    constexpr int D = Deg<T>::value;
-#pragma unroll 1
-    for (int j1 = 0; j1 < W; ++j1) {
-      const T w0 = window_point<T>(z0, op.poly + j1 * (D + 1));
-      const T ar = w0 * yv.x, ai = w0 * yv.y;
-      double2 *plane = G + (int64_t)r0 * n * P + f2;
-      int r1 = r1s;
-#pragma unroll
-      for (int j2 = 0; j2 < W; ++j2) {
-        double2 *row = plane + r1 * P;
-        const T br = p1[j2] * ar, bi = p1[j2] * ai;
-#pragma unroll
-        for (int j3 = 0; j3 < W; ++j3) {
-          atomicAdd(&row[j3].x, (double)(p2[j3] * br));
-          atomicAdd(&row[j3].y, (double)(p2[j3] * bi));
-        }
-        r1 = (r1 + 1 == n) ? 0 : r1 + 1;
-      }
-      r0 = (r0 + 1 == n) ? 0 : r0 + 1;
-    }
-  }
-}
-
-template <typename T, int ORDER, int MH>
-__global__ __launch_bounds__(kSpreadBS) void k_spread(const T *__restrict__ xT, int64_t Mx,
-                                                      const WorkItem *__restrict__ items, const DevTerm *__restrict__ terms,
-                                                      OrderParams<T> op, const cx_t<T> *__restrict__ y,
-                                                      cx_t<T> *__restrict__ gpart, int64_t gstride) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2 *G = reinterpret_cast<double2 *>(smem_raw);
-  const WorkItem it = items[blockIdx.x];
-  const DevTerm tm = terms[op.term_begin + blockIdx.y];
-  const int tid = threadIdx.x;
-  const int gsize = op.gsize;
-  for (int i = tid; i < gsize; i += kSpreadBS) G[i] = make_double2(0.0, 0.0);
-  __syncthreads();
-  for (int i = tid; i < it.count; i += kSpreadBS) spread_node<T, ORDER, MH>(G, xT, Mx, it.x0 + i, y[it.v0 + i], tm, op);
-  __syncthreads();
-  cx_t<T> *out = gpart + (int64_t)blockIdx.x * gstride + tm.gpart_off;
-  for (int i = tid; i < gsize; i += kSpreadBS) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
-}
+}  // namespace gt
+#include "gather.h"   // K3 gather (binned, one slot per term)
+#include "spread.h"   // K4 spread (binned, MFMA)
+namespace gt {
 
 // Partial sums of y over each gather item (for the empty-set coefficient).
 template <typename T>
@@ -519,25 +411,60 @@ __global__ __launch_bounds__(kGatherBS) void k_ysum(const WorkItem *__restrict__
   }
 }
 
+// One workgroup per right-hand side: fhat_empty(r) = sum of the item partial sums of r.
 template <typename T>
-__global__ void k_empty_adj(const int32_t *__restrict__ item_begin, const double *__restrict__ ysum, int R,
-                            int64_t ncoef, cx_t<T> *__restrict__ fhat) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
+__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restrict__ item_begin,
+                                                         const double *__restrict__ ysum, int64_t ncoef,
+                                                         cx_t<T> *__restrict__ fhat) {
+  __shared__ double sh[2 * (kGatherBS / 64)];
+  const int r = blockIdx.x;
   double a = 0, b = 0;
-  for (int i = item_begin[r]; i < item_begin[r + 1]; ++i) {
+  for (int i = item_begin[r] + threadIdx.x; i < item_begin[r + 1]; i += kGatherBS) {
     a += ysum[2 * i];
     b += ysum[2 * i + 1];
   }
-  fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
+  block_sum2(a, b, sh);
+  if (threadIdx.x == 0) fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
+}
+
+// ------------------------------------------------------------------ fold of the spread partials
+// One thread per unpadded grid point l of (right-hand side, term): sum over the spread items
+// of that right-hand side and over the halo copies p of l (p = l + m - 1 mod n, + n, ...),
+// in FP64.  gsum layout: [r][term_local][outer][n] with outer = n^(order-1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict__ gpart, int64_t gstride,
+                                                       const int32_t *__restrict__ item_begin,
+                                                       const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                       int order, cx_t<T> *__restrict__ gsum) {
+  const int n = op.n, P = op.P, mm1 = op.m - 1;
+  const int nt = op.term_end - op.term_begin;
+  const int64_t outer = order == 1 ? 1 : (order == 2 ? n : (int64_t)n * n);
+  const int64_t per_term = outer * n;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= per_term * nt) return;
+  const int r = blockIdx.y;
+  const int tl = (int)(idx / per_term);
+  const int64_t rem = idx - (int64_t)tl * per_term;
+  const int64_t o = rem / n;
+  const int l = (int)(rem - o * n);
+  const DevTerm tm = terms[op.term_begin + tl];
+  double re = 0, im = 0;
+  for (int s = item_begin[r]; s < item_begin[r + 1]; ++s) {
+    const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
+    for (int p = (l + mm1) % n; p < P; p += n) {
+      const cx_t<T> v = src[p];
+      re += (double)v.x;
+      im += (double)v.y;
+    }
+  }
+  gsum[((int64_t)r * nt + tl) * per_term + rem] = cmake<T>((T)re, (T)im);
 }
 
 // ------------------------------------------------------------------ K2 + K5 adjoint
-// One workgroup per (term, right-hand side): fold the halo and sum the chunk partial grids
-// (FP64), pruned forward DFT to the (N-1)^t non-zero frequencies, deconvolve, write.
+// One workgroup per (term, right-hand side): the folded grid, pruned forward DFT to the
+// (N-1)^t non-zero frequencies, deconvolve, write in group order.
 template <typename T, int ORDER>
-__global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gpart, int64_t gstride,
-                                                     const int32_t *__restrict__ item_begin,
+__global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
                                                      const DevTerm *__restrict__ terms, OrderParams<T> op,
                                                      const T *__restrict__ colscale, int64_t ncoef,
                                                      cx_t<T> *__restrict__ fhat) {
@@ -545,10 +472,11 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
   const int tid = threadIdx.x, BS = blockDim.x;
-  const DevTerm tm = terms[op.term_begin + blockIdx.x];
+  const int tl = blockIdx.x;
+  const DevTerm tm = terms[op.term_begin + tl];
   const int r = blockIdx.y;
-  const int s0 = item_begin[r], s1 = item_begin[r + 1];
-  const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = op.m - 1;
+  const int nt = op.term_end - op.term_begin;
+  const int K = op.nfreq, n = op.n, h = op.N / 2;
   const T *__restrict__ W = op.roots;
   const T *__restrict__ Dc = op.deconv;
   C *dst = fhat + (int64_t)r * ncoef + tm.coef_off;
@@ -559,22 +487,10 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
     while (e >= n) e -= n;
     return e;
   };
-  // G[..][l] = sum over chunks and over halo copies p of l (p = l + m - 1 mod n, + n, ...)
   const int outer = ORDER == 1 ? 1 : (ORDER == 2 ? n : n * n);
   C *G = S;
-  for (int i = tid; i < outer * n; i += BS) {
-    const int o = i / n, l = i - o * n;
-    double re = 0, im = 0;
-    for (int s = s0; s < s1; ++s) {
-      const C *src = gpart + (int64_t)s * gstride + tm.gpart_off + (int64_t)o * P;
-      for (int p = (l + mm1) % n; p < P; p += n) {
-        const C v = src[p];
-        re += (double)v.x;
-        im += (double)v.y;
-      }
-    }
-    G[i] = cmake<T>((T)re, (T)im);
-  }
+  const C *src = gsum + ((int64_t)r * nt + tl) * outer * n;
+  for (int i = tid; i < outer * n; i += BS) G[i] = src[i];
   __syncthreads();
   // conj twiddles: e^{-2 pi i k l / n}
   if (ORDER == 1) {
@@ -942,44 +858,54 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
   using C = cx_t<T>;
   if (int rc = launch_pack<T>(pl, fhat, colscale, s)) return rc;
   const int ngi = (int)pl->gitems.size();
-  for (int t = 1; t <= pl->ds; ++t) {
-    const OrderHost &o = pl->ord[t];
-    const int nb = (int)o.blocks.size() / 2;
-    if (nb == 0 || ngi == 0) continue;
-    OrderParams<T> op = order_params<T>(pl, t);
-    const size_t lds = (size_t)o.gsize * sizeof(C);
-    dim3 grid(ngi, nb);
-    prof_begin(s, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
-#define GT_LAUNCH_GATHER(MH)                                                                                        \
-  {                                                                                                                 \
-    if (t == 1) {                                                                                                   \
-      if (int rc = set_lds(k_gather<T, 1, MH>, lds)) return rc;                                                     \
-      hipLaunchKernelGGL((k_gather<T, 1, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
-                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
-                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
-    } else if (t == 2) {                                                                                            \
-      if (int rc = set_lds(k_gather<T, 2, MH>, lds)) return rc;                                                     \
-      hipLaunchKernelGGL((k_gather<T, 2, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
-                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
-                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
-    } else {                                                                                                        \
-      if (int rc = set_lds(k_gather<T, 3, MH>, lds)) return rc;                                                     \
-      hipLaunchKernelGGL((k_gather<T, 3, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot,         \
-                         pl->d_gitems, o.d_blocks, o.block_base, pl->d_terms, op, (const C *)pl->d_grid,           \
-                         pl->grid_total, (C *)pl->d_fpart, pl->Vtot);                                              \
-    }                                                                                                               \
+  if (ngi == 0) return GT_OK;
+  // terms 1..nterms-1 in blocks of nslots; each block: gathers into slots, then one reduction
+  const int S = std::max(1, pl->nslots);
+  const int nt_all = pl->nterms - 1;
+  for (int g0 = 1, blk = 0; blk == 0 || g0 <= nt_all; g0 += S, ++blk) {
+    const int g1 = std::min(pl->nterms, g0 + S);
+    for (int t = 1; t <= pl->ds; ++t) {
+      const OrderHost &o = pl->ord[t];
+      const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
+      if (tb >= te) continue;
+      const int i0 = o.gitem_begin[tb - o.term_begin], i1 = o.gitem_begin[te - o.term_begin];
+      if (i1 <= i0) continue;
+      OrderParams<T> op = order_params<T>(pl, t);
+      const size_t lds = (size_t)o.gsize * sizeof(C);
+      const GatherItem *items = o.d_gitems + i0;
+      const int64_t vstride = pl->ragged ? 0 : pl->M;
+      dim3 grid(i1 - i0);
+      prof_begin(s, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
+#define GT_LAUNCH_GATHER(MH)                                                                                      \
+  {                                                                                                               \
+    if (t == 1) {                                                                                                 \
+      if (int rc = set_lds(k_gather_sorted<T, 1, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_gather_sorted<T, 1, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         (C *)pl->d_fpart, pl->Vtot);                                                            \
+    } else if (t == 2) {                                                                                          \
+      if (int rc = set_lds(k_gather_sorted<T, 2, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_gather_sorted<T, 2, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         (C *)pl->d_fpart, pl->Vtot);                                                            \
+    } else {                                                                                                      \
+      if (int rc = set_lds(k_gather_sorted<T, 3, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_gather_sorted<T, 3, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         (C *)pl->d_fpart, pl->Vtot);                                                            \
+    }                                                                                                             \
   }
-    GT_DISPATCH_M(o.m, GT_LAUNCH_GATHER)
+      GT_DISPATCH_M(o.m, GT_LAUNCH_GATHER)
 #undef GT_LAUNCH_GATHER
-    prof_end(s);
-    if (int rc = check_launch("k_gather")) return rc;
-  }
-  if (ngi > 0) {
+      prof_end(s);
+      if (int rc = check_launch("k_gather_sorted")) return rc;
+    }
     prof_begin(s, "reduce_f");
     hipLaunchKernelGGL((k_reduce_f<T>), dim3(ngi), dim3(kGatherBS), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
-                       (const C *)pl->d_fpart, pl->nblocks, pl->Vtot, (C *)f);
+                       (const C *)pl->d_fpart, g1 - g0, pl->Vtot, blk > 0 ? 1 : 0, (C *)f);
     prof_end(s);
     if (int rc = check_launch("k_reduce_f")) return rc;
+    if (nt_all <= 0) break;
   }
   return GT_OK;
 }
@@ -994,24 +920,30 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const int nsi = (int)o.sitems.size();
     if (nt == 0 || nsi == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
+    SpreadArgs sa;
+    sa.perm = o.d_perm;
+    sa.cstart = o.d_cstart;
+    sa.B = pl->ragged ? pl->R : 1;
+    sa.ncell = o.ncell;
+    sa.vstride = pl->ragged ? 0 : pl->M;
     const size_t lds = (size_t)o.gsize * sizeof(double2);
     dim3 grid(nsi, nt);
     prof_begin(s, t == 1 ? "spread_1d" : t == 2 ? "spread_2d" : "spread_3d");
-#define GT_LAUNCH_SPREAD(MH)                                                                                         \
-  {                                                                                                                  \
-    if (t == 1) {                                                                                                    \
-      if (int rc = set_lds(k_spread<T, 1, MH>, lds)) return rc;                                                      \
-      hipLaunchKernelGGL((k_spread<T, 1, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
-                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
-    } else if (t == 2) {                                                                                             \
-      if (int rc = set_lds(k_spread<T, 2, MH>, lds)) return rc;                                                      \
-      hipLaunchKernelGGL((k_spread<T, 2, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
-                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
-    } else {                                                                                                         \
-      if (int rc = set_lds(k_spread<T, 3, MH>, lds)) return rc;                                                      \
-      hipLaunchKernelGGL((k_spread<T, 3, MH>), grid, dim3(kSpreadBS), lds, s, (const T *)pl->d_x, pl->Mtot,          \
-                         o.d_sitems, pl->d_terms, op, (const C *)y, (C *)o.d_gpart, o.gpart_stride);                \
-    }                                                                                                                \
+#define GT_LAUNCH_SPREAD(MH)                                                                                      \
+  {                                                                                                               \
+    if (t == 1) {                                                                                                 \
+      if (int rc = set_lds(k_spread_binned<T, 1, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_spread_binned<T, 1, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
+                         o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
+    } else if (t == 2) {                                                                                          \
+      if (int rc = set_lds(k_spread_binned<T, 2, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_spread_binned<T, 2, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
+                         o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
+    } else {                                                                                                      \
+      if (int rc = set_lds(k_spread_binned<T, 3, MH>, lds)) return rc;                                            \
+      hipLaunchKernelGGL((k_spread_binned<T, 3, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
+                         o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
+    }                                                                                                             \
   }
     GT_DISPATCH_M(o.m, GT_LAUNCH_SPREAD)
 #undef GT_LAUNCH_SPREAD
@@ -1024,20 +956,29 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (nt == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     const size_t lds = adj_lds<T>(pl, t);
+    {
+      const int64_t outer = t == 1 ? 1 : (t == 2 ? o.n : (int64_t)o.n * o.n);
+      const int64_t pts = outer * o.n * nt;
+      prof_begin(s, t == 1 ? "fold_1d" : t == 2 ? "fold_2d" : "fold_3d");
+      hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, s,
+                         (const C *)o.d_gpart, o.gpart_stride, o.d_sitem_begin, pl->d_terms, op, t, (C *)o.d_gsum);
+      prof_end(s);
+      if (int rc = check_launch("k_fold_partials")) return rc;
+    }
     dim3 grid(nt, pl->R);
     prof_begin(s, t == 1 ? "dft_adj_1d" : t == 2 ? "dft_adj_2d" : "dft_adj_3d");
     if (t == 1) {
       if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
-                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+      hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+                         colscale, pl->ncoef, (C *)fhat);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
-                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+                         colscale, pl->ncoef, (C *)fhat);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gpart, o.gpart_stride,
-                         o.d_sitem_begin, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat);
+      hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+                         colscale, pl->ncoef, (C *)fhat);
     }
     prof_end(s);
     if (int rc = check_launch("k_dft_adj")) return rc;
@@ -1045,8 +986,8 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
   if (ngi > 0) {
     prof_begin(s, "empty_adj");
     hipLaunchKernelGGL((k_ysum<T>), dim3(ngi), dim3(kGatherBS), 0, s, pl->d_gitems, (const C *)y, pl->d_ysum);
-    hipLaunchKernelGGL((k_empty_adj<T>), dim3((pl->R + 63) / 64), dim3(64), 0, s, pl->d_gitem_begin, pl->d_ysum,
-                       pl->R, pl->ncoef, (C *)fhat);
+    hipLaunchKernelGGL((k_empty_adj<T>), dim3(pl->R), dim3(kGatherBS), 0, s, pl->d_gitem_begin, pl->d_ysum,
+                       pl->ncoef, (C *)fhat);
     prof_end(s);
     if (int rc = check_launch("k_empty_adj")) return rc;
   }

@@ -214,6 +214,11 @@ static void window_poly(int m, long double b, int D, std::vector<double> &out) {
     }
     for (int q = 0; q <= D; ++q) out[(size_t)j * (D + 1) + q] = (double)mono[q];
   }
+  // Phi is even: point 2m-1-j at offset fr equals point j at 1 - fr, i.e. at -z.  Mirror the
+  // coefficients so that the pair is exactly symmetric (the kernels evaluate pairs together).
+  for (int j = 0; j < m; ++j)
+    for (int q = 0; q <= D; ++q)
+      out[(size_t)(W - 1 - j) * (D + 1) + q] = (q & 1) ? -out[(size_t)j * (D + 1) + q] : out[(size_t)j * (D + 1) + q];
 }
 
 }  // namespace gt
@@ -256,10 +261,13 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_deconv, nullptr);
     dev_free(o.d_roots, nullptr);
     dev_free(o.d_poly, nullptr);
-    dev_free(o.d_blocks, nullptr);
+    dev_free(o.d_gitems, nullptr);
     dev_free(o.d_sitems, nullptr);
     dev_free(o.d_sitem_begin, nullptr);
     dev_free(o.d_gpart, nullptr);
+    dev_free(o.d_perm, nullptr);
+    dev_free(o.d_gsum, nullptr);
+    dev_free(o.d_cstart, nullptr);
   }
   delete pl;
 }
@@ -403,38 +411,66 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   add_items(pl->gitems, pl->gitem_begin, kGatherBS);
   const int64_t ngi = (int64_t)pl->gitems.size();
 
-  // ---- gather term blocks per order (enough workgroups, few partial vectors)
-  int32_t nb = 0;
+  // ---- gather work items per order: runs of sorted positions of one term and right-hand
+  //      side (the binning sorts each term's nodes by cell, dataset by dataset)
   for (int t = 1; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
-    int nt = o.term_end - o.term_begin;
-    int W = 2 * o.m;
-    int wt = t == 1 ? W : (t == 2 ? W * W : W * W * W);
-    int min_tpb = std::max(1, 64 / wt);
-    int64_t want = (2048 + ngi - 1) / ngi;
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (nt + min_tpb - 1) / min_tpb));
-    int tpb = (nt + blocks - 1) / blocks;
-    o.blocks.clear();
-    for (int a = o.term_begin; a < o.term_end; a += tpb) {
-      o.blocks.push_back(a);
-      o.blocks.push_back(std::min(o.term_end, a + tpb));
+    const int nt = o.term_end - o.term_begin;
+    const int64_t chunk = (int64_t)kGatherBS * kGatherNodes;
+    o.gitems.clear();
+    o.gitem_begin.assign(nt + 1, 0);
+    for (int tl = 0; tl < nt; ++tl) {
+      o.gitem_begin[tl] = (int32_t)o.gitems.size();
+      for (int r = 0; r < pl->R; ++r) {
+        const int64_t lo = pl->ragged ? pl->offs[r] : 0, hi = pl->ragged ? pl->offs[r + 1] : pl->M;
+        for (int64_t a = lo; a < hi; a += chunk) {
+          GatherItem gi{};
+          gi.q0 = (int64_t)tl * pl->Mtot + a;
+          gi.count = (int32_t)std::min<int64_t>(chunk, hi - a);
+          gi.tl = tl;
+          gi.r = r;
+          o.gitems.push_back(gi);
+        }
+      }
     }
-    o.block_base = nb;
-    nb += (int32_t)o.blocks.size() / 2;
+    o.gitem_begin[nt] = (int32_t)o.gitems.size();
   }
-  pl->nblocks = nb;
+  // forward output slots: one per term of a block, about 512 MiB at most
+  {
+    const int64_t per_slot = std::max<int64_t>(1, pl->Vtot * (int64_t)csz);
+    const int64_t cap = std::max<int64_t>(1, (int64_t(512) << 20) / per_slot);
+    pl->nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap, std::max(1, pl->nterms - 1)));
+  }
 
-  // ---- spread work items per order
+  // ---- spread work items per order: ranges of cells per right-hand side, enough
+  //      single-wave workgroups, partial-grid memory bounded to about 1 GiB
   for (int t = 1; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
-    int nt = o.term_end - o.term_begin;
-    int64_t chunk = std::max<int64_t>(2048, (pl->Vtot * nt + 2047) / 2048);
-    // bound the partial-grid memory to about 1 GiB
-    int64_t per_item = (int64_t)nt * o.gsize * (int64_t)csz;
-    int64_t max_items = std::max<int64_t>(pl->R, (int64_t(1) << 30) / std::max<int64_t>(1, per_item));
-    int64_t items_est = (pl->Vtot + chunk - 1) / chunk + pl->R;
-    if (items_est > max_items) chunk = std::max<int64_t>(chunk, (pl->Vtot + max_items - 1) / std::max<int64_t>(1, max_items - pl->R));
-    add_items(o.sitems, o.sitem_begin, chunk);
+    const int64_t nt = o.term_end - o.term_begin;
+    int64_t ncell = 1;
+    for (int k = 0; k < t; ++k) ncell *= o.n;
+    o.ncell = ncell;
+    // about 8192 wavefronts in total, at least one cell per wavefront of a workgroup
+    const int64_t pairs = std::max<int64_t>(1, nt * pl->R);
+    const int64_t want = std::max<int64_t>(1, (8192 / kSpreadWaves + pairs - 1) / pairs);
+    const int64_t per_item = std::max<int64_t>(1, nt * o.gsize * (int64_t)csz);
+    const int64_t mem_items = std::max<int64_t>(1, ((int64_t(1) << 30) / per_item) / pl->R);
+    const int64_t cell_cap = std::max<int64_t>(1, ncell / kSpreadWaves);
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(cell_cap, mem_items)));
+    o.sitems.clear();
+    o.sitem_begin.assign(pl->R + 1, 0);
+    for (int r = 0; r < pl->R; ++r) {
+      o.sitem_begin[r] = (int32_t)o.sitems.size();
+      for (int64_t ch = 0; ch < chunks; ++ch) {
+        SpreadItem si{};
+        si.r = r;
+        si.b = pl->ragged ? r : 0;
+        si.c0 = (int32_t)(ncell * ch / chunks);
+        si.c1 = (int32_t)(ncell * (ch + 1) / chunks);
+        if (si.c1 > si.c0) o.sitems.push_back(si);
+      }
+    }
+    o.sitem_begin[pl->R] = (int32_t)o.sitems.size();
     o.gpart_stride = 0;
     for (int i = o.term_begin; i < o.term_end; ++i) {
       pl->terms[i].gpart_off = o.gpart_stride;
@@ -447,7 +483,7 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   if ((rc = upload_raw(pl->terms, &pl->d_terms)) || (rc = dev_alloc(&pl->d_x, (size_t)nx * pl->rsize, s)) ||
       (rc = dev_alloc(&pl->d_grid, (size_t)pl->R * pl->grid_total * csz, s)) ||
       (rc = upload_raw(pl->gitems, &pl->d_gitems)) || (rc = upload_raw(pl->gitem_begin, &pl->d_gitem_begin)) ||
-      (rc = dev_alloc(&pl->d_fpart, (size_t)std::max(1, pl->nblocks) * pl->Vtot * csz, s)) ||
+      (rc = dev_alloc(&pl->d_fpart, (size_t)std::max(1, pl->nslots) * pl->Vtot * csz, s)) ||
       (rc = dev_alloc((void **)&pl->d_ysum, (size_t)ngi * 2 * sizeof(double), s)) ||
       (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s))) {
     free_plan(pl);
@@ -455,9 +491,10 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   }
   for (int t = 1; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
-    if ((rc = upload_raw(o.blocks, &o.d_blocks)) || (rc = upload_raw(o.sitems, &o.d_sitems)) ||
+    if ((rc = upload_raw(o.gitems, &o.d_gitems)) || (rc = upload_raw(o.sitems, &o.d_sitems)) ||
         (rc = upload_raw(o.sitem_begin, &o.d_sitem_begin)) ||
-        (rc = dev_alloc(&o.d_gpart, (size_t)o.sitems.size() * o.gpart_stride * csz, s))) {
+        (rc = dev_alloc(&o.d_gpart, (size_t)o.sitems.size() * o.gpart_stride * csz, s)) ||
+        (rc = dev_alloc(&o.d_gsum, (size_t)pl->R * (o.term_end - o.term_begin) * (size_t)o.ncell * csz, s))) {
       free_plan(pl);
       return rc;
     }
@@ -479,6 +516,16 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   if (flag) {
     free_plan(pl);
     return fail(GT_EINVAL, "nodes contain NaN or Inf");
+  }
+  // ---- node binning for the spread (per term, by cell)
+  rc = p->dtype == GT_C64 ? launch_binning<float>(pl, s) : launch_binning<double>(pl, s);
+  if (rc == GT_OK) {
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess) rc = hip_fail(e2, "node binning");
+  }
+  if (rc) {
+    free_plan(pl);
+    return rc;
   }
   *out = pl;
   return GT_OK;
