@@ -143,6 +143,11 @@ __global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T 
 
 static __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
+static __global__ void k_zero_n(int32_t *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 // ------------------------------------------------------------------ K1 + K2 forward
 // One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
 // (N-1)^t non-zero frequencies onto the n^t grid, written in the halo layout.
@@ -160,7 +165,13 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
   C *dst = grids + (int64_t)r * grid_total + tm.grid_off;
   const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = op.m - 1;
-  const T *__restrict__ W = op.roots;
+  // roots of unity staged in LDS after the DFT stages (first read after the first barrier)
+  const size_t stage = sizeof(C) * (ORDER == 1 ? (size_t)K
+                                   : ORDER == 2 ? (size_t)K * K + (size_t)K * n
+                                                : (size_t)K * K * K + (size_t)K * K * n + (size_t)K * n * n);
+  T *Wl = reinterpret_cast<T *>(smem_raw + stage);
+  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
+  const T *W = Wl;
   const T *__restrict__ Dc = op.deconv;
   // exponent index (k_a * l) mod n for a = 0..K-1 stepping incrementally
   auto phase0 = [&](int l) { return (int)(((int64_t)(n - h) * l) % n); };   // k = -h
@@ -368,23 +379,36 @@ __device__ __forceinline__ cx_t<T> gather_term(const cx_t<T> *__restrict__ G, co
   return cmake<T>(re, im);
 }
 
-// f_v = (accumulate ? f_v : fhat_empty(r)) + sum over the term slots, in slot order.
+// f_v = (accumulate ? f_v : fhat_empty(r)) + sum over the term slots.  Workgroup = 64 nodes
+// x 4 parts; part p sums slots p, p+4, ...; the parts are combined in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_reduce_f(const cx_t<T> *__restrict__ fhat, int64_t ncoef,
-                                                        const WorkItem *__restrict__ items,
-                                                        const cx_t<T> *__restrict__ slots, int nslots, int64_t Vtot,
-                                                        int accumulate, cx_t<T> *__restrict__ f) {
-  const WorkItem it = items[blockIdx.x];
-  const int tid = threadIdx.x;
-  if (tid >= it.count) return;
-  const int64_t v = it.v0 + tid;
-  cx_t<T> acc = accumulate ? f[v] : fhat[(int64_t)it.r * ncoef];
-  for (int b = 0; b < nslots; ++b) {
-    const cx_t<T> p = slots[(int64_t)b * Vtot + v];
-    acc.x += p.x;
-    acc.y += p.y;
+__global__ __launch_bounds__(256) void k_reduce_f(const cx_t<T> *__restrict__ fhat, int64_t ncoef,
+                                                  const WorkItem *__restrict__ items,
+                                                  const cx_t<T> *__restrict__ slots, int nslots, int64_t Vtot,
+                                                  int accumulate, cx_t<T> *__restrict__ f) {
+  __shared__ cx_t<T> part[4][64];
+  const WorkItem it = items[blockIdx.x >> 2];
+  const int node = ((blockIdx.x & 3) << 6) + (threadIdx.x & 63), p = threadIdx.x >> 6;
+  const bool active = node < it.count;
+  const int64_t v = it.v0 + node;
+  T re = 0, im = 0;
+  if (active)
+    for (int b = p; b < nslots; b += 4) {
+      const cx_t<T> q = slots[(int64_t)b * Vtot + v];
+      re += q.x;
+      im += q.y;
+    }
+  part[p][threadIdx.x & 63] = cmake<T>(re, im);
+  __syncthreads();
+  if (p == 0 && active) {
+    cx_t<T> acc = accumulate ? f[v] : fhat[(int64_t)it.r * ncoef];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc.x += part[q][threadIdx.x].x;
+      acc.y += part[q][threadIdx.x].y;
+    }
+    f[v] = acc;
   }
-  f[v] = acc;
 }
 
 }  // namespace gt
@@ -392,11 +416,17 @@ __global__ __launch_bounds__(kGatherBS) void k_reduce_f(const cx_t<T> *__restric
 #include "spread.h"   // K4 spread (binned, MFMA)
 namespace gt {
 
-// Partial sums of y over each gather item (for the empty-set coefficient).
+// Empty-set coefficient fhat_empty(r) = sum_v y_v.  Each workgroup sums one gather item
+// (FP64) into ysum; the last workgroup of right-hand side r to finish (counter per r)
+// adds that side's partials in item order, writes the coefficient and resets the counter.
 template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_ysum(const WorkItem *__restrict__ items, const cx_t<T> *__restrict__ y,
-                                                    double *__restrict__ ysum) {
+__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const WorkItem *__restrict__ items,
+                                                         const int32_t *__restrict__ item_begin,
+                                                         const cx_t<T> *__restrict__ y, double *__restrict__ ysum,
+                                                         int32_t *__restrict__ counters, int64_t ncoef,
+                                                         cx_t<T> *__restrict__ fhat) {
   __shared__ double sh[2 * (kGatherBS / 64)];
+  __shared__ int last;
   const WorkItem it = items[blockIdx.x];
   double a = 0, b = 0;
   if ((int)threadIdx.x < it.count) {
@@ -408,56 +438,69 @@ __global__ __launch_bounds__(kGatherBS) void k_ysum(const WorkItem *__restrict__
   if (threadIdx.x == 0) {
     ysum[2 * blockIdx.x] = a;
     ysum[2 * blockIdx.x + 1] = b;
+    __threadfence();
+    const int nitems = item_begin[it.r + 1] - item_begin[it.r];
+    last = atomicAdd(&counters[it.r], 1) == nitems - 1;
   }
-}
-
-// One workgroup per right-hand side: fhat_empty(r) = sum of the item partial sums of r.
-template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restrict__ item_begin,
-                                                         const double *__restrict__ ysum, int64_t ncoef,
-                                                         cx_t<T> *__restrict__ fhat) {
-  __shared__ double sh[2 * (kGatherBS / 64)];
-  const int r = blockIdx.x;
-  double a = 0, b = 0;
-  for (int i = item_begin[r] + threadIdx.x; i < item_begin[r + 1]; i += kGatherBS) {
-    a += ysum[2 * i];
-    b += ysum[2 * i + 1];
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  a = 0;
+  b = 0;
+  for (int i = item_begin[it.r] + threadIdx.x; i < item_begin[it.r + 1]; i += kGatherBS) {
+    a += __hip_atomic_load(&ysum[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b += __hip_atomic_load(&ysum[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   block_sum2(a, b, sh);
-  if (threadIdx.x == 0) fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
+  if (threadIdx.x == 0) {
+    fhat[(int64_t)it.r * ncoef] = cmake<T>((T)a, (T)b);
+    counters[it.r] = 0;
+  }
 }
 
 // ------------------------------------------------------------------ fold of the spread partials
-// One thread per unpadded grid point l of (right-hand side, term): sum over the spread items
+// One output per unpadded grid point l of (right-hand side, term): sum over the spread items
 // of that right-hand side and over the halo copies p of l (p = l + m - 1 mod n, + n, ...),
-// in FP64.  gsum layout: [r][term_local][outer][n] with outer = n^(order-1).
+// in FP64.  Workgroup = 64 points x 4 parts (part q takes items q, q+4, ...), combined in a
+// fixed order.  gsum layout: [r][term_local][outer][n] with outer = n^(order-1).
 template <typename T>
 __global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict__ gpart, int64_t gstride,
                                                        const int32_t *__restrict__ item_begin,
                                                        const DevTerm *__restrict__ terms, OrderParams<T> op,
                                                        int order, cx_t<T> *__restrict__ gsum) {
+  __shared__ double part[4][64][2];
   const int n = op.n, P = op.P, mm1 = op.m - 1;
   const int nt = op.term_end - op.term_begin;
   const int64_t outer = order == 1 ? 1 : (order == 2 ? n : (int64_t)n * n);
   const int64_t per_term = outer * n;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= per_term * nt) return;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  const bool active = idx < per_term * nt;
   const int r = blockIdx.y;
-  const int tl = (int)(idx / per_term);
+  const int tl = active ? (int)(idx / per_term) : 0;
   const int64_t rem = idx - (int64_t)tl * per_term;
   const int64_t o = rem / n;
   const int l = (int)(rem - o * n);
-  const DevTerm tm = terms[op.term_begin + tl];
   double re = 0, im = 0;
-  for (int s = item_begin[r]; s < item_begin[r + 1]; ++s) {
-    const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
-    for (int p = (l + mm1) % n; p < P; p += n) {
-      const cx_t<T> v = src[p];
-      re += (double)v.x;
-      im += (double)v.y;
+  if (active) {
+    const DevTerm tm = terms[op.term_begin + tl];
+    for (int s = item_begin[r] + q; s < item_begin[r + 1]; s += 4) {
+      const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
+      for (int p = (l + mm1) % n; p < P; p += n) {
+        const cx_t<T> v = src[p];
+        re += (double)v.x;
+        im += (double)v.y;
+      }
     }
   }
-  gsum[((int64_t)r * nt + tl) * per_term + rem] = cmake<T>((T)re, (T)im);
+  part[q][threadIdx.x & 63][0] = re;
+  part[q][threadIdx.x & 63][1] = im;
+  __syncthreads();
+  if (q == 0 && active) {
+    re = part[0][threadIdx.x][0] + part[1][threadIdx.x][0] + part[2][threadIdx.x][0] + part[3][threadIdx.x][0];
+    im = part[0][threadIdx.x][1] + part[1][threadIdx.x][1] + part[2][threadIdx.x][1] + part[3][threadIdx.x][1];
+    gsum[((int64_t)r * nt + tl) * per_term + rem] = cmake<T>((T)re, (T)im);
+  }
 }
 
 // ------------------------------------------------------------------ K2 + K5 adjoint
@@ -477,7 +520,13 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
   const int r = blockIdx.y;
   const int nt = op.term_end - op.term_begin;
   const int K = op.nfreq, n = op.n, h = op.N / 2;
-  const T *__restrict__ W = op.roots;
+  // roots of unity staged in LDS after the DFT stages (first read after the first barrier)
+  const size_t stage = sizeof(C) * (ORDER == 1 ? (size_t)n
+                                   : ORDER == 2 ? (size_t)n * n + (size_t)n * K
+                                                : (size_t)n * n * n + (size_t)n * n * K);
+  T *Wl = reinterpret_cast<T *>(smem_raw + stage);
+  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
+  const T *W = Wl;
   const T *__restrict__ Dc = op.deconv;
   C *dst = fhat + (int64_t)r * ncoef + tm.coef_off;
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
@@ -812,7 +861,7 @@ static size_t pack_lds(const gt_plan *pl, int t) {
   const OrderHost &o = pl->ord[t];
   const size_t K = o.N - 1, n = o.n;
   const size_t c = sizeof(cx_t<T>);
-  return c * (t == 1 ? K : t == 2 ? K * K + K * n : K * K * K + K * K * n + K * n * n);
+  return c * (t == 1 ? K : t == 2 ? K * K + K * n : K * K * K + K * K * n + K * n * n) + 2 * n * sizeof(T);
 }
 
 template <typename T>
@@ -820,7 +869,7 @@ static size_t adj_lds(const gt_plan *pl, int t) {
   const OrderHost &o = pl->ord[t];
   const size_t K = o.N - 1, n = o.n;
   const size_t c = sizeof(cx_t<T>);
-  return c * (t == 1 ? n : t == 2 ? n * n + n * K : n * n * n + n * n * K);
+  return c * (t == 1 ? n : t == 2 ? n * n + n * K : n * n * n + n * n * K) + 2 * n * sizeof(T);
 }
 
 template <typename T>
@@ -901,7 +950,7 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
       if (int rc = check_launch("k_gather_sorted")) return rc;
     }
     prof_begin(s, "reduce_f");
-    hipLaunchKernelGGL((k_reduce_f<T>), dim3(ngi), dim3(kGatherBS), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
+    hipLaunchKernelGGL((k_reduce_f<T>), dim3(4 * ngi), dim3(256), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
                        (const C *)pl->d_fpart, g1 - g0, pl->Vtot, blk > 0 ? 1 : 0, (C *)f);
     prof_end(s);
     if (int rc = check_launch("k_reduce_f")) return rc;
@@ -960,7 +1009,7 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
       const int64_t outer = t == 1 ? 1 : (t == 2 ? o.n : (int64_t)o.n * o.n);
       const int64_t pts = outer * o.n * nt;
       prof_begin(s, t == 1 ? "fold_1d" : t == 2 ? "fold_2d" : "fold_3d");
-      hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 63) / 64), pl->R), dim3(256), 0, s,
                          (const C *)o.d_gpart, o.gpart_stride, o.d_sitem_begin, pl->d_terms, op, t, (C *)o.d_gsum);
       prof_end(s);
       if (int rc = check_launch("k_fold_partials")) return rc;
@@ -985,9 +1034,8 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
   }
   if (ngi > 0) {
     prof_begin(s, "empty_adj");
-    hipLaunchKernelGGL((k_ysum<T>), dim3(ngi), dim3(kGatherBS), 0, s, pl->d_gitems, (const C *)y, pl->d_ysum);
-    hipLaunchKernelGGL((k_empty_adj<T>), dim3(pl->R), dim3(kGatherBS), 0, s, pl->d_gitem_begin, pl->d_ysum,
-                       pl->ncoef, (C *)fhat);
+    hipLaunchKernelGGL((k_empty_adj<T>), dim3(ngi), dim3(kGatherBS), 0, s, pl->d_gitems, pl->d_gitem_begin,
+                       (const C *)y, pl->d_ysum, pl->d_ycount, pl->ncoef, (C *)fhat);
     prof_end(s);
     if (int rc = check_launch("k_empty_adj")) return rc;
   }
@@ -1065,6 +1113,7 @@ template <typename T>
 int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s) {
   const int64_t total = pl->Mtot * pl->d;
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pl->d_flag);
+  hipLaunchKernelGGL((k_zero_n), dim3((pl->R + 255) / 256), dim3(256), 0, s, pl->d_ycount, pl->R);
   if (total > 0)
     hipLaunchKernelGGL((k_prepare_nodes<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)x,
                        pl->Mtot, pl->d, (T *)pl->d_x, pl->d_flag);

@@ -256,6 +256,7 @@ void free_plan(gt_plan *pl) {
   dev_free(pl->d_fpart, nullptr);
   dev_free(pl->d_ysum, nullptr);
   dev_free(pl->d_flag, nullptr);
+  dev_free(pl->d_ycount, nullptr);
   dev_free(pl->d_gxp, nullptr);
   for (auto &o : pl->ord) {
     dev_free(o.d_deconv, nullptr);
@@ -360,6 +361,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
                                                          : (size_t)K * K * K + (size_t)K * K * o.n + (size_t)K * o.n * o.n);
     size_t lds_adj = (size_t)csz * (t == 1 ? o.n : t == 2 ? (size_t)o.n * o.n + (size_t)o.n * K
                                                          : (size_t)o.n * o.n * o.n + (size_t)o.n * o.n * K + (size_t)o.n * K * K);
+    lds_pack += 2 * (size_t)o.n * pl->rsize;   // roots of unity staged in LDS
+    lds_adj += 2 * (size_t)o.n * pl->rsize;
     size_t need = std::max(lds_gather, std::max(lds_pack, lds_adj));
     if (need > pl->lds_limit) {
       free_plan(pl);
@@ -402,6 +405,14 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
         w.v0 = vbase + a;
         w.x0 = a;
         w.count = (int32_t)std::min<int64_t>(chunk, hi - a);
+        w.r = r;
+        items.push_back(w);
+      }
+      if (hi == lo) {   // an empty dataset keeps one empty item: its per-side results are still written
+        WorkItem w{};
+        w.v0 = vbase + lo;
+        w.x0 = lo;
+        w.count = 0;
         w.r = r;
         items.push_back(w);
       }
@@ -485,7 +496,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
       (rc = upload_raw(pl->gitems, &pl->d_gitems)) || (rc = upload_raw(pl->gitem_begin, &pl->d_gitem_begin)) ||
       (rc = dev_alloc(&pl->d_fpart, (size_t)std::max(1, pl->nslots) * pl->Vtot * csz, s)) ||
       (rc = dev_alloc((void **)&pl->d_ysum, (size_t)ngi * 2 * sizeof(double), s)) ||
-      (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s))) {
+      (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s)) ||
+      (rc = dev_alloc((void **)&pl->d_ycount, (size_t)pl->R * sizeof(int32_t), s))) {
     free_plan(pl);
     return rc;
   }
