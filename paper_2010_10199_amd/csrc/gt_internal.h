@@ -59,6 +59,15 @@ struct GatherItem {    // a run of sorted positions of one term and right-hand s
   int32_t pad;
 };
 
+struct GraphEntry {    // a captured launch sequence of one plan call, keyed by its buffers
+  int kind = 0;        // 1 = forward, 2 = adjoint
+  const void *in = nullptr;
+  const void *out = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct SpreadItem {    // a range of grid cells of one right-hand side (dataset b of the binning)
   int32_t r, b, c0, c1;
 };
@@ -131,6 +140,7 @@ struct gt_plan {
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
   hipStream_t stream = nullptr;
   size_t lds_limit = 65536;
+  std::vector<gt::GraphEntry> graphs; // forward / adjoint launch sequences replayed as HIP graphs
 };
 
 namespace gt {
@@ -146,6 +156,7 @@ int hip_fail(hipError_t e, const char *what);
   } while (0)
 
 // ---- profiling of launches ----
+bool prof_enabled();
 void prof_begin(hipStream_t s, const char *name);
 void prof_end(hipStream_t s);
 

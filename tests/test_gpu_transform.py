@@ -168,3 +168,38 @@ def test_invalid_arguments_are_rejected():
         with pytest.raises(lib.GroupedError) as e:
             lib.grouped_trafo(p, x, fh, f)
         assert e.value.code in (lib.GT_EINVAL, lib.GT_EUNSUPPORTED)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_graph_replay_matches_oracle(prec):
+    """A plan replays its forward and adjoint launch sequences as HIP graphs from the second
+    call on (non-default stream, same buffers).  Change the inputs between calls with
+    ordinary torch work and check every call, eager, captured and replayed, against the
+    oracle."""
+    import torch
+    from paper_2010_10199_amd import lib
+    from tests.gpu_util import cdtype, dtype_code, to_dev
+    d, ds, N, M = 5, 2, (16, 8), 3000
+    iset = oidx.grouped_index_set(d, ds, N)
+    x, fhat, y = W.trafo_inputs(160, d, ds, M, iset.n_coeffs, 1, prec)
+    tol = TOL[prec]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=dtype_code(prec))
+        plan = lib.Plan(p, to_dev(x))
+        fd = to_dev(fhat.reshape(-1)).clone()
+        yd = to_dev(y.reshape(-1)).clone()
+        fo = torch.empty(M, dtype=cdtype(prec), device="cuda")
+        ao = torch.empty(iset.n_coeffs, dtype=cdtype(prec), device="cuda")
+        for call in range(5):
+            scale = 1.0 + 0.5 * call
+            fd.copy_(to_dev(fhat.reshape(-1)) * scale)       # eager work on the stream between replays
+            yd.copy_(to_dev(y.reshape(-1)) * (2.0 - 0.25 * call))
+            plan.trafo(fd, fo)
+            plan.adjoint(yd, ao)
+            s.synchronize()
+            e1 = rel(fo.cpu().numpy(), otr.forward(iset, x, fhat[0] * scale))
+            e2 = rel(ao.cpu().numpy(), otr.adjoint(iset, x, y.reshape(-1) * (2.0 - 0.25 * call)))
+            say(f"[graph] {prec} call {call}: forward {e1:.2e} adjoint {e2:.2e}")
+            assert e1 <= tol and e2 <= tol
+        plan.close()
