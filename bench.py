@@ -40,7 +40,7 @@ def flops_per_node_term(order: int, m: int) -> int:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels_impl.h", "gt_internal.h"):
+    for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h"):
         with open(os.path.join(ROOT, "paper_2010_10199_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=20000, help="nodes for the oracle baseline (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -133,6 +135,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)          # reads and writes 256 MiB each
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] fp32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     r32 = run_gpu("f32", args.steps, args.warmup, profile=True)
     node_terms = 2 * M * r32["nterms"]
@@ -169,7 +178,7 @@ def main():
         if os.path.exists(tf):
             with open(tf) as fh:
                 tj = json.load(fh)
-            ent = tj.get(name)
+            ent = tj.get("kernels", {}).get(name)
             if ent and ent.get("kernel_hash") == kernel_hash():
                 traffic = ent.get("bytes_per_launch")
         out["roofline"] = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
