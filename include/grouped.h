@@ -105,7 +105,8 @@ int64_t gt_num_coeffs(int32_t d, int32_t ds, const int32_t *N);
 int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets);
 
 /* ------------------------------------------------------------------ one-shot transforms
- * Each call builds a plan for (p, x), runs, and releases it in stream order.
+ * Each call builds a plan for (p, x), runs it on `stream`, synchronises `stream` and
+ * releases the plan before returning (so these calls are synchronous).
  *
  * grouped_trafo   (Definition def:skatoons via eq. somafm):  f = F fhat.
  *   x    device, real, Mtot x d row-major (Mtot = M, or offsets[R] when ragged)
