@@ -32,11 +32,18 @@ constexpr int kMaxM = 8;
 constexpr int kGatherBS = 256;    // threads per gather workgroup
 constexpr int kGatherNodes = 4;   // sorted nodes per gather thread
 constexpr int kSpreadWaves = 8;   // wavefronts per spread workgroup
+constexpr int kTileBatch = 32;    // nodes per batch of the order-2 tile spread
+constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 tile spread
+constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
+
+// Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
+// patch (TS + 2m - 1 = 16).
+constexpr int tile_side(int m) { return 17 - 2 * m; }
 constexpr int kPackBS = 256;
 constexpr int kVecBS = 256;
 
 template <typename T> struct Deg;                   // window polynomial degree per precision
-template <> struct Deg<float> { static constexpr int value = 8; };
+template <> struct Deg<float> { static constexpr int value = 7; };
 template <> struct Deg<double> { static constexpr int value = 14; };
 
 template <typename T> struct Cx;
@@ -99,8 +106,20 @@ struct OrderHost {
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
   // node binning of this order (per term, by cell) and spread work items
   int64_t ncell = 0;                  // n^order
+  int32_t ts = 1;                     // cells per tile side of the binning order (order 2: tile_side(m))
+  int32_t ntile = 0;                  // tiles per axis, ceil(n / ts)
+  int64_t nkey = 0;                   // binning keys per (term, dataset): ntile^order * ts^order
+  int32_t spread_waves = kSpreadWaves;
   int32_t *d_perm = nullptr;          // terms x Mtot sorted node indices
-  int64_t *d_cstart = nullptr;        // (terms x datasets x ncell) + 1 start positions
+  void *d_xs = nullptr;               // order 2: terms x Mtot x 2 coordinates of the term's axes, sorted order
+  // order 2 tile spread: wavefront work list and tile patches (built after the binning)
+  int32_t nwaves2 = 0;                // wavefronts (per right-hand side when nodes are shared)
+  int64_t nseg2 = 0;                  // (wavefront, tile) segments = patches per right-hand side
+  int32_t *d_waves2 = nullptr;        // nwaves2 x 4: first position, end position, first segment, dataset
+  int32_t *d_tileseg = nullptr;       // (terms x datasets x ntile^2) + 1: first segment of each tile
+  void *d_patch = nullptr;            // (R or 1) x nseg2 x 16 x 16 complex
+  void *d_tsum = nullptr;             // R x terms x ntile^2 x 16 x 16 complex: patches summed per tile
+  int64_t *d_cstart = nullptr;        // (terms x datasets x nkey) + 1 start positions
   std::vector<SpreadItem> sitems;
   SpreadItem *d_sitems = nullptr;
   std::vector<int32_t> sitem_begin;   // per right-hand side, R+1
@@ -139,7 +158,9 @@ struct gt_plan {
   int32_t *d_flag = nullptr;          // node validation flag
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
   hipStream_t stream = nullptr;
-  size_t lds_limit = 65536;
+  size_t lds_limit = 65536;           // LDS per workgroup
+  size_t lds_per_cu = 65536;          // LDS per compute unit
+  int num_cu = 256;                   // compute units of the device
   std::vector<gt::GraphEntry> graphs; // forward / adjoint launch sequences replayed as HIP graphs
 };
 

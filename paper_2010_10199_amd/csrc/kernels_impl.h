@@ -959,6 +959,18 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
   return GT_OK;
 }
 
+static Tile2Args tile2_args(const gt_plan *pl) {
+  const OrderHost &o = pl->ord[2];
+  Tile2Args ta;
+  ta.waves = o.d_waves2;
+  ta.nwaves = o.nwaves2;
+  ta.ntile = o.ntile;
+  ta.nseg = o.nseg2;
+  ta.vstride = pl->ragged ? 0 : pl->M;
+  ta.ragged = pl->ragged ? 1 : 0;
+  return ta;
+}
+
 template <typename T>
 int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
   using C = cx_t<T>;
@@ -967,13 +979,13 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     const int nsi = (int)o.sitems.size();
-    if (nt == 0 || nsi == 0) continue;
+    if (nt == 0 || (t == 2 ? o.nwaves2 == 0 : nsi == 0)) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     SpreadArgs sa;
     sa.perm = o.d_perm;
     sa.cstart = o.d_cstart;
     sa.B = pl->ragged ? pl->R : 1;
-    sa.ncell = o.ncell;
+    sa.ncell = o.nkey;
     sa.vstride = pl->ragged ? 0 : pl->M;
     const size_t lds = (size_t)o.gsize * sizeof(double2);
     dim3 grid(nsi, nt);
@@ -984,17 +996,27 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
       if (int rc = set_lds(k_spread_binned<T, 1, MH>, lds)) return rc;                                            \
       hipLaunchKernelGGL((k_spread_binned<T, 1, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
-    } else if (t == 2) {                                                                                          \
-      if (int rc = set_lds(k_spread_binned<T, 2, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_spread_binned<T, 2, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
-                         o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     } else {                                                                                                      \
       if (int rc = set_lds(k_spread_binned<T, 3, MH>, lds)) return rc;                                            \
       hipLaunchKernelGGL((k_spread_binned<T, 3, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     }                                                                                                             \
   }
-    GT_DISPATCH_M(o.m, GT_LAUNCH_SPREAD)
+    const Tile2Args ta = tile2_args(pl);
+#define GT_LAUNCH_TILE2(MH)                                                                                       \
+  {                                                                                                               \
+    const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T));                    \
+    if (int rc = set_lds(k_spread_tile2<T, MH>, lds2)) return rc;                                                 \
+    hipLaunchKernelGGL((k_spread_tile2<T, MH>), dim3((unsigned)((o.nwaves2 + kTileWaves - 1) / kTileWaves),     \
+                       (unsigned)(pl->ragged ? 1 : pl->R)), dim3(64 * kTileWaves), lds2, s, (const T *)o.d_xs,      \
+                       (const int32_t *)o.d_perm, op, ta, (const C *)y, (C *)o.d_patch);                           \
+  }
+    if (t == 2) {
+      GT_DISPATCH_M(o.m, GT_LAUNCH_TILE2)
+    } else {
+      GT_DISPATCH_M(o.m, GT_LAUNCH_SPREAD)
+    }
+#undef GT_LAUNCH_TILE2
 #undef GT_LAUNCH_SPREAD
     prof_end(s);
     if (int rc = check_launch("k_spread")) return rc;
@@ -1005,10 +1027,22 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (nt == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     const size_t lds = adj_lds<T>(pl, t);
-    {
-      const int64_t outer = t == 1 ? 1 : (t == 2 ? o.n : (int64_t)o.n * o.n);
+    if (t == 2) {
+      prof_begin(s, "fold_2d");
+      const int ntiles = o.ntile * o.ntile;
+      const int64_t nsum = (int64_t)nt * ntiles * 256;
+      hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)((nsum + 255) / 256), pl->R), dim3(256), 0, s,
+                         (const C *)o.d_patch, o.d_tileseg, tile2_args(pl), nt, pl->ragged ? pl->R : 1,
+                         (C *)o.d_tsum);
+      const int64_t pts = (int64_t)nt * o.n * o.n;
+      hipLaunchKernelGGL((k_fold_tiles<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, s,
+                         (const C *)o.d_tsum, op, o.ntile, o.ts, (C *)o.d_gsum);
+      prof_end(s);
+      if (int rc = check_launch("k_fold_tiles")) return rc;
+    } else {
+      const int64_t outer = t == 1 ? 1 : (int64_t)o.n * o.n;
       const int64_t pts = outer * o.n * nt;
-      prof_begin(s, t == 1 ? "fold_1d" : t == 2 ? "fold_2d" : "fold_3d");
+      prof_begin(s, t == 1 ? "fold_1d" : "fold_3d");
       hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 63) / 64), pl->R), dim3(256), 0, s,
                          (const C *)o.d_gpart, o.gpart_stride, o.d_sitem_begin, pl->d_terms, op, t, (C *)o.d_gsum);
       prof_end(s);

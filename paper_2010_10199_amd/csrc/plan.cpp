@@ -277,6 +277,11 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_perm, nullptr);
     dev_free(o.d_gsum, nullptr);
     dev_free(o.d_cstart, nullptr);
+    dev_free(o.d_xs, nullptr);
+    dev_free(o.d_waves2, nullptr);
+    dev_free(o.d_tileseg, nullptr);
+    dev_free(o.d_patch, nullptr);
+    dev_free(o.d_tsum, nullptr);
   }
   delete pl;
 }
@@ -328,6 +333,74 @@ int run_cached(gt_plan *pl, int kind, const void *in, const void *out, hipStream
   return GT_OK;
 }
 
+// Work list of the order-2 tile spread (needs the binning's tile boundaries on the host).
+// Each (term, dataset) gets ceil(nodes / target) wavefronts over equal runs of its sorted
+// positions, sized so that all wavefronts of all right-hand sides fit in one resident round
+// (at least 256 nodes each).  A wavefront writes one 16 x 16 patch per tile it meets, in
+// tile order, so its segments are numbered consecutively from its first segment; the
+// segments of one tile are consecutive too (waves follow the sorted order), which gives the
+// fold its per-tile segment ranges.
+static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
+  OrderHost &o = pl->ord[2];
+  const int nt = o.term_end - o.term_begin;
+  if (nt == 0) return GT_OK;
+  const int B = pl->ragged ? pl->R : 1;
+  const int TS = o.ts, TT = TS * TS;
+  const int64_t ntiles = (int64_t)o.ntile * o.ntile;
+  const int64_t nkeys = (int64_t)nt * B * o.nkey + 1;
+  std::vector<int64_t> cs(nkeys);
+  hipError_t e = hipMemcpyAsync(cs.data(), o.d_cstart, nkeys * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "tile boundaries");
+  const int64_t total = (int64_t)nt * pl->Mtot;
+  const int reff = pl->ragged ? 1 : pl->R;
+  const int64_t want_waves = std::max<int64_t>(1, (int64_t)pl->num_cu * 20 / reff);
+  const int64_t target = std::max<int64_t>(256, (total + want_waves - 1) / want_waves);
+  std::vector<int32_t> waves;
+  std::vector<int32_t> tileseg((size_t)nt * B * ntiles + 1, 0);
+  int64_t nseg = 0;
+  for (int tl = 0; tl < nt; ++tl) {
+    for (int b = 0; b < B; ++b) {
+      const int64_t key0 = ((int64_t)tl * B + b) * o.nkey;
+      const int64_t tb0 = ((int64_t)tl * B + b) * ntiles;
+      const int64_t P0 = cs[key0], P1 = cs[key0 + ntiles * TT];
+      const int64_t Mb = P1 - P0;
+      const int64_t nw = Mb > 0 ? (Mb + target - 1) / target : 0;
+      std::vector<int32_t> tfirst(ntiles, -1);
+      int64_t tile = 0;
+      for (int64_t w = 0; w < nw; ++w) {
+        const int64_t qa = P0 + Mb * w / nw, qb = P0 + Mb * (w + 1) / nw;
+        waves.push_back((int32_t)qa);
+        waves.push_back((int32_t)qb);
+        waves.push_back((int32_t)nseg);
+        waves.push_back(b);
+        while (tile < ntiles && cs[key0 + (tile + 1) * TT] <= qa) ++tile;   // first tile ending after qa
+        for (int64_t t = tile; t < ntiles && cs[key0 + t * TT] < qb; ++t) {
+          if (cs[key0 + (t + 1) * TT] <= cs[key0 + t * TT]) continue;        // empty tile
+          if (tfirst[t] < 0) tfirst[t] = (int32_t)nseg;
+          ++nseg;
+        }
+      }
+      // per-tile first segment (a tile without nodes gets an empty range)
+      int32_t next = (int32_t)nseg;
+      for (int64_t t = ntiles - 1; t >= 0; --t) {
+        if (tfirst[t] >= 0) next = tfirst[t];
+        tileseg[tb0 + t] = next;
+      }
+    }
+  }
+  tileseg[(size_t)nt * B * ntiles] = (int32_t)nseg;
+  if (nseg >= (int64_t(1) << 31) / 256) return fail(GT_EUNSUPPORTED, "too many tile patches");
+  o.nwaves2 = (int32_t)(waves.size() / 4);
+  o.nseg2 = nseg;
+  int rc;
+  if ((rc = upload_raw(waves, &o.d_waves2)) || (rc = upload_raw(tileseg, &o.d_tileseg))) return rc;
+  const size_t csz = 2 * pl->rsize;
+  if ((rc = dev_alloc(&o.d_patch, (size_t)reff * std::max<int64_t>(1, nseg) * 256 * csz, s))) return rc;
+  if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * ntiles * 256 * csz, s))) return rc;
+  return GT_OK;
+}
+
 int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out) {
   *out = nullptr;
   int rc = validate_problem(p);
@@ -360,6 +433,14 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   int lds = 65536;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     pl->lds_limit = (size_t)lds;
+  int lds_cu = 0, ncu = 0;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+      lds_cu > 0)
+    pl->lds_per_cu = (size_t)lds_cu;
+  else
+    pl->lds_per_cu = pl->lds_limit;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    pl->num_cu = ncu;
 
   // ---- terms in coefficient order
   int64_t coef = 0, grid = 0;
@@ -508,21 +589,31 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     pl->nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap, std::max(1, pl->nterms - 1)));
   }
 
-  // ---- spread work items per order: ranges of cells per right-hand side, enough
-  //      single-wave workgroups, partial-grid memory bounded to about 1 GiB
+  // ---- spread work items per order: ranges of cells (orders 1, 3) or tiles (order 2) per
+  //      right-hand side; partial-grid memory bounded to about 1 GiB
   for (int t = 1; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
     const int64_t nt = o.term_end - o.term_begin;
     int64_t ncell = 1;
     for (int k = 0; k < t; ++k) ncell *= o.n;
     o.ncell = ncell;
-    // about 8192 wavefronts in total, at least one cell per wavefront of a workgroup
-    const int64_t pairs = std::max<int64_t>(1, nt * pl->R);
-    const int64_t want = std::max<int64_t>(1, (8192 / kSpreadWaves + pairs - 1) / pairs);
+    o.ts = t == 2 ? tile_side(o.m) : 1;
+    o.ntile = (o.n + o.ts - 1) / o.ts;
+    o.nkey = t == 2 ? (int64_t)o.ntile * o.ntile * o.ts * o.ts : ncell;
     const int64_t per_item = std::max<int64_t>(1, nt * o.gsize * (int64_t)csz);
     const int64_t mem_items = std::max<int64_t>(1, ((int64_t(1) << 30) / per_item) / pl->R);
-    const int64_t cell_cap = std::max<int64_t>(1, ncell / kSpreadWaves);
-    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(cell_cap, mem_items)));
+    const int64_t pairs = std::max<int64_t>(1, nt * pl->R);
+    int64_t units, chunks;
+    if (t == 2) {
+      units = 0;   // the tile spread takes its work list from setup_tile_spread
+      chunks = 0;
+    } else {
+      // about 8192 wavefronts in total, at least one cell per wavefront of a workgroup
+      units = ncell;
+      const int64_t want = std::max<int64_t>(1, (8192 / kSpreadWaves + pairs - 1) / pairs);
+      const int64_t cell_cap = std::max<int64_t>(1, ncell / kSpreadWaves);
+      chunks = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(cell_cap, mem_items)));
+    }
     o.sitems.clear();
     o.sitem_begin.assign(pl->R + 1, 0);
     for (int r = 0; r < pl->R; ++r) {
@@ -531,8 +622,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
         SpreadItem si{};
         si.r = r;
         si.b = pl->ragged ? r : 0;
-        si.c0 = (int32_t)(ncell * ch / chunks);
-        si.c1 = (int32_t)(ncell * (ch + 1) / chunks);
+        si.c0 = (int32_t)(units * ch / chunks);
+        si.c1 = (int32_t)(units * (ch + 1) / chunks);
         if (si.c1 > si.c0) o.sitems.push_back(si);
       }
     }
@@ -590,6 +681,7 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     hipError_t e2 = hipStreamSynchronize(s);
     if (e2 != hipSuccess) rc = hip_fail(e2, "node binning");
   }
+  if (rc == GT_OK && p->ds >= 2) rc = setup_tile_spread(pl, s);
   if (rc) {
     free_plan(pl);
     return rc;

@@ -1,11 +1,11 @@
-// K4 spread (adjoint): binned; one workgroup of kSpreadWaves wavefronts per (term,
-// right-hand side, range of cells), the cells dealt round-robin to the wavefronts.
+// K4 spread (adjoint), binned.  Orders 1 and 3: k_spread_binned, one workgroup of
+// kSpreadWaves wavefronts per (term, right-hand side, range of cells), the cells dealt
+// round-robin to the wavefronts.  Order 2: k_spread_tile2 below.
 //
 // The nodes of a term are sorted by the grid cell of their first window point (binning.hip).
 // For one cell all nodes share the same window position, so the cell's contribution to the
 // grid is a sum of outer products of window vectors:
 //   order 1:  g[j]          += sum_v y_v psi_v[j]
-//   order 2:  g[j1][j2]     += sum_v (y_v psi0_v[j1]) psi1_v[j2]
 //   order 3:  g[j1][j2][j3] += sum_v (y_v psi0_v[j1]) psi1_v[j2] psi2_v[j3]
 // i.e. a dense contraction over the cell's nodes, done with 16x16x4 MFMA (4 nodes per step,
 // window points padded to 16).  The patch is then added once per cell into the workgroup's
@@ -46,7 +46,7 @@ struct SpreadArgs {
   const int32_t *perm;     // order's sorted node indices (term-major, Mtot per term)
   const int64_t *cstart;   // first sorted position per (term, dataset, cell) key
   int32_t B;               // datasets (1 for shared nodes)
-  int64_t ncell;           // n^order
+  int64_t ncell;           // binning keys per (term, dataset)
   int64_t vstride;         // virtual node of (r, node) = r * vstride + node  (M, or 0 when ragged)
 };
 
@@ -113,8 +113,9 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
       fl2 = rem - fl1 * n;
     }
     const T zc0 = (T)(n - 2 * fl0 - 1), zc1 = (T)(n - 2 * fl1 - 1), zc2 = (T)(n - 2 * fl2 - 1);
-    if (ORDER == 1 || ORDER == 2) {
-      acc_t dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    static_assert(ORDER != 2, "order 2 uses k_spread_tile2");
+    if (ORDER == 1) {
+      acc_t dre = {0, 0, 0, 0};
       // batches of 64 nodes: lane l loads node l of the batch once; the MFMA steps take the
       // window arguments and samples of their 4 nodes from those lanes
       for (int64_t b0 = p0; b0 < p1; b0 += 64) {
@@ -123,7 +124,6 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
         const int32_t node = sa.perm[valid ? q : p0];
         cx_t<T> yl = y[vbase + node];
         const T za = fma(two_n, x0p[node], zc0);
-        const T zb = ORDER == 2 ? fma(two_n, x1p[node], zc1) : (T)0;
         if (!valid) yl = cmake<T>(0, 0);
         const int steps = (int)((p1 - b0 + 3) >> 2) < 16 ? (int)((p1 - b0 + 3) >> 2) : 16;
         for (int st = 0; st < steps; ++st) {
@@ -131,30 +131,16 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
           const T z0 = __shfl(za, src, 64);
           const T yr = __shfl(yl.x, src, 64), yi = __shfl(yl.y, src, 64);
           const T w0 = wp(z0);
-          if (ORDER == 1) {
-            const T a = i16 == 0 ? yr : (i16 == 1 ? yi : (T)0);
-            dre = MF::run(a, w0, dre);
-          } else {
-            const T w1 = wp(__shfl(zb, src, 64));
-            dre = MF::run(w0 * yr, w1, dre);
-            dim = MF::run(w0 * yi, w1, dim);
-          }
+          const T a = i16 == 0 ? yr : (i16 == 1 ? yi : (T)0);
+          dre = MF::run(a, w0, dre);
         }
       }
-      const int rs = wrap_start(fl0, MH, n);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = MF::row(l, r);
-        if (ORDER == 1) {
-          if (i16 < W && row < 2) {
-            double *dst = row == 0 ? &G[fl0 + i16].x : &G[fl0 + i16].y;
-            atomicAdd(dst, (double)dre[r]);
-          }
-        } else if (row < W && i16 < W) {
-          const int gr = (rs + row) % n;
-          double2 *dst = &G[gr * P + fl1 + i16];
-          atomicAdd(&dst->x, (double)dre[r]);
-          atomicAdd(&dst->y, (double)dim[r]);
+        if (i16 < W && row < 2) {
+          double *dst = row == 0 ? &G[fl0 + i16].x : &G[fl0 + i16].y;
+          atomicAdd(dst, (double)dre[r]);
         }
       }
     } else {
@@ -216,6 +202,242 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
   __syncthreads();
   cx_t<T> *out = gpart + (int64_t)blockIdx.x * gstride + tm.gpart_off;
   for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
+}
+
+// Orders the LDS accesses of one wavefront: staging writes by some lanes before reads by
+// other lanes of the same wavefront (and those reads before the next overwrite).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Order-2 spread on tiles of TS x TS grid cells, TS = 17 - 2m (the binning numbers cells
+// tile-major, so a tile's nodes are contiguous in sorted order).  Every node of a tile has
+// its 2m x 2m window inside one 16 x 16 patch of the grid, at offset (s0, s1) = its cell
+// minus the tile's first cell, so the tile's contribution is the patch
+//   Pt[i][j] = sum_v A_v[i] B_v[j],   A_v[s0 + a] = y_v psi(axis 0)[a],  B_v[s1 + b] = psi(axis 1)[b],
+// a dense contraction over the tile's nodes, done with 16x16x4 MFMA (4 nodes per step).
+//
+// Each wavefront owns a run of sorted positions of one (term, dataset) from the plan's work
+// list and walks it in batches of 32: lanes 0..31 evaluate the window along axis 0 of one
+// node each (times the sample), lanes 32..63 along axis 1, and stage the shifted,
+// zero-padded 16-vectors in LDS; 8 MFMA steps read them back as operands (rows past the end
+// of a short batch carry zero samples).  The nodes of a batch usually share one tile; when
+// a tile ends inside the batch, the batch is run once per tile with the other tiles'
+// samples zeroed.  At each tile change the wavefront stores its finished patch, with plain
+// stores, in its next patch slot (slots are numbered per wavefront in tile order); the
+// fold kernel adds the patches into the grids in a fixed order.  Nothing is shared between
+// wavefronts, so there are no atomics and no workgroup barriers.
+//
+// Inputs stream with a four-deep register pipeline: sorted node indices and the sorted
+// coordinates (plan array xs) three batches ahead, the samples (gathered through the node
+// index) one batch ahead.
+template <typename T>
+struct TileStage {
+  int32_t p;    // node index
+  cx_t<T> x;    // the node's coordinates along the term's two axes
+  cx_t<T> y;    // sample
+};
+
+struct Tile2Args {
+  const int32_t *waves;    // per wavefront: first position, end position, first patch slot, dataset
+  int32_t nwaves;
+  int32_t ntile;           // tiles per axis
+  int64_t nseg;            // patch slots per right-hand side
+  int64_t vstride;         // sample of (r, node) = y[r * vstride + node]  (M, or 0 when ragged)
+  int32_t ragged;          // datasets own their samples: r = dataset, one set of slots
+};
+
+template <typename T, int MH>
+__global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__restrict__ xs,
+                                                                  const int32_t *__restrict__ perm, OrderParams<T> op,
+                                                                  Tile2Args ta, const cx_t<T> *__restrict__ y,
+                                                                  cx_t<T> *__restrict__ patch) {
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc;
+  using C = cx_t<T>;
+  constexpr int W = 2 * MH, TS = tile_side(MH), UB = kTileBatch, SR = kTileRow;
+  static_assert(TS >= 1 && TS + W - 1 == 16, "tile patch must be 16 x 16");
+  static_assert(UB == 32, "one node per lane pair of a wavefront");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int l = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+  const int h = l >> 5, j = l & 31, i16 = l & 15, kk = l >> 4;
+  C *SAw = reinterpret_cast<C *>(smem_raw) + (size_t)wv * UB * SR;                                    // UB x SR
+  T *SBw = reinterpret_cast<T *>(smem_raw + (size_t)kTileWaves * UB * SR * sizeof(C)) + (size_t)wv * UB * SR;
+  const int w = blockIdx.x * kTileWaves + wv;
+  if (w >= ta.nwaves) return;   // whole wavefront; the kernel has no workgroup barrier
+  const int32_t qbeg = ta.waves[4 * w], qend = ta.waves[4 * w + 1];
+  int64_t slot = ta.waves[4 * w + 2];
+  const int r = ta.ragged ? ta.waves[4 * w + 3] : (int)blockIdx.y;
+  if (!ta.ragged) slot += (int64_t)blockIdx.y * ta.nseg;
+  const int nbat = (qend - qbeg + UB - 1) / UB;
+  const int64_t vbase = (int64_t)r * ta.vstride;
+  const int n = op.n, ntile = ta.ntile;
+  // window polynomial coefficients of points 0..m-1 (the others mirror them), in registers
+  constexpr int NC = MH * (Deg<T>::value + 1);
+  T cf[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) cf[i] = op.poly[i];
+
+  // Loads are issued unconditionally (positions past the wavefront's range are clamped to
+  // its last node), so the wait counts stay exact across the unrolled pipeline.
+  const C *__restrict__ xs2 = reinterpret_cast<const C *>(xs);
+  auto issue_px = [&](TileStage<T> &s, int k) {
+    int32_t q = qbeg + k * UB + j;
+    q = q < qend ? q : qend - 1;
+    s.p = perm[q];
+    s.x = xs2[q];
+  };
+  auto issue_y = [&](TileStage<T> &s) { s.y = y[vbase + s.p]; };
+
+  acc_t are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+  int cur_tile = -1;
+  bool dirty = false;
+  auto store_patch = [&]() {   // patch row MF::row(l, r), column i16
+    C *dst = patch + slot * 256 + i16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[MF::row(l, q) * 16] = cmake<T>((T)are[q], (T)aim[q]);
+    ++slot;
+    are = acc_t{0, 0, 0, 0};
+    aim = acc_t{0, 0, 0, 0};
+  };
+  auto process = [&](const TileStage<T> &st, int k) {
+    const bool valid = qbeg + k * UB + j < qend;
+    int f0, f1;
+    const T r0 = frac_offset<T>(st.x.x, n, f0), r1 = frac_offset<T>(st.x.y, n, f1);
+    const T z = (h ? r1 : r0) * (T)2 - (T)1;
+    T psi[W];
+    window_values<T, MH>(z, cf, psi);
+    const int ty = f0 / TS, tx = f1 / TS;
+    const int tile = valid ? ty * ntile + tx : 0x7fffffff;
+    const int s = h ? f1 - tx * TS : f0 - ty * TS;
+    unsigned long long pending = __ballot(valid);
+    while (pending) {
+      const int t = __builtin_amdgcn_readlane(tile, __ffsll((long long)pending) - 1);
+      const bool in = tile == t;
+      if (t != cur_tile) {
+        if (dirty) store_patch();
+        cur_tile = t;
+      }
+      if (h == 0) {
+        const T yr = in ? st.y.x : (T)0, yi = in ? st.y.y : (T)0;
+        C *row = SAw + j * SR;
+#pragma unroll
+        for (int a = 0; a < W; ++a) row[s + a] = cmake<T>(psi[a] * yr, psi[a] * yi);
+#pragma unroll
+        for (int q = 0; q < 16 - W; ++q) row[(s + W + q) & 15] = cmake<T>((T)0, (T)0);
+      } else {
+        T *row = SBw + j * SR;
+#pragma unroll
+        for (int a = 0; a < W; ++a) row[s + a] = psi[a];
+#pragma unroll
+        for (int q = 0; q < 16 - W; ++q) row[(s + W + q) & 15] = (T)0;
+      }
+      wave_lds_sync();
+      C av[UB / 4];
+      T bv[UB / 4];
+#pragma unroll
+      for (int q = 0; q < UB / 4; ++q) {
+        av[q] = SAw[(4 * q + kk) * SR + i16];
+        bv[q] = SBw[(4 * q + kk) * SR + i16];
+      }
+#pragma unroll
+      for (int q = 0; q < UB / 4; ++q) {
+        are = MF::run(av[q].x, bv[q], are);
+        aim = MF::run(av[q].y, bv[q], aim);
+      }
+      wave_lds_sync();
+      dirty = true;
+      pending &= ~__ballot(in);
+    }
+  };
+
+  if (nbat > 0) {
+    TileStage<T> S[4];
+    issue_px(S[0], 0);
+    issue_px(S[1], 1);
+    issue_px(S[2], 2);
+    issue_y(S[0]);
+    for (int k0 = 0; k0 < nbat; k0 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u;
+        issue_px(S[(u + 3) & 3], k + 3);
+        issue_y(S[(u + 1) & 3]);
+        if (k < nbat) process(S[u], k);
+      }
+    }
+  }
+  if (dirty) store_patch();
+}
+
+// Fold of the order-2 tile patches, in two passes with a fixed summation order (so the
+// result is deterministic).
+// k_tile_sums: one thread per (right-hand side, term, tile, patch element) adds the tile's
+//   patches (consecutive slots) in slot order: tsum[(r * terms + tl) * ntile^2 + tile][16 x 16].
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_sums(const cx_t<T> *__restrict__ patch,
+                                                   const int32_t *__restrict__ tileseg, Tile2Args ta, int nt, int B,
+                                                   cx_t<T> *__restrict__ tsum) {
+  const int ntiles = ta.ntile * ta.ntile;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (tl, tile, e)
+  if (idx >= (int64_t)nt * ntiles * 256) return;
+  const int r = blockIdx.y;
+  const int e = (int)(idx & 255);
+  const int64_t tt = idx >> 8;   // tl * ntiles + tile
+  const int tl = (int)(tt / ntiles), tile = (int)(tt - (int64_t)tl * ntiles);
+  const int b = ta.ragged ? r : 0;
+  const int64_t pbase = ta.ragged ? 0 : (int64_t)r * ta.nseg;
+  const int64_t lin = ((int64_t)tl * B + b) * ntiles + tile;
+  const int s0 = tileseg[lin], s1 = tileseg[lin + 1];
+  T re = 0, im = 0;
+  for (int sg = s0; sg < s1; ++sg) {
+    const cx_t<T> v = patch[(pbase + sg) * 256 + e];
+    re += v.x;
+    im += v.y;
+  }
+  tsum[((int64_t)r * nt * ntiles + tt) * 256 + e] = cmake<T>(re, im);
+}
+
+// k_fold_tiles: folded grid point (l0, l1) of term tl and right-hand side r is the sum of the
+// tile sums whose 16 x 16 patch covers it (patch rows wrap modulo n; halo columns
+// p = l1 + m - 1 (mod n)), tiles in row-major order.  gsum layout: [r][term][l0][l1].
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_tiles(const cx_t<T> *__restrict__ tsum, OrderParams<T> op, int ntile,
+                                                    int ts, cx_t<T> *__restrict__ gsum) {
+  const int n = op.n, P = op.P, mm1 = op.m - 1, ntiles = ntile * ntile;
+  const int nt = op.term_end - op.term_begin;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nt * n * n) return;
+  const int r = blockIdx.y;
+  const int tl = (int)(idx / ((int64_t)n * n));
+  const int pt = (int)(idx - (int64_t)tl * n * n);
+  const int l0 = pt / n, l1 = pt - l0 * n;
+  const cx_t<T> *src = tsum + ((int64_t)r * nt + tl) * ntiles * 256;
+  T re = 0, im = 0;
+  for (int ty = 0; ty < ntile; ++ty) {
+    int rs = (ty * ts - mm1) % n;
+    rs = rs < 0 ? rs + n : rs;
+    int pr0 = (l0 - rs) % n;
+    pr0 = pr0 < 0 ? pr0 + n : pr0;
+    if (pr0 >= 16) continue;
+    for (int p = (l1 + mm1) % n; p < P; p += n) {
+      int tx0 = p >= 15 ? (p - 15 + ts - 1) / ts : 0;
+      int tx1 = p / ts;
+      tx1 = tx1 < ntile - 1 ? tx1 : ntile - 1;
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const cx_t<T> *tp = src + (int64_t)(ty * ntile + tx) * 256 + (p - tx * ts);
+        for (int pr = pr0; pr < 16; pr += n) {
+          const cx_t<T> v = tp[pr * 16];
+          re += v.x;
+          im += v.y;
+        }
+      }
+    }
+  }
+  gsum[((int64_t)r * nt + tl) * n * n + pt] = cmake<T>(re, im);
 }
 
 }  // namespace gt
