@@ -158,6 +158,8 @@ struct gt_plan {
   int32_t *d_flag = nullptr;          // node validation flag
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;         // second stream (default priority) for the order-1 kernels
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t lds_limit = 65536;           // LDS per workgroup
   size_t lds_per_cu = 65536;          // LDS per compute unit
   int num_cu = 256;                   // compute units of the device

@@ -873,9 +873,10 @@ static size_t adj_lds(const gt_plan *pl, int t) {
 }
 
 template <typename T>
-static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStream_t s) {
+static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStream_t s, int only = 0) {
   using C = cx_t<T>;
   for (int t = 1; t <= pl->ds; ++t) {
+    if (only && t != only) continue;
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     if (nt == 0) continue;
@@ -902,18 +903,36 @@ static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStre
   return GT_OK;
 }
 
+// Orders are independent until the final sums, so the order-1 kernels (and the empty
+// set's) run on the plan's side stream, forked from and joined back into the caller's
+// stream with events (inside a graph capture this makes parallel branches).  Not while
+// per-launch profiling is on.
+static bool fork_side(gt_plan *pl, hipStream_t s) {
+  if (!pl->side || prof_enabled() || pl->ds < 2) return false;
+  if (hipEventRecord(pl->ev_fork, s) != hipSuccess) return false;
+  return hipStreamWaitEvent(pl->side, pl->ev_fork, 0) == hipSuccess;
+}
+static int join_side(gt_plan *pl, hipStream_t s) {
+  GT_HIP(hipEventRecord(pl->ev_join, pl->side));
+  GT_HIP(hipStreamWaitEvent(s, pl->ev_join, 0));
+  return GT_OK;
+}
+
 template <typename T>
 int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
   using C = cx_t<T>;
-  if (int rc = launch_pack<T>(pl, fhat, colscale, s)) return rc;
   const int ngi = (int)pl->gitems.size();
-  if (ngi == 0) return GT_OK;
+  if (ngi == 0) return launch_pack<T>(pl, fhat, colscale, s);
   // terms 1..nterms-1 in blocks of nslots; each block: gathers into slots, then one reduction
   const int S = std::max(1, pl->nslots);
   const int nt_all = pl->nterms - 1;
   for (int g0 = 1, blk = 0; blk == 0 || g0 <= nt_all; g0 += S, ++blk) {
     const int g1 = std::min(pl->nterms, g0 + S);
+    const bool fk = fork_side(pl, s);
     for (int t = 1; t <= pl->ds; ++t) {
+      const hipStream_t st = (fk && t == 1) ? pl->side : s;
+      if (blk == 0)
+        if (int rc = launch_pack<T>(pl, fhat, colscale, st, t)) return rc;
       const OrderHost &o = pl->ord[t];
       const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
       if (tb >= te) continue;
@@ -924,31 +943,33 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
       const GatherItem *items = o.d_gitems + i0;
       const int64_t vstride = pl->ragged ? 0 : pl->M;
       dim3 grid(i1 - i0);
-      prof_begin(s, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
+      prof_begin(st, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
 #define GT_LAUNCH_GATHER(MH)                                                                                      \
   {                                                                                                               \
     if (t == 1) {                                                                                                 \
       if (int rc = set_lds(k_gather_sorted<T, 1, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_gather_sorted<T, 1, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+      hipLaunchKernelGGL((k_gather_sorted<T, 1, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
                          items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     } else if (t == 2) {                                                                                          \
       if (int rc = set_lds(k_gather_sorted<T, 2, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_gather_sorted<T, 2, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+      hipLaunchKernelGGL((k_gather_sorted<T, 2, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
                          items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     } else {                                                                                                      \
       if (int rc = set_lds(k_gather_sorted<T, 3, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_gather_sorted<T, 3, MH>), grid, dim3(kGatherBS), lds, s, (const T *)pl->d_x, pl->Mtot, \
+      hipLaunchKernelGGL((k_gather_sorted<T, 3, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
                          items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     }                                                                                                             \
   }
       GT_DISPATCH_M(o.m, GT_LAUNCH_GATHER)
 #undef GT_LAUNCH_GATHER
-      prof_end(s);
+      prof_end(st);
       if (int rc = check_launch("k_gather_sorted")) return rc;
     }
+    if (fk)
+      if (int rc = join_side(pl, s)) return rc;
     prof_begin(s, "reduce_f");
     hipLaunchKernelGGL((k_reduce_f<T>), dim3(4 * ngi), dim3(256), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
                        (const C *)pl->d_fpart, g1 - g0, pl->Vtot, blk > 0 ? 1 : 0, (C *)f);
@@ -975,7 +996,9 @@ template <typename T>
 int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
+  const bool fk = fork_side(pl, s);
   for (int t = 1; t <= pl->ds; ++t) {
+    const hipStream_t st = (fk && t == 1) ? pl->side : s;
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     const int nsi = (int)o.sitems.size();
@@ -989,16 +1012,16 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     sa.vstride = pl->ragged ? 0 : pl->M;
     const size_t lds = (size_t)o.gsize * sizeof(double2);
     dim3 grid(nsi, nt);
-    prof_begin(s, t == 1 ? "spread_1d" : t == 2 ? "spread_2d" : "spread_3d");
+    prof_begin(st, t == 1 ? "spread_1d" : t == 2 ? "spread_2d" : "spread_3d");
 #define GT_LAUNCH_SPREAD(MH)                                                                                      \
   {                                                                                                               \
     if (t == 1) {                                                                                                 \
       if (int rc = set_lds(k_spread_binned<T, 1, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_spread_binned<T, 1, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
+      hipLaunchKernelGGL((k_spread_binned<T, 1, MH>), grid, dim3(64 * kSpreadWaves), lds, st, (const T *)pl->d_x, pl->Mtot,       \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     } else {                                                                                                      \
       if (int rc = set_lds(k_spread_binned<T, 3, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_spread_binned<T, 3, MH>), grid, dim3(64 * kSpreadWaves), lds, s, (const T *)pl->d_x, pl->Mtot,       \
+      hipLaunchKernelGGL((k_spread_binned<T, 3, MH>), grid, dim3(64 * kSpreadWaves), lds, st, (const T *)pl->d_x, pl->Mtot,       \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     }                                                                                                             \
   }
@@ -1008,7 +1031,7 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T));                    \
     if (int rc = set_lds(k_spread_tile2<T, MH>, lds2)) return rc;                                                 \
     hipLaunchKernelGGL((k_spread_tile2<T, MH>), dim3((unsigned)((o.nwaves2 + kTileWaves - 1) / kTileWaves),     \
-                       (unsigned)(pl->ragged ? 1 : pl->R)), dim3(64 * kTileWaves), lds2, s, (const T *)o.d_xs,      \
+                       (unsigned)(pl->ragged ? 1 : pl->R)), dim3(64 * kTileWaves), lds2, st, (const T *)o.d_xs,      \
                        (const int32_t *)o.d_perm, op, ta, (const C *)y, (C *)o.d_patch);                           \
   }
     if (t == 2) {
@@ -1018,61 +1041,65 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     }
 #undef GT_LAUNCH_TILE2
 #undef GT_LAUNCH_SPREAD
-    prof_end(s);
+    prof_end(st);
     if (int rc = check_launch("k_spread")) return rc;
   }
   for (int t = 1; t <= pl->ds; ++t) {
+    const hipStream_t st = (fk && t == 1) ? pl->side : s;
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     if (nt == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     const size_t lds = adj_lds<T>(pl, t);
     if (t == 2) {
-      prof_begin(s, "fold_2d");
+      prof_begin(st, "fold_2d");
       const int ntiles = o.ntile * o.ntile;
       const int64_t nsum = (int64_t)nt * ntiles * 256;
-      hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)((nsum + 255) / 256), pl->R), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)((nsum + 255) / 256), pl->R), dim3(256), 0, st,
                          (const C *)o.d_patch, o.d_tileseg, tile2_args(pl), nt, pl->ragged ? pl->R : 1,
                          (C *)o.d_tsum);
       const int64_t pts = (int64_t)nt * o.n * o.n;
-      hipLaunchKernelGGL((k_fold_tiles<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_fold_tiles<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, st,
                          (const C *)o.d_tsum, op, o.ntile, o.ts, (C *)o.d_gsum);
-      prof_end(s);
+      prof_end(st);
       if (int rc = check_launch("k_fold_tiles")) return rc;
     } else {
       const int64_t outer = t == 1 ? 1 : (int64_t)o.n * o.n;
       const int64_t pts = outer * o.n * nt;
-      prof_begin(s, t == 1 ? "fold_1d" : "fold_3d");
-      hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 63) / 64), pl->R), dim3(256), 0, s,
+      prof_begin(st, t == 1 ? "fold_1d" : "fold_3d");
+      hipLaunchKernelGGL((k_fold_partials<T>), dim3((unsigned)((pts + 63) / 64), pl->R), dim3(256), 0, st,
                          (const C *)o.d_gpart, o.gpart_stride, o.d_sitem_begin, pl->d_terms, op, t, (C *)o.d_gsum);
-      prof_end(s);
+      prof_end(st);
       if (int rc = check_launch("k_fold_partials")) return rc;
     }
     dim3 grid(nt, pl->R);
-    prof_begin(s, t == 1 ? "dft_adj_1d" : t == 2 ? "dft_adj_2d" : "dft_adj_3d");
+    prof_begin(st, t == 1 ? "dft_adj_1d" : t == 2 ? "dft_adj_2d" : "dft_adj_3d");
     if (t == 1) {
       if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+      hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
                          colscale, pl->ncoef, (C *)fhat);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
                          colscale, pl->ncoef, (C *)fhat);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)o.d_gsum, pl->d_terms, op,
+      hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
                          colscale, pl->ncoef, (C *)fhat);
     }
-    prof_end(s);
+    prof_end(st);
     if (int rc = check_launch("k_dft_adj")) return rc;
   }
   if (ngi > 0) {
-    prof_begin(s, "empty_adj");
-    hipLaunchKernelGGL((k_empty_adj<T>), dim3(ngi), dim3(kGatherBS), 0, s, pl->d_gitems, pl->d_gitem_begin,
+    const hipStream_t st = fk ? pl->side : s;
+    prof_begin(st, "empty_adj");
+    hipLaunchKernelGGL((k_empty_adj<T>), dim3(ngi), dim3(kGatherBS), 0, st, pl->d_gitems, pl->d_gitem_begin,
                        (const C *)y, pl->d_ysum, pl->d_ycount, pl->ncoef, (C *)fhat);
-    prof_end(s);
+    prof_end(st);
     if (int rc = check_launch("k_empty_adj")) return rc;
   }
+  if (fk)
+    if (int rc = join_side(pl, s)) return rc;
   return GT_OK;
 }
 

@@ -256,6 +256,14 @@ void free_plan(gt_plan *pl) {
     if (ge.graph) (void)hipGraphDestroy(ge.graph);
   }
   pl->graphs.clear();
+  if (pl->side) {
+    (void)hipStreamSynchronize(pl->side);
+    (void)hipStreamDestroy(pl->side);
+    pl->side = nullptr;
+  }
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  pl->ev_fork = pl->ev_join = nullptr;
   dev_free(pl->d_terms, nullptr);
   dev_free(pl->d_x, nullptr);
   dev_free(pl->d_grid, nullptr);
@@ -441,6 +449,17 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     pl->lds_per_cu = pl->lds_limit;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     pl->num_cu = ncu;
+  // side stream for independent per-order kernels (non-blocking, default priority); without
+  // it everything runs on the caller's stream
+  if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (pl->side) (void)hipStreamDestroy(pl->side);
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    pl->side = nullptr;
+    pl->ev_fork = pl->ev_join = nullptr;
+  }
 
   // ---- terms in coefficient order
   int64_t coef = 0, grid = 0;
