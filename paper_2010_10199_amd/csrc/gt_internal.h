@@ -118,7 +118,7 @@ struct OrderHost {
   int32_t *d_waves2 = nullptr;        // nwaves2 x 4: first position, end position, first segment, dataset
   int32_t *d_tileseg = nullptr;       // (terms x datasets x ntile^2) + 1: first segment of each tile
   void *d_patch = nullptr;            // (R or 1) x nseg2 x 16 x 16 complex
-  void *d_tsum = nullptr;             // R x terms x ntile^2 x 16 x 16 complex: patches summed per tile
+  void *d_tsum = nullptr;             // R x terms x ntile x 16 x n complex: patches folded along columns
   int64_t *d_cstart = nullptr;        // (terms x datasets x nkey) + 1 start positions
   std::vector<SpreadItem> sitems;
   SpreadItem *d_sitems = nullptr;

@@ -151,15 +151,18 @@ static __global__ void k_zero_n(int32_t *p, int n) {
 // ------------------------------------------------------------------ K1 + K2 forward
 // One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
 // (N-1)^t non-zero frequencies onto the n^t grid, written in the halo layout.
+// The last stage's outputs are split over `slices` workgroups per term (each recomputes the
+// earlier, smaller stages), so a launch has slices x terms workgroups.
 template <typename T, int ORDER>
 __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict__ fhat, const T *__restrict__ colscale,
                                                       int64_t ncoef, const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                      cx_t<T> *__restrict__ grids, int64_t grid_total) {
+                                                      cx_t<T> *__restrict__ grids, int64_t grid_total, int slices) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
   const int tid = threadIdx.x, BS = blockDim.x;
-  const DevTerm tm = terms[op.term_begin + blockIdx.x];
+  const int slice = blockIdx.x % slices;
+  const DevTerm tm = terms[op.term_begin + blockIdx.x / slices];
   const int r = blockIdx.y;
   const C *src = fhat + (int64_t)r * ncoef + tm.coef_off;
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
@@ -192,7 +195,8 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
       S[a] = cmake<T>(v.x * sc, v.y * sc);
     }
     __syncthreads();
-    for (int p = tid; p < P; p += BS) {
+    const int p0 = (int)((int64_t)P * slice / slices), p1 = (int)((int64_t)P * (slice + 1) / slices);
+    for (int p = p0 + tid; p < p1; p += BS) {
       const int l = unpad(p);
       T re = 0, im = 0;
       int e = phase0(l);
@@ -229,7 +233,8 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
       B[i] = cmake<T>(re, im);
     }
     __syncthreads();
-    for (int i = tid; i < n * P; i += BS) {
+    const int i0 = (int)((int64_t)n * P * slice / slices), i1 = (int)((int64_t)n * P * (slice + 1) / slices);
+    for (int i = i0 + tid; i < i1; i += BS) {
       const int l1 = i / P, p2 = i - l1 * P, l2 = unpad(p2);
       T re = 0, im = 0;
       int e = phase0(l1);
@@ -281,7 +286,8 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
       Cc[i] = cmake<T>(re, im);
     }
     __syncthreads();
-    for (int i = tid; i < n * n * P; i += BS) {
+    const int i0 = (int)((int64_t)n * n * P * slice / slices), i1 = (int)((int64_t)n * n * P * (slice + 1) / slices);
+    for (int i = i0 + tid; i < i1; i += BS) {
       const int l1 = i / (n * P), rem = i - l1 * n * P, l2 = rem / P, p3 = rem - l2 * P, l3 = unpad(p3);
       T re = 0, im = 0;
       int e = phase0(l1);
@@ -510,7 +516,7 @@ template <typename T, int ORDER>
 __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
                                                      const DevTerm *__restrict__ terms, OrderParams<T> op,
                                                      const T *__restrict__ colscale, int64_t ncoef,
-                                                     cx_t<T> *__restrict__ fhat) {
+                                                     cx_t<T> *__restrict__ fhat, int ntile, int ts) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
@@ -538,8 +544,32 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
   };
   const int outer = ORDER == 1 ? 1 : (ORDER == 2 ? n : n * n);
   C *G = S;
-  const C *src = gsum + ((int64_t)r * nt + tl) * outer * n;
-  for (int i = tid; i < outer * n; i += BS) G[i] = src[i];
+  if (ORDER == 2 && ntile > 0) {
+    // order 2 from the tile spread: gsum holds the column-folded patches
+    // hcol[ty][pr][l1] of this term; grid row l0 collects the patch rows that land on it
+    // (start row of tile row ty plus pr, modulo n), tile rows in order
+    const int mm1 = op.m - 1;
+    const C *hc = gsum + ((int64_t)r * nt + tl) * ntile * 16 * n;
+    for (int i = tid; i < n * n; i += BS) {
+      const int l0 = i / n, l1 = i - l0 * n;
+      T re = 0, im = 0;
+      for (int ty = 0; ty < ntile; ++ty) {
+        int rs = (ty * ts - mm1) % n;
+        rs = rs < 0 ? rs + n : rs;
+        int pr = (l0 - rs) % n;
+        pr = pr < 0 ? pr + n : pr;
+        for (; pr < 16; pr += n) {
+          const C v = hc[(ty * 16 + pr) * n + l1];
+          re += v.x;
+          im += v.y;
+        }
+      }
+      G[i] = cmake<T>(re, im);
+    }
+  } else {
+    const C *src = gsum + ((int64_t)r * nt + tl) * outer * n;
+    for (int i = tid; i < outer * n; i += BS) G[i] = src[i];
+  }
   __syncthreads();
   // conj twiddles: e^{-2 pi i k l / n}
   if (ORDER == 1) {
@@ -882,20 +912,21 @@ static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStre
     if (nt == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     const size_t lds = pack_lds<T>(pl, t);
-    dim3 grid(nt, pl->R);
+    const int slices = t == 1 ? 4 : 8;
+    dim3 grid(nt * slices, pl->R);
     prof_begin(s, t == 1 ? "pack_fwd_1d" : t == 2 ? "pack_fwd_2d" : "pack_fwd_3d");
     if (t == 1) {
       if (int rc = set_lds(k_pack_fwd<T, 1>, lds)) return rc;
       hipLaunchKernelGGL((k_pack_fwd<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
-                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     } else if (t == 2) {
       if (int rc = set_lds(k_pack_fwd<T, 2>, lds)) return rc;
       hipLaunchKernelGGL((k_pack_fwd<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
-                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     } else {
       if (int rc = set_lds(k_pack_fwd<T, 3>, lds)) return rc;
       hipLaunchKernelGGL((k_pack_fwd<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
-                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total);
+                         pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     }
     prof_end(s);
     if (int rc = check_launch("k_pack_fwd")) return rc;
@@ -1053,16 +1084,12 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const size_t lds = adj_lds<T>(pl, t);
     if (t == 2) {
       prof_begin(st, "fold_2d");
-      const int ntiles = o.ntile * o.ntile;
-      const int64_t nsum = (int64_t)nt * ntiles * 256;
-      hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)((nsum + 255) / 256), pl->R), dim3(256), 0, st,
-                         (const C *)o.d_patch, o.d_tileseg, tile2_args(pl), nt, pl->ragged ? pl->R : 1,
+      const int64_t ncol = (int64_t)nt * o.ntile * 16 * o.n;
+      hipLaunchKernelGGL((k_fold_cols<T>), dim3((unsigned)((ncol + 255) / 256), pl->R), dim3(256), 0, st,
+                         (const C *)o.d_patch, o.d_tileseg, op, tile2_args(pl), pl->ragged ? pl->R : 1, o.ts,
                          (C *)o.d_tsum);
-      const int64_t pts = (int64_t)nt * o.n * o.n;
-      hipLaunchKernelGGL((k_fold_tiles<T>), dim3((unsigned)((pts + 255) / 256), pl->R), dim3(256), 0, st,
-                         (const C *)o.d_tsum, op, o.ntile, o.ts, (C *)o.d_gsum);
       prof_end(st);
-      if (int rc = check_launch("k_fold_tiles")) return rc;
+      if (int rc = check_launch("k_fold_cols")) return rc;
     } else {
       const int64_t outer = t == 1 ? 1 : (int64_t)o.n * o.n;
       const int64_t pts = outer * o.n * nt;
@@ -1077,15 +1104,15 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (t == 1) {
       if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat);
+                         colscale, pl->ncoef, (C *)fhat, 0, 0);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat);
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, st, (const C *)o.d_tsum, pl->d_terms, op,
+                         colscale, pl->ncoef, (C *)fhat, o.ntile, o.ts);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat);
+                         colscale, pl->ncoef, (C *)fhat, 0, 0);
     }
     prof_end(st);
     if (int rc = check_launch("k_dft_adj")) return rc;

@@ -405,7 +405,7 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
   if ((rc = upload_raw(waves, &o.d_waves2)) || (rc = upload_raw(tileseg, &o.d_tileseg))) return rc;
   const size_t csz = 2 * pl->rsize;
   if ((rc = dev_alloc(&o.d_patch, (size_t)reff * std::max<int64_t>(1, nseg) * 256 * csz, s))) return rc;
-  if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * ntiles * 256 * csz, s))) return rc;
+  if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * o.ntile * 16 * o.n * csz, s))) return rc;
   return GT_OK;
 }
 
@@ -671,7 +671,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     if ((rc = upload_raw(o.gitems, &o.d_gitems)) || (rc = upload_raw(o.sitems, &o.d_sitems)) ||
         (rc = upload_raw(o.sitem_begin, &o.d_sitem_begin)) ||
         (rc = dev_alloc(&o.d_gpart, (size_t)o.sitems.size() * o.gpart_stride * csz, s)) ||
-        (rc = dev_alloc(&o.d_gsum, (size_t)pl->R * (o.term_end - o.term_begin) * (size_t)o.ncell * csz, s))) {
+        (rc = dev_alloc(&o.d_gsum, t == 2 ? 0 : (size_t)pl->R * (o.term_end - o.term_begin) * (size_t)o.ncell * csz,
+                        s))) {
       free_plan(pl);
       return rc;
     }

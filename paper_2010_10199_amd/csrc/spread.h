@@ -373,71 +373,43 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__res
   if (dirty) store_patch();
 }
 
-// Fold of the order-2 tile patches, in two passes with a fixed summation order (so the
-// result is deterministic).
-// k_tile_sums: one thread per (right-hand side, term, tile, patch element) adds the tile's
-//   patches (consecutive slots) in slot order: tsum[(r * terms + tl) * ntile^2 + tile][16 x 16].
+// Fold of the order-2 tile patches into the folded grids, in two separable passes with a
+// fixed summation order (so the result is deterministic): the columns here, the rows at the
+// start of the order-2 adjoint DFT (k_dft_adj).
+// k_fold_cols: one thread per (right-hand side, term, tile row ty, patch row pr, grid column
+//   l1) adds, over the tile columns tx whose patch covers halo column p = l1 + m - 1 (mod n)
+//   and over each tile's patches in slot order, the patch entries (pr, p - tx ts):
+//   hcol[(r * terms + tl) * ntile + ty][pr][l1].
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_sums(const cx_t<T> *__restrict__ patch,
-                                                   const int32_t *__restrict__ tileseg, Tile2Args ta, int nt, int B,
-                                                   cx_t<T> *__restrict__ tsum) {
-  const int ntiles = ta.ntile * ta.ntile;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (tl, tile, e)
-  if (idx >= (int64_t)nt * ntiles * 256) return;
+__global__ __launch_bounds__(256) void k_fold_cols(const cx_t<T> *__restrict__ patch,
+                                                   const int32_t *__restrict__ tileseg, OrderParams<T> op,
+                                                   Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+  const int n = op.n, P = op.P, mm1 = op.m - 1, ntile = ta.ntile, ntiles = ntile * ntile;
+  const int nt = op.term_end - op.term_begin;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // ((tl * ntile + ty) * 16 + pr) * n + l1
+  if (idx >= (int64_t)nt * ntile * 16 * n) return;
   const int r = blockIdx.y;
-  const int e = (int)(idx & 255);
-  const int64_t tt = idx >> 8;   // tl * ntiles + tile
-  const int tl = (int)(tt / ntiles), tile = (int)(tt - (int64_t)tl * ntiles);
+  const int l1 = (int)(idx % n);
+  const int pr = (int)((idx / n) & 15);
+  const int64_t tty = idx / (16 * n);   // tl * ntile + ty
+  const int tl = (int)(tty / ntile), ty = (int)(tty - (int64_t)tl * ntile);
   const int b = ta.ragged ? r : 0;
   const int64_t pbase = ta.ragged ? 0 : (int64_t)r * ta.nseg;
-  const int64_t lin = ((int64_t)tl * B + b) * ntiles + tile;
-  const int s0 = tileseg[lin], s1 = tileseg[lin + 1];
+  const int32_t *tsg = tileseg + ((int64_t)tl * B + b) * ntiles + ty * ntile;
   T re = 0, im = 0;
-  for (int sg = s0; sg < s1; ++sg) {
-    const cx_t<T> v = patch[(pbase + sg) * 256 + e];
-    re += v.x;
-    im += v.y;
-  }
-  tsum[((int64_t)r * nt * ntiles + tt) * 256 + e] = cmake<T>(re, im);
-}
-
-// k_fold_tiles: folded grid point (l0, l1) of term tl and right-hand side r is the sum of the
-// tile sums whose 16 x 16 patch covers it (patch rows wrap modulo n; halo columns
-// p = l1 + m - 1 (mod n)), tiles in row-major order.  gsum layout: [r][term][l0][l1].
-template <typename T>
-__global__ __launch_bounds__(256) void k_fold_tiles(const cx_t<T> *__restrict__ tsum, OrderParams<T> op, int ntile,
-                                                    int ts, cx_t<T> *__restrict__ gsum) {
-  const int n = op.n, P = op.P, mm1 = op.m - 1, ntiles = ntile * ntile;
-  const int nt = op.term_end - op.term_begin;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nt * n * n) return;
-  const int r = blockIdx.y;
-  const int tl = (int)(idx / ((int64_t)n * n));
-  const int pt = (int)(idx - (int64_t)tl * n * n);
-  const int l0 = pt / n, l1 = pt - l0 * n;
-  const cx_t<T> *src = tsum + ((int64_t)r * nt + tl) * ntiles * 256;
-  T re = 0, im = 0;
-  for (int ty = 0; ty < ntile; ++ty) {
-    int rs = (ty * ts - mm1) % n;
-    rs = rs < 0 ? rs + n : rs;
-    int pr0 = (l0 - rs) % n;
-    pr0 = pr0 < 0 ? pr0 + n : pr0;
-    if (pr0 >= 16) continue;
-    for (int p = (l1 + mm1) % n; p < P; p += n) {
-      int tx0 = p >= 15 ? (p - 15 + ts - 1) / ts : 0;
-      int tx1 = p / ts;
-      tx1 = tx1 < ntile - 1 ? tx1 : ntile - 1;
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const cx_t<T> *tp = src + (int64_t)(ty * ntile + tx) * 256 + (p - tx * ts);
-        for (int pr = pr0; pr < 16; pr += n) {
-          const cx_t<T> v = tp[pr * 16];
-          re += v.x;
-          im += v.y;
-        }
+  for (int p = (l1 + mm1) % n; p < P; p += n) {
+    const int tx0 = p >= 15 ? (p - 15 + ts - 1) / ts : 0;
+    const int tx1 = p / ts < ntile - 1 ? p / ts : ntile - 1;
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const cx_t<T> *src = patch + pbase * 256 + pr * 16 + (p - tx * ts);
+      for (int sg = tsg[tx]; sg < tsg[tx + 1]; ++sg) {
+        const cx_t<T> v = src[(int64_t)sg * 256];
+        re += v.x;
+        im += v.y;
       }
     }
   }
-  gsum[((int64_t)r * nt + tl) * n * n + pt] = cmake<T>(re, im);
+  hcol[((int64_t)r * nt * ntile + tty) * 16 * n + pr * n + l1] = cmake<T>(re, im);
 }
 
 }  // namespace gt
