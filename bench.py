@@ -94,6 +94,81 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
     return dict(ms=ms, ms_eager=ms_eager, plan_ms=plan_ms, nterms=nterms, ncoef=ncoef, kernels=kern)
 
 
+# solver workload: the group-lasso configuration's shape (d = 12, d_s = 2, N = 48 / 16,
+# 79 terms, 15,415 coefficients, M = 200,000) with 8 lambda values
+SD, SDS, SN, SM, SR = 12, 2, (48, 16), 200000, 8
+FISTA_ITERS, LSQR_ITERS = 200, 50
+
+
+def run_solvers():
+    """FP32 batched (all 8 lambda in one call) vs FP64 plain (one call per lambda) at the same
+    iteration count, on the same FP32-rounded nodes; wall time of the library calls (each
+    builds its plan and synchronises), and the largest relative difference between the two
+    solutions over the lambda grid."""
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    x32 = W.uniform_nodes(W.rng(4, W.P_NODES), SM, SD, "f32")
+    target = W.bspline_target(x32)
+    y = W.add_noise(W.rng(4, W.P_NOISE), target.astype(np.complex128), 0.01)
+    ncoef = lib.gt_num_coeffs(SD, SDS, SN)
+    _, offs = lib.gt_term_table(SD, SDS, SN)
+    p64, k64 = lib.make_problem(SD, SDS, SN, M=SM, R=1, dtype=lib.GT_C128)
+    xd64 = torch.from_numpy(x32.astype(np.float64)).cuda()
+    xd32 = torch.from_numpy(x32).cuda()
+    yd64 = torch.from_numpy(y).cuda()
+    yd32 = torch.from_numpy(y.astype(np.complex64)).cuda()
+    # lambda grids: group lasso from lambda_max = max_u ||(F^H y)_u|| (zero solution above it)
+    g = torch.empty(ncoef, dtype=torch.complex128, device="cuda")
+    lib.grouped_adjoint(p64, xd64, yd64, g)
+    gh = g.cpu().numpy()
+    lam_max = max(float(np.linalg.norm(gh[offs[i]:offs[i + 1]])) for i in range(len(offs) - 1))
+    lam_fista = lam_max * 10.0 ** (-3.0 * np.arange(SR) / (SR - 1))
+    lam_lsqr = np.logspace(-4, 1, SR)
+    out = {"workload": f"group-lasso shape: d={SD}, d_s={SDS}, N={SN[0]}/{SN[1]}, 79 terms, {ncoef} coefficients, "
+                       f"M={SM} uniform nodes, target: 3 one- and 2 two-dimensional B-spline terms + 1% noise, "
+                       f"{SR} lambda values", "timing": "wall time of the one-shot library calls (plan + solve)"}
+
+    def solve(kind, prec, lams, iters):
+        R = len(lams)
+        code = lib.GT_C64 if prec == "f32" else lib.GT_C128
+        prob, keep = lib.make_problem(SD, SDS, SN, M=SM, R=R, dtype=code)
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        yy = (yd32 if prec == "f32" else yd64).repeat(R)
+        xx = xd32 if prec == "f32" else xd64
+        fh = torch.zeros(R * ncoef, dtype=cdt, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "fista":
+            lib.fista_group_lasso(prob, xx, yy, lams, None, iters, 0.0, 1.0, 0.0, fh)
+        else:
+            lib.lsqr_solve(prob, xx, yy, lams, None, iters, 0.0, fh)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, fh.cpu().numpy().reshape(R, ncoef)
+
+    for kind, lams, iters in (("fista", lam_fista, FISTA_ITERS), ("lsqr", lam_lsqr, LSQR_ITERS)):
+        solve(kind, "f32", lams[:1], 2)          # warm-up (code objects, allocator)
+        solve(kind, "f64", lams[:1], 2)
+        t32, f32 = solve(kind, "f32", lams, iters)
+        t64, f64 = 0.0, []
+        for lam in lams:
+            dt, fl = solve(kind, "f64", [lam], iters)
+            t64 += dt
+            f64.append(fl[0])
+        f64 = np.array(f64)
+        nrm = np.linalg.norm(f64, axis=1)
+        # relative difference per lambda; a solution that is zero up to rounding (lambda at
+        # lambda_max) is compared by its absolute difference instead
+        nz = nrm > 1e-10 * nrm.max()
+        rel = [float(np.linalg.norm(f32[j] - f64[j]) / nrm[j]) for j in range(len(lams)) if nz[j]]
+        absz = [float(np.linalg.norm(f32[j] - f64[j])) for j in range(len(lams)) if not nz[j]]
+        out[kind] = {"iters": iters, "lambdas": [float(v) for v in lams], "fp32_batched_s": t32,
+                     "fp64_plain_s": t64, "speedup": t64 / t32,
+                     "max_rel_diff_fp32_vs_fp64": max(rel) if rel else 0.0,
+                     "zero_solutions_abs_diff": max(absz) if absz else None}
+    return out
+
+
 def cpu_baseline(sample_nodes: int):
     """The FP64 oracle (direct sums) on the first `sample_nodes` nodes, forward + adjoint."""
     import workloads as W
@@ -124,6 +199,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=20000, help="nodes for the oracle baseline (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the FP32-batched vs FP64 solver timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -193,6 +269,9 @@ def main():
         r64 = run_gpu("f64", args.steps, args.warmup, profile=False)
         out["fp64"] = {"value": node_terms * args.steps / (r64["ms"] * 1e-3), "unit": "node-terms/s",
                        "ms_per_step": r64["ms"] / args.steps}
+    if not args.no_solvers:
+        print("[bench] solvers", file=sys.stderr, flush=True)
+        out["solvers"] = run_solvers()
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
