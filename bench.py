@@ -6,10 +6,10 @@ samples CN(0, 1), Kaiser-Bessel window m = 6, oversampling 2.  One step = one fo
 one adjoint transform on a plan built once for the node set (inputs resident in HBM).
 
 metric: node-terms/s = 2 * M * |U| / (time of forward + adjoint), FP32 bulk arithmetic.
-Prints one JSON line.  The timed steps run on a non-default stream, where the library
-replays its launch sequences as HIP graphs.  A second timed pass of the same steps launches
-eagerly with a HIP event pair around every kernel launch; the per-kernel durations and the
-roofline of the dominant kernel come from that pass.
+Prints one JSON line.  The timed steps run on a dedicated stream (the library forks its
+order-1 kernels onto a second stream and joins them back).  A second timed pass of the same
+steps runs on one stream with a HIP event pair around every kernel launch; the per-kernel
+durations and the roofline of the dominant kernel come from that pass.
 """
 from __future__ import annotations
 
@@ -60,7 +60,7 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
     yd = torch.from_numpy(y).cuda()
     f_out = torch.empty(M, dtype=cdt, device="cuda")
     a_out = torch.empty(ncoef, dtype=cdt, device="cuda")
-    stream = torch.cuda.Stream()          # a capturable (non-default) stream, default priority
+    stream = torch.cuda.Stream()          # a dedicated stream, default priority
     prob, keep = lib.make_problem(D, DS, NB, M=M, R=1, dtype=code, m=M_WIN, sigma=SIGMA)
 
     def timed(n):
@@ -80,10 +80,10 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
         plan = lib.Plan(prob, xd, keepalive=keep)
         torch.cuda.synchronize()
         plan_ms = (time.perf_counter() - t0) * 1e3
-        for _ in range(max(warmup, 3)):   # the library captures its launch sequences on the second call
+        for _ in range(max(warmup, 1)):
             plan.trafo(fd, f_out)
             plan.adjoint(yd, a_out)
-        ms = timed(steps)                 # graph replays
+        ms = timed(steps)
         kern, ms_eager = {}, None
         if profile:                       # same steps, eager launches with a HIP event pair per launch
             lib.prof_enable(True)
@@ -261,8 +261,8 @@ def main():
                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                            "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl}
         out["kernels_ms"] = {k: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3} for k, v in sorted(kern.items())}
-        out["roofline"]["timing"] = ("per-launch HIP events on the benchmark stream over a second timed pass of the "
-                                     "same steps with eager launches (the first pass replays HIP graphs)")
+        out["roofline"]["timing"] = ("per-launch HIP events over a second timed pass of the same steps on one "
+                                     "stream (the timed pass overlaps the order-1 kernels on a second stream)")
         out["eager_ms_per_step"] = r32["ms_eager"] / args.steps
     if not args.no_fp64:
         print("[bench] fp64", file=sys.stderr, flush=True)

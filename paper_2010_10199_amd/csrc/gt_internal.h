@@ -66,15 +66,6 @@ struct GatherItem {    // a run of sorted positions of one term and right-hand s
   int32_t pad;
 };
 
-struct GraphEntry {    // a captured launch sequence of one plan call, keyed by its buffers
-  int kind = 0;        // 1 = forward, 2 = adjoint
-  const void *in = nullptr;
-  const void *out = nullptr;
-  hipStream_t stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
 struct SpreadItem {    // a range of grid cells of one right-hand side (dataset b of the binning)
   int32_t r, b, c0, c1;
 };
@@ -163,7 +154,6 @@ struct gt_plan {
   size_t lds_limit = 65536;           // LDS per workgroup
   size_t lds_per_cu = 65536;          // LDS per compute unit
   int num_cu = 256;                   // compute units of the device
-  std::vector<gt::GraphEntry> graphs; // forward / adjoint launch sequences replayed as HIP graphs
 };
 
 namespace gt {

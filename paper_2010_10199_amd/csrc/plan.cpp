@@ -250,12 +250,6 @@ int upload_raw(const std::vector<V> &h, V **d) {
 void free_plan(gt_plan *pl) {
   if (!pl) return;
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
-  for (auto &ge : pl->graphs) {
-    if (ge.stream) (void)hipStreamSynchronize(ge.stream);
-    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
-    if (ge.graph) (void)hipGraphDestroy(ge.graph);
-  }
-  pl->graphs.clear();
   if (pl->side) {
     (void)hipStreamSynchronize(pl->side);
     (void)hipStreamDestroy(pl->side);
@@ -294,52 +288,6 @@ void free_plan(gt_plan *pl) {
   delete pl;
 }
 
-// Run a plan call; repeated calls with the same buffers and stream replay a HIP graph of the
-// launch sequence.  The first call of a key runs eagerly (it also sets kernel attributes),
-// the second captures and launches, later ones replay.  Calls on the null stream, calls on
-// a stream the caller is already capturing, and calls while per-launch profiling is on
-// always run eagerly.  The plan's scratch buffers are fixed, so a replay reads the current
-// contents of `in` and overwrites `out` exactly as an eager call does.
-template <class F>
-int run_cached(gt_plan *pl, int kind, const void *in, const void *out, hipStream_t s, F &&launch) {
-  if (s == nullptr || prof_enabled()) return launch();
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return launch();
-  GraphEntry *ge = nullptr;
-  for (auto &g : pl->graphs)
-    if (g.kind == kind && g.in == in && g.out == out && g.stream == s) ge = &g;
-  if (!ge) {
-    if (pl->graphs.size() < 8) {
-      GraphEntry g;
-      g.kind = kind;
-      g.in = in;
-      g.out = out;
-      g.stream = s;
-      pl->graphs.push_back(g);
-    }
-    return launch();
-  }
-  if (!ge->exec) {
-    GT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const int rc = launch();
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
-    if (rc || e != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc ? rc : hip_fail(e, "hipStreamEndCapture");
-    }
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return hip_fail(e, "hipGraphInstantiate");
-    }
-    ge->graph = graph;
-    ge->exec = exec;
-  }
-  GT_HIP(hipGraphLaunch(ge->exec, s));
-  return GT_OK;
-}
 
 // Work list of the order-2 tile spread (needs the binning's tile boundaries on the host).
 // Each (term, dataset) gets ceil(nodes / target) wavefronts over equal runs of its sorted
@@ -830,19 +778,15 @@ int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n) {
 int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream) {
   if (!plan || !fhat || !f) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
-  return run_cached(plan, 1, fhat, f, (hipStream_t)stream, [&] {
-    return plan->dtype == GT_C64 ? launch_forward<float>(plan, fhat, nullptr, f, (hipStream_t)stream)
-                                 : launch_forward<double>(plan, fhat, nullptr, f, (hipStream_t)stream);
-  });
+  return plan->dtype == GT_C64 ? launch_forward<float>(plan, fhat, nullptr, f, (hipStream_t)stream)
+                               : launch_forward<double>(plan, fhat, nullptr, f, (hipStream_t)stream);
 }
 
 int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream) {
   if (!plan || !fhat || !y) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
-  return run_cached(plan, 2, y, fhat, (hipStream_t)stream, [&] {
-    return plan->dtype == GT_C64 ? launch_adjoint<float>(plan, y, nullptr, fhat, (hipStream_t)stream)
-                                 : launch_adjoint<double>(plan, y, nullptr, fhat, (hipStream_t)stream);
-  });
+  return plan->dtype == GT_C64 ? launch_adjoint<float>(plan, y, nullptr, fhat, (hipStream_t)stream)
+                               : launch_adjoint<double>(plan, y, nullptr, fhat, (hipStream_t)stream);
 }
 
 int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, void *stream) {

@@ -171,11 +171,12 @@ def test_invalid_arguments_are_rejected():
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_graph_replay_matches_oracle(prec):
-    """A plan replays its forward and adjoint launch sequences as HIP graphs from the second
-    call on (non-default stream, same buffers).  Change the inputs between calls with
-    ordinary torch work and check every call, eager, captured and replayed, against the
-    oracle."""
+def test_caller_graph_capture_matches_oracle(prec):
+    """Plan calls allocate nothing and synchronise nothing, so a caller can capture them in a
+    graph: here torch.cuda.CUDAGraph drives HIP stream capture, and the library's side
+    stream joins the capture through its fork/join events.  The graph is replayed several
+    times with ordinary torch work on the inputs between replays, and every replay is
+    checked against the oracle."""
     import torch
     from paper_2010_10199_amd import lib
     from tests.gpu_util import cdtype, dtype_code, to_dev
@@ -187,19 +188,29 @@ def test_graph_replay_matches_oracle(prec):
     with torch.cuda.stream(s):
         p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=dtype_code(prec))
         plan = lib.Plan(p, to_dev(x))
-        fd = to_dev(fhat.reshape(-1)).clone()
-        yd = to_dev(y.reshape(-1)).clone()
+        f0 = to_dev(fhat.reshape(-1))
+        y0 = to_dev(y.reshape(-1))
+        fd = f0.clone()
+        yd = y0.clone()
         fo = torch.empty(M, dtype=cdtype(prec), device="cuda")
         ao = torch.empty(iset.n_coeffs, dtype=cdtype(prec), device="cuda")
-        for call in range(5):
-            scale = 1.0 + 0.5 * call
-            fd.copy_(to_dev(fhat.reshape(-1)) * scale)       # eager work on the stream between replays
-            yd.copy_(to_dev(y.reshape(-1)) * (2.0 - 0.25 * call))
-            plan.trafo(fd, fo)
-            plan.adjoint(yd, ao)
-            s.synchronize()
-            e1 = rel(fo.cpu().numpy(), otr.forward(iset, x, fhat[0] * scale))
-            e2 = rel(ao.cpu().numpy(), otr.adjoint(iset, x, y.reshape(-1) * (2.0 - 0.25 * call)))
-            say(f"[graph] {prec} call {call}: forward {e1:.2e} adjoint {e2:.2e}")
-            assert e1 <= tol and e2 <= tol
-        plan.close()
+        plan.trafo(fd, fo)              # eager call first (sets kernel attributes)
+        plan.adjoint(yd, ao)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.trafo(fd, fo)
+        plan.adjoint(yd, ao)
+    for call in range(5):
+        scale, ys = 1.0 + 0.5 * call, 2.0 - 0.25 * call
+        with torch.cuda.stream(s):
+            fd.copy_(f0 * scale)        # eager work on the stream between replays
+            yd.copy_(y0 * ys)
+            g.replay()
+        torch.cuda.synchronize()
+        e1 = rel(fo.cpu().numpy(), otr.forward(iset, x, fhat[0] * scale))
+        e2 = rel(ao.cpu().numpy(), otr.adjoint(iset, x, y.reshape(-1) * ys))
+        say(f"[graph] {prec} replay {call}: forward {e1:.2e} adjoint {e2:.2e}")
+        assert e1 <= tol and e2 <= tol
+    del g
+    plan.close()
