@@ -39,7 +39,7 @@ constexpr int kTileRow = 17;      // padded staging row (elements) of the order-
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
 constexpr int tile_side(int m) { return 17 - 2 * m; }
-constexpr int kPackBS = 256;
+constexpr int kPackBS = 512;   // threads of the pack and adjoint-DFT workgroups
 constexpr int kVecBS = 256;
 
 template <typename T> struct Deg;                   // window polynomial degree per precision

@@ -544,25 +544,38 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
   };
   const int outer = ORDER == 1 ? 1 : (ORDER == 2 ? n : n * n);
   C *G = S;
-  if (ORDER == 2 && ntile > 0) {
+  if (ORDER == 2 && ntile != 0) {
     // order 2 from the tile spread: gsum holds the column-folded patches
     // hcol[ty][pr][l1] of this term; grid row l0 collects the patch rows that land on it
     // (start row of tile row ty plus pr, modulo n), tile rows in order
+    // (staged in LDS after the DFT stages and the roots of unity)
+    // (read from global memory when it does not fit: ntile < 0 asks for that)
+    const bool staged = ntile > 0;
+    ntile = staged ? ntile : -ntile;
     const int mm1 = op.m - 1;
     const C *hc = gsum + ((int64_t)r * nt + tl) * ntile * 16 * n;
+    C *HCl = reinterpret_cast<C *>(smem_raw + stage + 2 * n * sizeof(T));
+    if (staged) {
+      for (int i = tid; i < ntile * 16 * n; i += BS) HCl[i] = hc[i];
+      __syncthreads();
+    }
+    const C *HC = staged ? HCl : hc;
+    int rs0 = (-mm1) % n;
+    rs0 = rs0 < 0 ? rs0 + n : rs0;   // start row of tile row 0
     for (int i = tid; i < n * n; i += BS) {
       const int l0 = i / n, l1 = i - l0 * n;
       T re = 0, im = 0;
+      int rs = rs0;
       for (int ty = 0; ty < ntile; ++ty) {
-        int rs = (ty * ts - mm1) % n;
-        rs = rs < 0 ? rs + n : rs;
-        int pr = (l0 - rs) % n;
+        int pr = l0 - rs;
         pr = pr < 0 ? pr + n : pr;
         for (; pr < 16; pr += n) {
-          const C v = hc[(ty * 16 + pr) * n + l1];
+          const C v = HC[(ty * 16 + pr) * n + l1];
           re += v.x;
           im += v.y;
         }
+        rs += ts;
+        while (rs >= n) rs -= n;
       }
       G[i] = cmake<T>(re, im);
     }
@@ -1081,7 +1094,10 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const int nt = o.term_end - o.term_begin;
     if (nt == 0) continue;
     OrderParams<T> op = order_params<T>(pl, t);
-    const size_t lds = adj_lds<T>(pl, t);
+    // order 2: the adjoint DFT stages the column-folded patches in LDS when they fit
+    const size_t lds_h = t == 2 ? (size_t)o.ntile * 16 * o.n * sizeof(C) : 0;
+    const bool stage_h = t == 2 && adj_lds<T>(pl, t) + lds_h <= pl->lds_limit;
+    const size_t lds = adj_lds<T>(pl, t) + (stage_h ? lds_h : 0);
     if (t == 2) {
       prof_begin(st, "fold_2d");
       const int64_t ncol = (int64_t)nt * o.ntile * 16 * o.n;
@@ -1108,7 +1124,7 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, st, (const C *)o.d_tsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, o.ntile, o.ts);
+                         colscale, pl->ncoef, (C *)fhat, stage_h ? o.ntile : -o.ntile, o.ts);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
