@@ -21,7 +21,10 @@ __global__ __launch_bounds__(kGatherBS) void k_gather_sorted(const T *__restrict
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *G = reinterpret_cast<C *>(smem_raw);
-  const GatherItem it = items[blockIdx.x];
+  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each XCD takes a
+  // contiguous range of items (items are grouped by term), so a term's scattered slot writes
+  // meet in one L2 and leave it as whole lines.
+  const GatherItem it = items[xcd_contiguous(blockIdx.x, gridDim.x)];
   const DevTerm tm = terms[op.term_begin + it.tl];
   const C *src = grids + (int64_t)it.r * grid_total + tm.grid_off;
   const int tid = threadIdx.x;

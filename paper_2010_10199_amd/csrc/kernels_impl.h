@@ -56,6 +56,13 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
   }
 }
 
+// Bijection on [0, nb) giving the blocks of each XCD (block b runs on XCD b mod 8) one
+// contiguous range of logical indices.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7, x = b & 7, j = b >> 3;
+  return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
+
 // ------------------------------------------------------------------ window
 // Grid index of the first window point and the 2m window values of one coordinate.
 // s = n x + n/2 in [0, n) places grid index 0 at x = -1/2; window point j sits at
