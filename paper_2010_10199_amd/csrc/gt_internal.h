@@ -100,7 +100,6 @@ struct OrderHost {
   int32_t ts = 1;                     // cells per tile side of the binning order (order 2: tile_side(m))
   int32_t ntile = 0;                  // tiles per axis, ceil(n / ts)
   int64_t nkey = 0;                   // binning keys per (term, dataset): ntile^order * ts^order
-  int32_t spread_waves = kSpreadWaves;
   int32_t *d_perm = nullptr;          // terms x Mtot sorted node indices
   void *d_xs = nullptr;               // order 2: terms x Mtot x 2 coordinates of the term's axes, sorted order
   // order 2 tile spread: wavefront work list and tile patches (built after the binning)
@@ -152,7 +151,6 @@ struct gt_plan {
   hipStream_t side = nullptr;         // second stream (default priority) for the order-1 kernels
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t lds_limit = 65536;           // LDS per workgroup
-  size_t lds_per_cu = 65536;          // LDS per compute unit
   int num_cu = 256;                   // compute units of the device
 };
 

@@ -389,12 +389,7 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   int lds = 65536;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     pl->lds_limit = (size_t)lds;
-  int lds_cu = 0, ncu = 0;
-  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
-      lds_cu > 0)
-    pl->lds_per_cu = (size_t)lds_cu;
-  else
-    pl->lds_per_cu = pl->lds_limit;
+  int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     pl->num_cu = ncu;
   // side stream for independent per-order kernels (non-blocking, default priority); without
