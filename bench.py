@@ -63,13 +63,15 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
     stream = torch.cuda.Stream()          # a dedicated stream, default priority
     prob, keep = lib.make_problem(D, DS, NB, M=M, R=1, dtype=code, m=M_WIN, sigma=SIGMA)
 
-    def timed(n):
+    def timed(n, fwd=True, adj=True):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(n):
-            plan.trafo(fd, f_out)
-            plan.adjoint(yd, a_out)
+            if fwd:
+                plan.trafo(fd, f_out)
+            if adj:
+                plan.adjoint(yd, a_out)
         ev1.record(stream)
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1)
@@ -84,6 +86,8 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
             plan.trafo(fd, f_out)
             plan.adjoint(yd, a_out)
         ms = timed(steps)
+        ms_fwd = timed(steps, adj=False)
+        ms_adj = timed(steps, fwd=False)
         kern, ms_eager = {}, None
         if profile:                       # same steps, eager launches with a HIP event pair per launch
             lib.prof_enable(True)
@@ -91,81 +95,129 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
             kern = lib.prof_report()
             lib.prof_enable(False)
     plan.close()
-    return dict(ms=ms, ms_eager=ms_eager, plan_ms=plan_ms, nterms=nterms, ncoef=ncoef, kernels=kern)
+    return dict(ms=ms, ms_fwd=ms_fwd, ms_adj=ms_adj, ms_eager=ms_eager, plan_ms=plan_ms, nterms=nterms,
+                ncoef=ncoef, kernels=kern)
 
 
 # solver workload: the group-lasso configuration's shape (d = 12, d_s = 2, N = 48 / 16,
 # 79 terms, 15,415 coefficients, M = 200,000) with 8 lambda values
 SD, SDS, SN, SM, SR = 12, 2, (48, 16), 200000, 8
-FISTA_ITERS, LSQR_ITERS = 200, 50
+TAU = 1e-5                           # accuracy both forms must reach, relative l2 per lambda
+REF_ITERS, REF_TOL = 4000, 1e-13     # FP64 reference runs: iteration cap and stopping tolerance
+KMAX = 2048                          # largest iteration count tried in the search
 
 
 def run_solvers():
-    """FP32 batched (all 8 lambda in one call) vs FP64 plain (one call per lambda) at the same
-    iteration count, on the same FP32-rounded nodes; wall time of the library calls (each
-    builds its plan and synchronises), and the largest relative difference between the two
-    solutions over the lambda grid."""
+    """Time to accuracy TAU of the two solvers, FP32 batched (all lambda values in one call)
+    against FP64 plain (one call per lambda), on the same FP32-rounded nodes and samples.
+
+    1. Reference: FP64, all lambda values in one call, run until the solver's own stopping
+       test reaches REF_TOL (LSQR: normal-equation residual relative to its start; FISTA:
+       relative step).
+    2. Off the clock, for each form the smallest iteration count K whose solution is within
+       TAU of the reference for every lambda it covers (relative l2 error; a reference that
+       is zero, lambda at lambda_max, is compared by the error relative to the largest
+       reference solution), by doubling from 8 and then bisection (the error is taken to
+       stay below TAU once it is).  FP32 batched has one K for the batch; FP64 plain one K
+       per lambda.
+    3. On the clock: each form's calls at its K, wall time of the one-shot library calls
+       (plan creation included; each call synchronises).
+    FISTA runs take one step constant for all, L = 1.05 x a 50-step FP64 power-iteration
+    estimate of ||F||^2 computed once off the clock, with constant steps."""
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
     x32 = W.uniform_nodes(W.rng(4, W.P_NODES), SM, SD, "f32")
     target = W.bspline_target(x32)
-    y = W.add_noise(W.rng(4, W.P_NOISE), target.astype(np.complex128), 0.01)
+    y = W.add_noise(W.rng(4, W.P_NOISE), target.astype(np.complex128), 0.01).astype(np.complex64)
     ncoef = lib.gt_num_coeffs(SD, SDS, SN)
     _, offs = lib.gt_term_table(SD, SDS, SN)
     p64, k64 = lib.make_problem(SD, SDS, SN, M=SM, R=1, dtype=lib.GT_C128)
-    xd64 = torch.from_numpy(x32.astype(np.float64)).cuda()
-    xd32 = torch.from_numpy(x32).cuda()
-    yd64 = torch.from_numpy(y).cuda()
-    yd32 = torch.from_numpy(y.astype(np.complex64)).cuda()
+    xd = {"f32": torch.from_numpy(x32).cuda(), "f64": torch.from_numpy(x32.astype(np.float64)).cuda()}
+    yd = {"f32": torch.from_numpy(y).cuda(), "f64": torch.from_numpy(y.astype(np.complex128)).cuda()}
     # lambda grids: group lasso from lambda_max = max_u ||(F^H y)_u|| (zero solution above it)
     g = torch.empty(ncoef, dtype=torch.complex128, device="cuda")
-    lib.grouped_adjoint(p64, xd64, yd64, g)
+    lib.grouped_adjoint(p64, xd["f64"], yd["f64"], g)
     gh = g.cpu().numpy()
     lam_max = max(float(np.linalg.norm(gh[offs[i]:offs[i + 1]])) for i in range(len(offs) - 1))
-    lam_fista = lam_max * 10.0 ** (-3.0 * np.arange(SR) / (SR - 1))
-    lam_lsqr = np.logspace(-4, 1, SR)
+    lams = {"fista": lam_max * 10.0 ** (-3.0 * np.arange(SR) / (SR - 1)), "lsqr": np.logspace(-4, 1, SR)}
+    plan = lib.Plan(p64, xd["f64"], keepalive=k64)
+    L = 1.05 * plan.norm_estimate(50)
+    plan.close()
     out = {"workload": f"group-lasso shape: d={SD}, d_s={SDS}, N={SN[0]}/{SN[1]}, 79 terms, {ncoef} coefficients, "
                        f"M={SM} uniform nodes, target: 3 one- and 2 two-dimensional B-spline terms + 1% noise, "
-                       f"{SR} lambda values", "timing": "wall time of the one-shot library calls (plan + solve)"}
+                       f"{SR} lambda values", "tau": TAU, "fista_L": L,
+           "timing": "wall time of the one-shot library calls (plan + solve) at the smallest iteration count "
+                     "whose solution is within tau of the converged FP64 reference; counts found off the clock"}
 
-    def solve(kind, prec, lams, iters):
-        R = len(lams)
+    def solve(kind, prec, lam, iters, tol=0.0):
+        R = len(lam)
         code = lib.GT_C64 if prec == "f32" else lib.GT_C128
         prob, keep = lib.make_problem(SD, SDS, SN, M=SM, R=R, dtype=code)
         cdt = torch.complex64 if prec == "f32" else torch.complex128
-        yy = (yd32 if prec == "f32" else yd64).repeat(R)
-        xx = xd32 if prec == "f32" else xd64
+        yy = yd[prec].repeat(R)
         fh = torch.zeros(R * ncoef, dtype=cdt, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if kind == "fista":
-            lib.fista_group_lasso(prob, xx, yy, lams, None, iters, 0.0, 1.0, 0.0, fh)
+            info = lib.fista_group_lasso(prob, xd[prec], yy, lam, None, iters, L, 1.0, tol, fh)
         else:
-            lib.lsqr_solve(prob, xx, yy, lams, None, iters, 0.0, fh)
+            info = lib.lsqr_solve(prob, xd[prec], yy, lam, None, iters, tol, fh)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, fh.cpu().numpy().reshape(R, ncoef)
+        dt = time.perf_counter() - t0
+        del keep
+        print(f"[bench]   {kind} {prec} R={R} iters={iters} {dt:.3f} s", file=sys.stderr, flush=True)
+        return dt, fh.cpu().numpy().reshape(R, ncoef).astype(np.complex128), info
 
-    for kind, lams, iters in (("fista", lam_fista, FISTA_ITERS), ("lsqr", lam_lsqr, LSQR_ITERS)):
-        solve(kind, "f32", lams[:1], 2)          # warm-up (code objects, allocator)
-        solve(kind, "f64", lams[:1], 2)
-        t32, f32 = solve(kind, "f32", lams, iters)
-        t64, f64 = 0.0, []
-        for lam in lams:
-            dt, fl = solve(kind, "f64", [lam], iters)
+    def smallest(ok):
+        """Smallest K in [1, KMAX] with ok(K), assuming ok stays true past the first K."""
+        hi = 8
+        while not ok(hi):
+            if hi >= KMAX:
+                return None
+            hi = min(2 * hi, KMAX)
+        lo = hi // 2 if hi > 8 else 0     # ok(lo) is false (or lo = 0)
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if ok(mid):
+                hi = mid
+            else:
+                lo = mid
+        return hi
+
+    for kind in ("fista", "lsqr"):
+        lam = lams[kind]
+        solve(kind, "f32", lam[:1], 2)           # warm-up (code objects, allocator)
+        solve(kind, "f64", lam[:1], 2)
+        _, ref, rinfo = solve(kind, "f64", lam, REF_ITERS, REF_TOL)
+        nrm = np.linalg.norm(ref, axis=1)
+        scale = np.where(nrm > 1e-10 * nrm.max(), nrm, nrm.max())
+
+        def err(sol, idx):
+            return float(max(np.linalg.norm(sol[k] - ref[j]) / scale[j] for k, j in enumerate(idx)))
+
+        every = list(range(SR))
+        k32 = smallest(lambda K: err(solve(kind, "f32", lam, K)[1], every) <= TAU)
+        k64 = [smallest(lambda K, j=j: err(solve(kind, "f64", lam[j:j + 1], K)[1], [j]) <= TAU)
+               for j in range(SR)]
+        res = {"lambdas": [float(v) for v in lam],
+               "reference": {"form": "FP64, all lambda values in one call", "iters": max(i.iters for i in rinfo),
+                             "tol": REF_TOL, "final_test_value": max(i.resid for i in rinfo),
+                             "converged": all(i.flags & 1 for i in rinfo)}}
+        if k32 is None or None in k64:
+            res["error"] = f"tau not reached within {KMAX} iterations"
+            out[kind] = res
+            continue
+        t32, s32, _ = solve(kind, "f32", lam, k32)
+        t64, e64 = 0.0, 0.0
+        for j in range(SR):
+            dt, sj, _ = solve(kind, "f64", lam[j:j + 1], k64[j])
             t64 += dt
-            f64.append(fl[0])
-        f64 = np.array(f64)
-        nrm = np.linalg.norm(f64, axis=1)
-        # relative difference per lambda; a solution that is zero up to rounding (lambda at
-        # lambda_max) is compared by its absolute difference instead
-        nz = nrm > 1e-10 * nrm.max()
-        rel = [float(np.linalg.norm(f32[j] - f64[j]) / nrm[j]) for j in range(len(lams)) if nz[j]]
-        absz = [float(np.linalg.norm(f32[j] - f64[j])) for j in range(len(lams)) if not nz[j]]
-        out[kind] = {"iters": iters, "lambdas": [float(v) for v in lams], "fp32_batched_s": t32,
-                     "fp64_plain_s": t64, "speedup": t64 / t32,
-                     "max_rel_diff_fp32_vs_fp64": max(rel) if rel else 0.0,
-                     "zero_solutions_abs_diff": max(absz) if absz else None}
+            e64 = max(e64, err(sj, [j]))
+        res.update({"fp32_batched": {"iters": k32, "s": t32, "max_rel_err": err(s32, every)},
+                    "fp64_plain": {"iters_per_lambda": k64, "s": t64, "max_rel_err": e64},
+                    "speedup": t64 / t32})
+        out[kind] = res
     return out
 
 
@@ -239,6 +291,10 @@ def main():
                                "56 terms, 10,756 coefficients, M=50,000 uniform nodes, Kaiser-Bessel m=6, sigma=2",
                    "d": D, "ds": DS, "N": list(NB), "M": M, "m": M_WIN, "sigma": SIGMA,
                    "plan_ms": round(r32["plan_ms"], 3)},
+        "forward": {"value": M * r32["nterms"] * args.steps / (r32["ms_fwd"] * 1e-3), "unit": "node-terms/s",
+                    "ms": r32["ms_fwd"] / args.steps},
+        "adjoint": {"value": M * r32["nterms"] * args.steps / (r32["ms_adj"] * 1e-3), "unit": "node-terms/s",
+                    "ms": r32["ms_adj"] / args.steps},
     }
     # dominant kernel and its roofline
     kern = r32["kernels"]
@@ -268,7 +324,8 @@ def main():
         print("[bench] fp64", file=sys.stderr, flush=True)
         r64 = run_gpu("f64", args.steps, args.warmup, profile=False)
         out["fp64"] = {"value": node_terms * args.steps / (r64["ms"] * 1e-3), "unit": "node-terms/s",
-                       "ms_per_step": r64["ms"] / args.steps}
+                       "ms_per_step": r64["ms"] / args.steps, "forward_ms": r64["ms_fwd"] / args.steps,
+                       "adjoint_ms": r64["ms_adj"] / args.steps}
     if not args.no_solvers:
         print("[bench] solvers", file=sys.stderr, flush=True)
         out["solvers"] = run_solvers()
