@@ -35,6 +35,7 @@ constexpr int kSpreadWaves = 8;   // wavefronts per spread workgroup
 constexpr int kTileBatch = 32;    // nodes per batch of the order-2 tile spread
 constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 tile spread
 constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
+constexpr double kCellGatherFill = 0.6;   // smallest lane fill of the cell gather's work items
 
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
@@ -66,6 +67,13 @@ struct GatherItem {    // a run of sorted positions of one term and right-hand s
   int32_t pad;
 };
 
+struct CellItem {       // up to 64 sorted positions of one grid cell of one term (and dataset)
+  int32_t q0;          // first position in the order's perm array
+  int32_t count;       // 1..64
+  int32_t tl;          // term index within the order
+  int32_t r;           // dataset when ragged, else 0 (the launch adds the right-hand side)
+};
+
 struct SpreadItem {    // a range of grid cells of one right-hand side (dataset b of the binning)
   int32_t r, b, c0, c1;
 };
@@ -95,6 +103,9 @@ struct OrderHost {
   std::vector<struct GatherItem> gitems;
   struct GatherItem *d_gitems = nullptr;
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
+  std::vector<CellItem> citems;       // cell gather work items (empty: k_gather_sorted is used)
+  CellItem *d_citems = nullptr;
+  std::vector<int32_t> citem_begin;   // per term of the order, +1
   // node binning of this order (per term, by cell) and spread work items
   int64_t ncell = 0;                  // n^order
   int32_t ts = 1;                     // cells per tile side of the binning order (order 2: tile_side(m))

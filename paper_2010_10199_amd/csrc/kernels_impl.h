@@ -987,9 +987,36 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
       const OrderHost &o = pl->ord[t];
       const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
       if (tb >= te) continue;
+      OrderParams<T> op = order_params<T>(pl, t);
+      if (!o.citems.empty()) {   // cell gather: one wavefront per run of a cell's nodes
+        const int c0 = o.citem_begin[tb - o.term_begin], c1 = o.citem_begin[te - o.term_begin];
+        if (c1 <= c0) continue;
+        const int64_t vstride = pl->ragged ? 0 : pl->M;
+        dim3 grid((unsigned)((c1 - c0 + 3) / 4), pl->ragged ? 1u : (unsigned)pl->R);
+        prof_begin(st, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
+#define GT_LAUNCH_CELL(MH)                                                                                          \
+  {                                                                                                                 \
+    if (t == 1)                                                                                                     \
+      hipLaunchKernelGGL((k_gather_cell<T, 1, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
+                         o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
+                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+    else if (t == 2)                                                                                                \
+      hipLaunchKernelGGL((k_gather_cell<T, 2, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
+                         o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
+                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_gather_cell<T, 3, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
+                         o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
+                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+  }
+        GT_DISPATCH_M(o.m, GT_LAUNCH_CELL)
+#undef GT_LAUNCH_CELL
+        prof_end(st);
+        if (int rc = check_launch("k_gather_cell")) return rc;
+        continue;
+      }
       const int i0 = o.gitem_begin[tb - o.term_begin], i1 = o.gitem_begin[te - o.term_begin];
       if (i1 <= i0) continue;
-      OrderParams<T> op = order_params<T>(pl, t);
       const size_t lds = (size_t)o.gsize * sizeof(C);
       const GatherItem *items = o.d_gitems + i0;
       const int64_t vstride = pl->ragged ? 0 : pl->M;

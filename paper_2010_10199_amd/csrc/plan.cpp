@@ -273,6 +273,7 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_roots, nullptr);
     dev_free(o.d_poly, nullptr);
     dev_free(o.d_gitems, nullptr);
+    dev_free(o.d_citems, nullptr);
     dev_free(o.d_sitems, nullptr);
     dev_free(o.d_sitem_begin, nullptr);
     dev_free(o.d_gpart, nullptr);
@@ -354,6 +355,52 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
   const size_t csz = 2 * pl->rsize;
   if ((rc = dev_alloc(&o.d_patch, (size_t)reff * std::max<int64_t>(1, nseg) * 256 * csz, s))) return rc;
   if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * o.ntile * 16 * o.n * csz, s))) return rc;
+  return GT_OK;
+}
+
+// Cell gather items (k_gather_cell): runs of at most 64 sorted positions inside one grid
+// cell of one term and dataset.  Kept only when the runs fill at least kCellGatherFill of the
+// lanes they occupy (otherwise the order keeps k_gather_sorted, whose workgroups take any 1024
+// consecutive positions).
+static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
+  for (int t = 1; t <= pl->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    o.citems.clear();
+    o.citem_begin.clear();
+    const int nt = o.term_end - o.term_begin;
+    if (nt == 0 || (int64_t)nt * pl->Mtot >= (int64_t(1) << 31)) continue;
+    const int B = pl->ragged ? pl->R : 1;
+    const int64_t nkeys = (int64_t)nt * B * o.nkey + 1;
+    std::vector<int64_t> cs(nkeys);
+    hipError_t e = hipMemcpyAsync(cs.data(), o.d_cstart, nkeys * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "cell boundaries");
+    std::vector<CellItem> items;
+    std::vector<int32_t> begin(nt + 1, 0);
+    for (int tl = 0; tl < nt; ++tl) {
+      begin[tl] = (int32_t)items.size();
+      for (int b = 0; b < B; ++b) {
+        const int64_t key0 = ((int64_t)tl * B + b) * o.nkey;
+        for (int64_t k = 0; k < o.nkey; ++k) {
+          const int64_t c0 = cs[key0 + k], c1 = cs[key0 + k + 1];
+          for (int64_t q = c0; q < c1; q += 64) {
+            CellItem ci;
+            ci.q0 = (int32_t)q;
+            ci.count = (int32_t)std::min<int64_t>(64, c1 - q);
+            ci.tl = tl;
+            ci.r = pl->ragged ? b : 0;
+            items.push_back(ci);
+          }
+        }
+      }
+    }
+    begin[nt] = (int32_t)items.size();
+    const double fill = items.empty() ? 0.0 : (double)((int64_t)nt * pl->Mtot) / (64.0 * (double)items.size());
+    if (fill < kCellGatherFill || items.size() >= (size_t(1) << 31)) continue;
+    o.citems.swap(items);
+    o.citem_begin.swap(begin);
+    if (int rc = upload_raw(o.citems, &o.d_citems)) return rc;
+  }
   return GT_OK;
 }
 
@@ -645,6 +692,7 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     if (e2 != hipSuccess) rc = hip_fail(e2, "node binning");
   }
   if (rc == GT_OK && p->ds >= 2) rc = setup_tile_spread(pl, s);
+  if (rc == GT_OK && p->ds >= 1) rc = setup_cell_gather(pl, s);
   if (rc) {
     free_plan(pl);
     return rc;
