@@ -439,11 +439,16 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     pl->num_cu = ncu;
+  // The fork/join events order two streams of this device only, so they skip the
+  // system-scope fence (an L2 write-back that would make the data visible to the host):
+  // kernels release their results at device scope when they end, which is what the other
+  // stream's kernels need.
+  constexpr unsigned kSyncEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
   // side stream for independent per-order kernels (non-blocking, default priority); without
   // it everything runs on the caller's stream
   if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&pl->ev_fork, kSyncEventFlags) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_join, kSyncEventFlags) != hipSuccess) {
     (void)hipGetLastError();
     if (pl->side) (void)hipStreamDestroy(pl->side);
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
