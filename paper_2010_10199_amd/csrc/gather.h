@@ -73,16 +73,15 @@ __global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, i
   const int n = op.n, P = op.P;
   const bool act = l < it.count;
   const int32_t node = perm[it.q0 + (act ? l : 0)];
-  int f0, f1 = 0, f2 = 0;
+  // the item's cell (the binning's cell of each of its nodes); offsets z relative to it
+  const int c0 = it.cell[0], c1 = it.cell[1], c2 = it.cell[2];
+  const T nf = (T)n;
   T p0[W], p1[W], p2[W];
-  window_values<T, MH>(frac_offset<T>(xT[(int64_t)tm.c0 * Mx + node], n, f0) * (T)2 - (T)1, op.poly, p0);
+  window_values<T, MH>(fma(nf, xT[(int64_t)tm.c0 * Mx + node], (T)(n / 2 - c0)) * (T)2 - (T)1, op.poly, p0);
   if (ORDER >= 2)
-    window_values<T, MH>(frac_offset<T>(xT[(int64_t)tm.c1 * Mx + node], n, f1) * (T)2 - (T)1, op.poly, p1);
+    window_values<T, MH>(fma(nf, xT[(int64_t)tm.c1 * Mx + node], (T)(n / 2 - c1)) * (T)2 - (T)1, op.poly, p1);
   if (ORDER >= 3)
-    window_values<T, MH>(frac_offset<T>(xT[(int64_t)tm.c2 * Mx + node], n, f2) * (T)2 - (T)1, op.poly, p2);
-  // the cell, the same for every node of the item (lane 0 always holds a node)
-  const int c0 = __builtin_amdgcn_readfirstlane(f0), c1 = __builtin_amdgcn_readfirstlane(f1),
-            c2 = __builtin_amdgcn_readfirstlane(f2);
+    window_values<T, MH>(fma(nf, xT[(int64_t)tm.c2 * Mx + node], (T)(n / 2 - c2)) * (T)2 - (T)1, op.poly, p2);
   T re = 0, im = 0;
   if (ORDER == 1) {
     const C *g = G + c0;
@@ -135,6 +134,130 @@ __global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, i
     }
   }
   if (act) slots[(int64_t)(slot_base + op.term_begin + it.tl) * Vtot + (int64_t)r * vstride + node] = cmake<T>(re, im);
+}
+
+// ------------------------------------------------------------------ order-2 gather in the
+// polynomial basis of the window (FP32).
+// Window point j of a node in cell f is the polynomial psi_j(z) = sum_q c[j][q] z^q of the
+// node's offset z = 2 (n x + n/2 - f) - 1, the same polynomials for every cell.  The gather
+// sum of a node in cell (f0, f1) is therefore a bivariate polynomial in (z0, z1) whose
+// coefficients depend on the cell only:
+//   f = sum_{a,j} psi_a(z0) psi_j(z1) G[f0-m+1+a][f1+j] = sum_{q',q} z0^q' z1^q K[q'][q],
+//   K[q'][q] = sum_{a,j} c[a][q'] c[j][q] G[f0-m+1+a][f1+j]   (rows mod n, halo columns).
+// k_poly_coef2 computes K for every cell of every term (two separable passes over the
+// grid, the window coefficients as scalar operands); k_gather_poly2 then evaluates the
+// polynomial per node: (D+1) Horner sums in z1 and one in z0, 2 (D+1) D FMAs instead of the
+// (2m)^2 complex window terms and the 4m window evaluations of the direct sum.
+
+// Workgroup = (term, right-hand side, kPolyRows cell rows).  LDS holds the first pass,
+// H[hr][f1][q] = sum_j c[j][q] G[row(hr)][f1 + j] for the 2m - 1 + kPolyRows grid rows the
+// cell rows need; the second pass writes K[f0][f1][q'][q] = sum_a c[a][q'] H[f0 - F0 + a][f1][q]
+// (kpoly layout: (r, term, f0, f1) blocks of (D+1)^2 complex, q fastest).
+template <int MH>
+__global__ __launch_bounds__(512) void k_poly_coef2(const cx_t<float> *__restrict__ grids, int64_t grid_total,
+                                                    const DevTerm *__restrict__ terms, OrderParams<float> op,
+                                                    int nslab, cx_t<float> *__restrict__ kpoly) {
+  using C = cx_t<float>;
+  constexpr int W = 2 * MH, NQ = Deg<float>::value + 1, HR = kPolyRows + W - 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = op.n, P = op.P, mm1 = MH - 1;
+  C *H = reinterpret_cast<C *>(smem_raw);   // HR x n x NQ
+  C *Gs = H + HR * n * NQ;                  // HR x P: the grid rows of the first pass
+  const int nt = op.term_end - op.term_begin;
+  const int tl = blockIdx.x / nslab, F0 = (blockIdx.x - tl * nslab) * kPolyRows, r = blockIdx.y;
+  const DevTerm tm = terms[op.term_begin + tl];
+  const C *__restrict__ G = grids + (int64_t)r * grid_total + tm.grid_off;
+  const float *__restrict__ c = op.poly;   // W x NQ, all 2m points
+  for (int i = threadIdx.x; i < HR * P; i += blockDim.x) {
+    const int hr = i / P, p = i - hr * P;
+    int row = (F0 - mm1 + hr) % n;
+    row = row < 0 ? row + n : row;
+    Gs[i] = G[(int64_t)row * P + p];
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < HR * n; task += blockDim.x) {
+    const int hr = task / n, f1 = task - hr * n;
+    const C *g = Gs + hr * P + f1;
+    C gv[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) gv[j] = g[j];
+    C *h = H + (hr * n + f1) * NQ;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        sr = fmaf(c[j * NQ + q], gv[j].x, sr);
+        si = fmaf(c[j * NQ + q], gv[j].y, si);
+      }
+      h[q] = cmake<float>(sr, si);
+    }
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < kPolyRows * n * NQ; task += blockDim.x) {
+    const int q = task % NQ, rest = task / NQ, f1 = rest % n, fr = rest / n, f0 = F0 + fr;
+    if (f0 >= n) continue;
+    C hv[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) hv[a] = H[((fr + a) * n + f1) * NQ + q];
+    C *dst = kpoly + ((((int64_t)r * nt + tl) * n + f0) * n + f1) * (NQ * NQ) + q;
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        sr = fmaf(c[a * NQ + qq], hv[a].x, sr);
+        si = fmaf(c[a * NQ + qq], hv[a].y, si);
+      }
+      dst[qq * NQ] = cmake<float>(sr, si);
+    }
+  }
+}
+
+// One wavefront per run of at most 64 nodes of one cell (the cell gather's work items): the
+// cell's (D+1)^2 coefficients are read with scalar loads and enter the lanes' Horner sums
+// as scalar operands; the node coordinates come from the binning's sorted copy (xs, two
+// per position).  Results go to the term's output slot as in k_gather_sorted.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ xs,
+                                                      const CellItem *__restrict__ items, int nitems,
+                                                      const int32_t *__restrict__ perm,
+                                                      OrderParams<float> op,
+                                                      const cx_t<float> *__restrict__ kpoly, int64_t vstride,
+                                                      int slot_base, cx_t<float> *__restrict__ slots, int64_t Vtot) {
+  static_assert(std::is_same<T, float>::value, "FP32 only");
+  using C = cx_t<float>;
+  constexpr int NQ = Deg<float>::value + 1;
+  const int l = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ii = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wv;
+  if (ii >= nitems) return;   // whole wavefront; no workgroup barrier follows
+  const CellItem it = items[ii];
+  const int r = it.r + (int)blockIdx.y;
+  const int n = op.n, nt = op.term_end - op.term_begin;
+  const bool act = l < it.count;
+  const int c0 = it.cell[0], c1 = it.cell[1];
+  const C *__restrict__ K = kpoly + ((((int64_t)r * nt + it.tl) * n + c0) * n + c1) * (NQ * NQ);
+  const int q = it.q0 + (act ? l : 0);
+  const int32_t node = perm[q];
+  const cx_t<float> xv = reinterpret_cast<const cx_t<float> *>(xs)[q];
+  const float nf = (float)n;
+  const float z0 = fmaf(nf, xv.x, (float)(n / 2 - c0)) * 2.f - 1.f;
+  const float z1 = fmaf(nf, xv.y, (float)(n / 2 - c1)) * 2.f - 1.f;
+  float fr = 0.f, fi = 0.f;
+#pragma unroll
+  for (int qq = NQ - 1; qq >= 0; --qq) {
+    const C *kr = K + qq * NQ;
+    float tr = kr[NQ - 1].x, ti = kr[NQ - 1].y;
+#pragma unroll
+    for (int q = NQ - 2; q >= 0; --q) {
+      tr = fmaf(tr, z1, kr[q].x);
+      ti = fmaf(ti, z1, kr[q].y);
+    }
+    fr = fmaf(fr, z0, tr);
+    fi = fmaf(fi, z0, ti);
+  }
+  if (act) slots[(int64_t)(slot_base + op.term_begin + it.tl) * Vtot + (int64_t)r * vstride + node] = cmake<float>(fr, fi);
 }
 
 }  // namespace gt

@@ -36,6 +36,8 @@ constexpr int kTileBatch = 32;    // nodes per batch of the order-2 tile spread
 constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 tile spread
 constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
 constexpr double kCellGatherFill = 0.6;   // smallest lane fill of the cell gather's work items
+constexpr size_t kPolyMaxBytes = size_t(1) << 30;   // largest coefficient buffer of the order-2 polynomial gather
+constexpr int kPolyRows = 2;       // cell rows per workgroup of k_poly_coef2
 
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
@@ -72,6 +74,8 @@ struct CellItem {       // up to 64 sorted positions of one grid cell of one ter
   int32_t count;       // 1..64
   int32_t tl;          // term index within the order
   int32_t r;           // dataset when ragged, else 0 (the launch adds the right-hand side)
+  int32_t cell[3];     // the cell's grid indices along the term's axes (unused axes 0)
+  int32_t pad;
 };
 
 struct SpreadItem {    // a range of grid cells of one right-hand side (dataset b of the binning)
@@ -105,6 +109,7 @@ struct OrderHost {
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
   std::vector<CellItem> citems;       // cell gather work items (empty: k_gather_sorted is used)
   CellItem *d_citems = nullptr;
+  void *d_kpoly = nullptr;            // order 2 FP32: per-cell window-polynomial coefficients of the grids (k_poly_coef2)
   std::vector<int32_t> citem_begin;   // per term of the order, +1
   // node binning of this order (per term, by cell) and spread work items
   int64_t ncell = 0;                  // n^order

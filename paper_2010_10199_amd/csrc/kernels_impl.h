@@ -985,6 +985,25 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
       if (blk == 0)
         if (int rc = launch_pack<T>(pl, fhat, colscale, st, t)) return rc;
       const OrderHost &o = pl->ord[t];
+      if constexpr (std::is_same<T, float>::value) {
+        if (blk == 0 && t == 2 && o.d_kpoly) {   // per-cell polynomial coefficients of the grids
+          const OrderParams<float> opf = order_params<float>(pl, 2);
+          const int nt2 = o.term_end - o.term_begin, nslab = (o.n + kPolyRows - 1) / kPolyRows;
+          const size_t plds = (size_t)(kPolyRows + 2 * o.m - 1) * (o.n * (Deg<float>::value + 1) + o.P) * sizeof(C);
+          dim3 pgrid((unsigned)(nt2 * nslab), (unsigned)pl->R);
+          prof_begin(st, "poly_coef_2d");
+#define GT_LAUNCH_PCOEF(MH)                                                                                      \
+  {                                                                                                              \
+    if (int rc = set_lds(k_poly_coef2<MH>, plds)) return rc;                                                     \
+    hipLaunchKernelGGL((k_poly_coef2<MH>), pgrid, dim3(512), plds, st, (const C *)pl->d_grid, pl->grid_total,    \
+                       pl->d_terms, opf, nslab, (C *)o.d_kpoly);                                                 \
+  }
+          GT_DISPATCH_M(o.m, GT_LAUNCH_PCOEF)
+#undef GT_LAUNCH_PCOEF
+          prof_end(st);
+          if (int rc = check_launch("k_poly_coef2")) return rc;
+        }
+      }
       const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
       if (tb >= te) continue;
       OrderParams<T> op = order_params<T>(pl, t);
@@ -994,6 +1013,16 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
         const int64_t vstride = pl->ragged ? 0 : pl->M;
         dim3 grid((unsigned)((c1 - c0 + 3) / 4), pl->ragged ? 1u : (unsigned)pl->R);
         prof_begin(st, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
+        if constexpr (std::is_same<T, float>::value) {
+          if (t == 2 && o.d_kpoly) {
+            hipLaunchKernelGGL((k_gather_poly2<T>), grid, dim3(256), 0, st, (const T *)o.d_xs, o.d_citems + c0,
+                               c1 - c0, o.d_perm, op, (const C *)o.d_kpoly, vstride, -g0,
+                               (C *)pl->d_fpart, pl->Vtot);
+            prof_end(st);
+            if (int rc = check_launch("k_gather_poly2")) return rc;
+            continue;
+          }
+        }
 #define GT_LAUNCH_CELL(MH)                                                                                          \
   {                                                                                                                 \
     if (t == 1)                                                                                                     \

@@ -274,6 +274,7 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_poly, nullptr);
     dev_free(o.d_gitems, nullptr);
     dev_free(o.d_citems, nullptr);
+    dev_free(o.d_kpoly, nullptr);
     dev_free(o.d_sitems, nullptr);
     dev_free(o.d_sitem_begin, nullptr);
     dev_free(o.d_gpart, nullptr);
@@ -383,12 +384,29 @@ static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
         const int64_t key0 = ((int64_t)tl * B + b) * o.nkey;
         for (int64_t k = 0; k < o.nkey; ++k) {
           const int64_t c0 = cs[key0 + k], c1 = cs[key0 + k + 1];
+          if (c1 <= c0) continue;
+          // the cell of binning key k (order 2 numbers cells tile-major, see the binning)
+          int32_t cell[3] = {0, 0, 0};
+          if (t == 1) {
+            cell[0] = (int32_t)k;
+          } else if (t == 2) {
+            const int64_t TT = (int64_t)o.ts * o.ts, tile = k / TT, rem = k - tile * TT;
+            cell[0] = (int32_t)((tile / o.ntile) * o.ts + rem / o.ts);
+            cell[1] = (int32_t)((tile % o.ntile) * o.ts + rem % o.ts);
+          } else {
+            cell[0] = (int32_t)(k / ((int64_t)o.n * o.n));
+            cell[1] = (int32_t)((k / o.n) % o.n);
+            cell[2] = (int32_t)(k % o.n);
+          }
           for (int64_t q = c0; q < c1; q += 64) {
-            CellItem ci;
+            CellItem ci{};
             ci.q0 = (int32_t)q;
             ci.count = (int32_t)std::min<int64_t>(64, c1 - q);
             ci.tl = tl;
             ci.r = pl->ragged ? b : 0;
+            ci.cell[0] = cell[0];
+            ci.cell[1] = cell[1];
+            ci.cell[2] = cell[2];
             items.push_back(ci);
           }
         }
@@ -400,6 +418,15 @@ static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
     o.citems.swap(items);
     o.citem_begin.swap(begin);
     if (int rc = upload_raw(o.citems, &o.d_citems)) return rc;
+    // order 2, FP32: the gather evaluates per-cell polynomials (k_poly_coef2 / k_gather_poly2)
+    // when their coefficients take at most kPolyMaxBytes and the first pass fits in LDS
+    if (t == 2 && pl->dtype == GT_C64) {
+      constexpr int NQ = Deg<float>::value + 1;
+      const size_t bytes = (size_t)pl->R * nt * o.n * o.n * NQ * NQ * 2 * sizeof(float);
+      const size_t lds = (size_t)(kPolyRows + 2 * o.m - 1) * (o.n * NQ + o.P) * 2 * sizeof(float);
+      if (bytes <= kPolyMaxBytes && lds <= pl->lds_limit)
+        if (int rc = dev_alloc(&o.d_kpoly, bytes, s)) return rc;
+    }
   }
   return GT_OK;
 }
