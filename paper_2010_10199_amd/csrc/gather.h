@@ -144,44 +144,32 @@ __global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, i
 // coefficients depend on the cell only:
 //   f = sum_{a,j} psi_a(z0) psi_j(z1) G[f0-m+1+a][f1+j] = sum_{q',q} z0^q' z1^q K[q'][q],
 //   K[q'][q] = sum_{a,j} c[a][q'] c[j][q] G[f0-m+1+a][f1+j]   (rows mod n, halo columns).
-// k_poly_coef2 computes K for every cell of every term (two separable passes over the
-// grid, the window coefficients as scalar operands); k_gather_poly2 then evaluates the
+// k_pack_poly2 computes K for every cell of every term (the pack's DFT, then two separable
+// passes, the window coefficients as scalar operands); k_gather_poly2 then evaluates the
 // polynomial per node: (D+1) Horner sums in z1 and one in z0, 2 (D+1) D FMAs instead of the
 // (2m)^2 complex window terms and the 4m window evaluations of the direct sum.
 
-// Workgroup = (term, right-hand side, kPolyRows cell rows).  LDS holds the first pass,
-// H[hr][f1][q] = sum_j c[j][q] G[row(hr)][f1 + j] for the 2m - 1 + kPolyRows grid rows the
-// cell rows need; the second pass writes K[f0][f1][q'][q] = sum_a c[a][q'] H[f0 - F0 + a][f1][q]
-// (kpoly layout: (r, term, f0, f1) blocks of (D+1)^2 complex, q fastest).
+// The two separable passes for the cell rows F0 .. F0 + kPolyRows - 1 of one term and
+// right-hand side, from the grid rows they need, Gs[hr] = row (F0 - m + 1 + hr) mod n
+// (HR = kPolyRows + 2m - 1 rows of P halo columns, in LDS):
+//   H[hr][f1][q] = sum_j c[j][q] Gs[hr][f1 + j]               (LDS, row stride NQ + 1)
+//   K[f0][f1][q'][q] = sum_a c[a][q'] H[f0 - F0 + a][f1][q]    (kpoly: (r, term, f0, f1) blocks
+//                                                               of NQ^2 complex, q fastest)
+// The window coefficients c (2m x NQ, all points) are uniform scalar operands.  Ends with the
+// second pass (callers place a barrier between their writes of Gs and this call).
 template <int MH>
-__global__ __launch_bounds__(512) void k_poly_coef2(const cx_t<float> *__restrict__ grids, int64_t grid_total,
-                                                    const DevTerm *__restrict__ terms, OrderParams<float> op,
-                                                    int nslab, cx_t<float> *__restrict__ kpoly) {
+__device__ __forceinline__ void poly2_passes(const cx_t<float> *Gs, cx_t<float> *H, int n, int P,
+                                             const float *__restrict__ c, int F0, int nt, int tl, int r,
+                                             cx_t<float> *__restrict__ kpoly) {
   using C = cx_t<float>;
-  constexpr int W = 2 * MH, NQ = Deg<float>::value + 1, HR = kPolyRows + W - 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = op.n, P = op.P, mm1 = MH - 1;
-  C *H = reinterpret_cast<C *>(smem_raw);   // HR x n x NQ
-  C *Gs = H + HR * n * NQ;                  // HR x P: the grid rows of the first pass
-  const int nt = op.term_end - op.term_begin;
-  const int tl = blockIdx.x / nslab, F0 = (blockIdx.x - tl * nslab) * kPolyRows, r = blockIdx.y;
-  const DevTerm tm = terms[op.term_begin + tl];
-  const C *__restrict__ G = grids + (int64_t)r * grid_total + tm.grid_off;
-  const float *__restrict__ c = op.poly;   // W x NQ, all 2m points
-  for (int i = threadIdx.x; i < HR * P; i += blockDim.x) {
-    const int hr = i / P, p = i - hr * P;
-    int row = (F0 - mm1 + hr) % n;
-    row = row < 0 ? row + n : row;
-    Gs[i] = G[(int64_t)row * P + p];
-  }
-  __syncthreads();
+  constexpr int W = 2 * MH, NQ = Deg<float>::value + 1, HR = kPolyRows + W - 1, HS = NQ + 1;
   for (int task = threadIdx.x; task < HR * n; task += blockDim.x) {
     const int hr = task / n, f1 = task - hr * n;
     const C *g = Gs + hr * P + f1;
     C gv[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) gv[j] = g[j];
-    C *h = H + (hr * n + f1) * NQ;
+    C *hp = H + (hr * n + f1) * HS;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       float sr = 0.f, si = 0.f;
@@ -190,7 +178,7 @@ __global__ __launch_bounds__(512) void k_poly_coef2(const cx_t<float> *__restric
         sr = fmaf(c[j * NQ + q], gv[j].x, sr);
         si = fmaf(c[j * NQ + q], gv[j].y, si);
       }
-      h[q] = cmake<float>(sr, si);
+      hp[q] = cmake<float>(sr, si);
     }
   }
   __syncthreads();
@@ -199,7 +187,7 @@ __global__ __launch_bounds__(512) void k_poly_coef2(const cx_t<float> *__restric
     if (f0 >= n) continue;
     C hv[W];
 #pragma unroll
-    for (int a = 0; a < W; ++a) hv[a] = H[((fr + a) * n + f1) * NQ + q];
+    for (int a = 0; a < W; ++a) hv[a] = H[((fr + a) * n + f1) * HS + q];
     C *dst = kpoly + ((((int64_t)r * nt + tl) * n + f0) * n + f1) * (NQ * NQ) + q;
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) {
@@ -212,6 +200,75 @@ __global__ __launch_bounds__(512) void k_poly_coef2(const cx_t<float> *__restric
       dst[qq * NQ] = cmake<float>(sr, si);
     }
   }
+}
+
+// Forward pack of the order-2 terms straight into the polynomial coefficients: workgroup =
+// (term, right-hand side, kPolyRows cell rows).  The first two stages are those of
+// k_pack_fwd (deconvolved coefficients A, then the DFT along the last axis, B); the last
+// stage evaluates only the HR grid rows that the cell rows need, into LDS, and poly2_passes
+// turns them into the cells' coefficients.  The grid itself is not stored.
+template <int MH>
+__global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__restrict__ fhat,
+                                                        const float *__restrict__ colscale, int64_t ncoef,
+                                                        const DevTerm *__restrict__ terms, OrderParams<float> op,
+                                                        int nslab, cx_t<float> *__restrict__ kpoly) {
+  using C = cx_t<float>;
+  constexpr int W = 2 * MH, NQ = Deg<float>::value + 1, HR = kPolyRows + W - 1, HS = NQ + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = MH - 1;
+  const int nt = op.term_end - op.term_begin;
+  const int tl = blockIdx.x / nslab, F0 = (blockIdx.x - tl * nslab) * kPolyRows, r = blockIdx.y;
+  const DevTerm tm = terms[op.term_begin + tl];
+  const C *__restrict__ src = fhat + (int64_t)r * ncoef + tm.coef_off;
+  const float *__restrict__ cs = colscale ? colscale + tm.coef_off : nullptr;
+  const float *__restrict__ Dc = op.deconv;
+  C *H = reinterpret_cast<C *>(smem_raw);   // HR x n x HS
+  C *Gs = H + HR * n * HS;                  // HR x P
+  C *A = Gs + HR * P;                       // K x K
+  C *B = A + K * K;                         // K x n
+  float *Wl = reinterpret_cast<float *>(B + K * n);   // 2n: cos, sin of 2 pi j / n
+  const int tid = threadIdx.x, BS = blockDim.x;
+  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
+  for (int i = tid; i < K * K; i += BS) {
+    const int a1 = i / K, a2 = i - a1 * K;
+    const C v = src[i];
+    const float sc = Dc[a1] * Dc[a2] * (cs ? cs[i] : 1.f);
+    A[i] = cmake<float>(v.x * sc, v.y * sc);
+  }
+  __syncthreads();
+  for (int i = tid; i < K * n; i += BS) {
+    const int a1 = i / n, l2 = i - a1 * n;
+    float re = 0.f, im = 0.f;
+    int e = pack_phase0(l2, n, h);
+    for (int a2 = 0; a2 < K; ++a2) {
+      const C v = A[a1 * K + a2];
+      const float co = Wl[2 * e], si = Wl[2 * e + 1];
+      re = fmaf(v.x, co, fmaf(-v.y, si, re));
+      im = fmaf(v.x, si, fmaf(v.y, co, im));
+      e = pack_step(e, a2, l2, n, h);
+    }
+    B[i] = cmake<float>(re, im);
+  }
+  __syncthreads();
+  for (int i = tid; i < HR * P; i += BS) {
+    const int hr = i / P, p = i - hr * P;
+    int l1 = (F0 - mm1 + hr) % n;
+    l1 = l1 < 0 ? l1 + n : l1;
+    int l2 = (p - mm1) % n;   // halo column -> grid column
+    l2 = l2 < 0 ? l2 + n : l2;
+    float re = 0.f, im = 0.f;
+    int e = pack_phase0(l1, n, h);
+    for (int a1 = 0; a1 < K; ++a1) {
+      const C v = B[a1 * n + l2];
+      const float co = Wl[2 * e], si = Wl[2 * e + 1];
+      re = fmaf(v.x, co, fmaf(-v.y, si, re));
+      im = fmaf(v.x, si, fmaf(v.y, co, im));
+      e = pack_step(e, a1, l1, n, h);
+    }
+    Gs[i] = cmake<float>(re, im);
+  }
+  __syncthreads();
+  poly2_passes<MH>(Gs, H, n, P, op.poly, F0, nt, tl, r, kpoly);
 }
 
 // One wavefront per run of at most 64 nodes of one cell (the cell gather's work items): the

@@ -37,7 +37,7 @@ constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 til
 constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
 constexpr double kCellGatherFill = 0.6;   // smallest lane fill of the cell gather's work items
 constexpr size_t kPolyMaxBytes = size_t(1) << 30;   // largest coefficient buffer of the order-2 polynomial gather
-constexpr int kPolyRows = 2;       // cell rows per workgroup of k_poly_coef2
+constexpr int kPolyRows = 2;       // cell rows per workgroup of k_pack_poly2
 
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
@@ -109,7 +109,7 @@ struct OrderHost {
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
   std::vector<CellItem> citems;       // cell gather work items (empty: k_gather_sorted is used)
   CellItem *d_citems = nullptr;
-  void *d_kpoly = nullptr;            // order 2 FP32: per-cell window-polynomial coefficients of the grids (k_poly_coef2)
+  void *d_kpoly = nullptr;            // order 2 FP32: per-cell window-polynomial coefficients of the grids (k_pack_poly2)
   std::vector<int32_t> citem_begin;   // per term of the order, +1
   // node binning of this order (per term, by cell) and spread work items
   int64_t ncell = 0;                  // n^order
@@ -134,6 +134,14 @@ struct OrderHost {
   void *d_gpart = nullptr;
   void *d_gsum = nullptr;             // folded spread grids: R x terms x n^order
 };
+
+// LDS bytes of k_pack_poly2 (order 2, FP32): first-pass array H (HR x n x (NQ + 1)), grid rows
+// (HR x P), deconvolved coefficients (K x K) and the first DFT stage (K x n), complex, plus the
+// 2n roots of unity; HR = kPolyRows + 2m - 1, NQ = Deg<float> + 1, K = N - 1.
+inline size_t poly_pack_lds(const OrderHost &o) {
+  const size_t HR = (size_t)(kPolyRows + 2 * o.m - 1), NQ = Deg<float>::value + 1, K = (size_t)(o.N - 1);
+  return (HR * o.n * (NQ + 1) + HR * o.P + K * K + K * o.n) * 2 * sizeof(float) + 2 * (size_t)o.n * sizeof(float);
+}
 
 }  // namespace gt
 

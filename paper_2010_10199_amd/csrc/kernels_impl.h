@@ -156,6 +156,15 @@ static __global__ void k_zero_n(int32_t *p, int n) {
 }
 
 // ------------------------------------------------------------------ K1 + K2 forward
+// Exponent index (k_a l) mod n of the pruned DFT over k_a = -h..-1, 1..h-1 (a = 0..K-1):
+// the value for a = 0, and the step a -> a + 1 (which skips k = 0).
+__device__ __forceinline__ int pack_phase0(int l, int n, int h) { return (int)(((int64_t)(n - h) * l) % n); }
+__device__ __forceinline__ int pack_step(int e, int a, int l, int n, int h) {
+  e += (a == h - 1) ? 2 * l : l;
+  while (e >= n) e -= n;
+  return e;
+}
+
 // One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
 // (N-1)^t non-zero frequencies onto the n^t grid, written in the halo layout.
 // The last stage's outputs are split over `slices` workgroups per term (each recomputes the
@@ -184,12 +193,8 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
   const T *W = Wl;
   const T *__restrict__ Dc = op.deconv;
   // exponent index (k_a * l) mod n for a = 0..K-1 stepping incrementally
-  auto phase0 = [&](int l) { return (int)(((int64_t)(n - h) * l) % n); };   // k = -h
-  auto step = [&](int e, int a, int l) {                                   // k_a -> k_{a+1}
-    e += (a == h - 1) ? 2 * l : l;
-    while (e >= n) e -= n;
-    return e;
-  };
+  auto phase0 = [&](int l) { return pack_phase0(l, n, h); };                       // k = -h
+  auto step = [&](int e, int a, int l) { return pack_step(e, a, l, n, h); };   // k_a -> k_{a+1}
   auto unpad = [&](int p) {
     int l = (p - mm1) % n;
     return l < 0 ? l + n : l;
@@ -982,28 +987,30 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
     const bool fk = fork_side(pl, s);
     for (int t = 1; t <= pl->ds; ++t) {
       const hipStream_t st = (fk && t == 1) ? pl->side : s;
-      if (blk == 0)
-        if (int rc = launch_pack<T>(pl, fhat, colscale, st, t)) return rc;
       const OrderHost &o = pl->ord[t];
+      bool packed = false;
       if constexpr (std::is_same<T, float>::value) {
-        if (blk == 0 && t == 2 && o.d_kpoly) {   // per-cell polynomial coefficients of the grids
+        if (blk == 0 && t == 2 && o.d_kpoly) {   // order 2: pack straight into per-cell polynomials
           const OrderParams<float> opf = order_params<float>(pl, 2);
           const int nt2 = o.term_end - o.term_begin, nslab = (o.n + kPolyRows - 1) / kPolyRows;
-          const size_t plds = (size_t)(kPolyRows + 2 * o.m - 1) * (o.n * (Deg<float>::value + 1) + o.P) * sizeof(C);
+          const size_t plds = poly_pack_lds(o);
           dim3 pgrid((unsigned)(nt2 * nslab), (unsigned)pl->R);
-          prof_begin(st, "poly_coef_2d");
-#define GT_LAUNCH_PCOEF(MH)                                                                                      \
+          prof_begin(st, "pack_fwd_2d");
+#define GT_LAUNCH_PPACK(MH)                                                                                      \
   {                                                                                                              \
-    if (int rc = set_lds(k_poly_coef2<MH>, plds)) return rc;                                                     \
-    hipLaunchKernelGGL((k_poly_coef2<MH>), pgrid, dim3(512), plds, st, (const C *)pl->d_grid, pl->grid_total,    \
+    if (int rc = set_lds(k_pack_poly2<MH>, plds)) return rc;                                                     \
+    hipLaunchKernelGGL((k_pack_poly2<MH>), pgrid, dim3(kPackBS), plds, st, (const C *)fhat, colscale, pl->ncoef, \
                        pl->d_terms, opf, nslab, (C *)o.d_kpoly);                                                 \
   }
-          GT_DISPATCH_M(o.m, GT_LAUNCH_PCOEF)
-#undef GT_LAUNCH_PCOEF
+          GT_DISPATCH_M(o.m, GT_LAUNCH_PPACK)
+#undef GT_LAUNCH_PPACK
           prof_end(st);
-          if (int rc = check_launch("k_poly_coef2")) return rc;
+          if (int rc = check_launch("k_pack_poly2")) return rc;
+          packed = true;
         }
       }
+      if (blk == 0 && !packed)
+        if (int rc = launch_pack<T>(pl, fhat, colscale, st, t)) return rc;
       const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
       if (tb >= te) continue;
       OrderParams<T> op = order_params<T>(pl, t);

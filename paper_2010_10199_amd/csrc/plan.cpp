@@ -418,13 +418,12 @@ static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
     o.citems.swap(items);
     o.citem_begin.swap(begin);
     if (int rc = upload_raw(o.citems, &o.d_citems)) return rc;
-    // order 2, FP32: the gather evaluates per-cell polynomials (k_poly_coef2 / k_gather_poly2)
-    // when their coefficients take at most kPolyMaxBytes and the first pass fits in LDS
+    // order 2, FP32: the gather evaluates per-cell polynomials (k_pack_poly2 / k_gather_poly2)
+    // when their coefficients take at most kPolyMaxBytes and the pack's arrays fit in LDS
     if (t == 2 && pl->dtype == GT_C64) {
       constexpr int NQ = Deg<float>::value + 1;
       const size_t bytes = (size_t)pl->R * nt * o.n * o.n * NQ * NQ * 2 * sizeof(float);
-      const size_t lds = (size_t)(kPolyRows + 2 * o.m - 1) * (o.n * NQ + o.P) * 2 * sizeof(float);
-      if (bytes <= kPolyMaxBytes && lds <= pl->lds_limit)
+      if (bytes <= kPolyMaxBytes && poly_pack_lds(o) <= pl->lds_limit)
         if (int rc = dev_alloc(&o.d_kpoly, bytes, s)) return rc;
     }
   }
