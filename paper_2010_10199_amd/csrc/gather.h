@@ -203,10 +203,11 @@ __device__ __forceinline__ void poly2_passes(const cx_t<float> *Gs, cx_t<float> 
 }
 
 // Forward pack of the order-2 terms straight into the polynomial coefficients: workgroup =
-// (term, right-hand side, kPolyRows cell rows).  The first two stages are those of
-// k_pack_fwd (deconvolved coefficients A, then the DFT along the last axis, B); the last
-// stage evaluates only the HR grid rows that the cell rows need, into LDS, and poly2_passes
-// turns them into the cells' coefficients.  The grid itself is not stored.
+// (term, right-hand side, kPolyRows cell rows).  The first two stages compute what k_pack_fwd
+// computes (deconvolved coefficients A, then the DFT along the last axis, B), with the DFT
+// factors tabulated in LDS; the last stage evaluates only the HR grid rows that the cell rows
+// need, into LDS, and poly2_passes turns them into the cells' coefficients.  The grid itself
+// is not stored.
 template <int MH>
 __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__restrict__ fhat,
                                                         const float *__restrict__ colscale, int64_t ncoef,
@@ -226,9 +227,14 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
   C *Gs = H + HR * n * HS;                  // HR x P
   C *A = Gs + HR * P;                       // K x K
   C *B = A + K * K;                         // K x n
-  float *Wl = reinterpret_cast<float *>(B + K * n);   // 2n: cos, sin of 2 pi j / n
+  C *Wt = B + K * n;                        // K x n: e^{2 pi i k_a l / n}, k_a = -h..-1, 1..h-1
   const int tid = threadIdx.x, BS = blockDim.x;
-  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
+  for (int i = tid; i < K * n; i += BS) {
+    const int a = i / n, l = i - a * n, k = a < h ? a - h : a - h + 1;
+    int e = (int)(((int64_t)k * l) % n);
+    e = e < 0 ? e + n : e;
+    Wt[i] = cmake<float>(op.roots[2 * e], op.roots[2 * e + 1]);
+  }
   for (int i = tid; i < K * K; i += BS) {
     const int a1 = i / K, a2 = i - a1 * K;
     const C v = src[i];
@@ -239,13 +245,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
   for (int i = tid; i < K * n; i += BS) {
     const int a1 = i / n, l2 = i - a1 * n;
     float re = 0.f, im = 0.f;
-    int e = pack_phase0(l2, n, h);
     for (int a2 = 0; a2 < K; ++a2) {
-      const C v = A[a1 * K + a2];
-      const float co = Wl[2 * e], si = Wl[2 * e + 1];
-      re = fmaf(v.x, co, fmaf(-v.y, si, re));
-      im = fmaf(v.x, si, fmaf(v.y, co, im));
-      e = pack_step(e, a2, l2, n, h);
+      const C v = A[a1 * K + a2], w = Wt[a2 * n + l2];
+      re = fmaf(v.x, w.x, fmaf(-v.y, w.y, re));
+      im = fmaf(v.x, w.y, fmaf(v.y, w.x, im));
     }
     B[i] = cmake<float>(re, im);
   }
@@ -257,13 +260,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
     int l2 = (p - mm1) % n;   // halo column -> grid column
     l2 = l2 < 0 ? l2 + n : l2;
     float re = 0.f, im = 0.f;
-    int e = pack_phase0(l1, n, h);
     for (int a1 = 0; a1 < K; ++a1) {
-      const C v = B[a1 * n + l2];
-      const float co = Wl[2 * e], si = Wl[2 * e + 1];
-      re = fmaf(v.x, co, fmaf(-v.y, si, re));
-      im = fmaf(v.x, si, fmaf(v.y, co, im));
-      e = pack_step(e, a1, l1, n, h);
+      const C v = B[a1 * n + l2], w = Wt[a1 * n + l1];
+      re = fmaf(v.x, w.x, fmaf(-v.y, w.y, re));
+      im = fmaf(v.x, w.y, fmaf(v.y, w.x, im));
     }
     Gs[i] = cmake<float>(re, im);
   }

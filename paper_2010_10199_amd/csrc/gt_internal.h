@@ -37,7 +37,7 @@ constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 til
 constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
 constexpr double kCellGatherFill = 0.6;   // smallest lane fill of the cell gather's work items
 constexpr size_t kPolyMaxBytes = size_t(1) << 30;   // largest coefficient buffer of the order-2 polynomial gather
-constexpr int kPolyRows = 2;       // cell rows per workgroup of k_pack_poly2
+constexpr int kPolyRows = 3;       // cell rows per workgroup of k_pack_poly2
 
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
@@ -135,12 +135,12 @@ struct OrderHost {
   void *d_gsum = nullptr;             // folded spread grids: R x terms x n^order
 };
 
-// LDS bytes of k_pack_poly2 (order 2, FP32): first-pass array H (HR x n x (NQ + 1)), grid rows
-// (HR x P), deconvolved coefficients (K x K) and the first DFT stage (K x n), complex, plus the
-// 2n roots of unity; HR = kPolyRows + 2m - 1, NQ = Deg<float> + 1, K = N - 1.
+// LDS bytes of k_pack_poly2 (order 2, FP32), all complex: first-pass array H (HR x n x (NQ + 1)),
+// grid rows (HR x P), deconvolved coefficients (K x K), first DFT stage (K x n) and the DFT
+// factors (K x n); HR = kPolyRows + 2m - 1, NQ = Deg<float> + 1, K = N - 1.
 inline size_t poly_pack_lds(const OrderHost &o) {
   const size_t HR = (size_t)(kPolyRows + 2 * o.m - 1), NQ = Deg<float>::value + 1, K = (size_t)(o.N - 1);
-  return (HR * o.n * (NQ + 1) + HR * o.P + K * K + K * o.n) * 2 * sizeof(float) + 2 * (size_t)o.n * sizeof(float);
+  return (HR * o.n * (NQ + 1) + HR * o.P + K * K + 2 * K * o.n) * 2 * sizeof(float);
 }
 
 }  // namespace gt
