@@ -135,6 +135,17 @@ int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, 
 /* Window half-width m and FFT grid size n chosen for order t (1..ds); for reports. */
 int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n);
 
+/* Which forward gather the plan uses for order t (1..ds); for reports and tests.  All three
+ * compute the window sum of Definition def:skatoons via eq. somafm for every node of every
+ * term of the order:
+ *   GT_GATHER_SORTED  runs of cell-sorted nodes, the term's grid staged in LDS;
+ *   GT_GATHER_CELL    one wavefront per run of <= 64 nodes of one grid cell, the grid block as
+ *                     scalar operands (when the cells hold enough nodes);
+ *   GT_GATHER_POLY    order 2, FP32: per-cell coefficients of the window polynomials (built by
+ *                     the forward pack), evaluated per node by Horner sums. */
+enum { GT_GATHER_SORTED = 0, GT_GATHER_CELL = 1, GT_GATHER_POLY = 2 };
+int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path);
+
 /* ------------------------------------------------------------------ solvers
  * lsqr_solve: R independent weighted Tikhonov problems (eq. new_min_prob), one per
  * right-hand side r with its own lambda[r] >= 0 (lambda = 0: eq. min_prob), solved by

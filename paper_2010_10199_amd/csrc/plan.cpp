@@ -849,6 +849,13 @@ int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n) {
   return GT_OK;
 }
 
+int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path) {
+  if (!plan || t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  const OrderHost &o = plan->ord[t];
+  if (path) *path = o.d_kpoly ? GT_GATHER_POLY : (!o.citems.empty() ? GT_GATHER_CELL : GT_GATHER_SORTED);
+  return GT_OK;
+}
+
 int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream) {
   if (!plan || !fhat || !f) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;

@@ -20,12 +20,13 @@ GT_OK, GT_EINVAL, GT_ENOMEM, GT_EHIP, GT_EUNSUPPORTED = 0, -1, -2, -3, -4
 GT_C64, GT_C128 = 1, 2
 GT_MAX_ORDER = 3
 GT_SOLVE_CONVERGED, GT_SOLVE_MAX_ITER, GT_SOLVE_BREAKDOWN, GT_SOLVE_BACKTRACK_CAP = 1, 2, 4, 8
+GT_GATHER_SORTED, GT_GATHER_CELL, GT_GATHER_POLY = 0, 1, 2
 
 # every symbol include/grouped.h declares
 EXPORTS = [
     "gt_num_terms", "gt_num_coeffs", "gt_term_table", "grouped_trafo", "grouped_adjoint",
     "gt_plan_create", "gt_plan_destroy", "gt_plan_trafo", "gt_plan_adjoint", "gt_plan_node_grad",
-    "gt_plan_order_info", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
+    "gt_plan_order_info", "gt_plan_gather_path", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
     "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
 ]
 
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH):
         "gt_plan_adjoint": (C.c_int, [vp, vp, vp, vp]),
         "gt_plan_node_grad": (C.c_int, [vp, vp, vp, vp, vp]),
         "gt_plan_order_info": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "gt_plan_gather_path": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "gt_plan_norm_estimate": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
         "fista_group_lasso": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp,
@@ -203,6 +205,12 @@ class Plan:
         out = C.c_double()
         _check(self._lib.gt_plan_norm_estimate(self.handle, int(iters), C.byref(out), _stream(stream)))
         return float(out.value)
+
+    def gather_path(self, t: int) -> int:
+        """GT_GATHER_SORTED / GT_GATHER_CELL / GT_GATHER_POLY for order t."""
+        path = C.c_int32()
+        _check(self._lib.gt_plan_gather_path(self.handle, int(t), C.byref(path)))
+        return int(path.value)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -12,7 +12,8 @@ import pytest
 import workloads as W
 from oracle import index_set as oidx
 from oracle import transform as otr
-from tests.gpu_util import TOL, gpu_adjoint, gpu_trafo, nfft_model_error, rel, say
+from paper_2010_10199_amd import lib
+from tests.gpu_util import TOL, dtype_code, gpu_adjoint, gpu_trafo, nfft_model_error, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +28,19 @@ CASES = [
     ("only-empty-set", 3, 0, (), 300, 2, 0, 0.0),
     ("bandwidth-2", 3, 3, (2, 2, 2), 513, 1, 0, 0.0),
     ("wide-window-small-grid", 2, 2, (4, 4), 400, 1, 8, 2.0),
+    # enough nodes per grid cell for the cell gather (and the polynomial gather in FP32)
+    ("cells-2d-R2", 3, 2, (8, 6), 20000, 2, 0, 0.0),
+    ("cells-ragged-2d", 3, 2, (6, 4), [10000, 12000], 2, 0, 0.0),
+    ("cells-3d", 3, 3, (4, 4, 4), 30000, 1, 0, 0.0),
 ]
+
+# forward gather path per order of the cell cases: FP32 takes the polynomial gather for
+# order 2, FP64 the cell gather
+PATHS = {
+    "cells-2d-R2": {1: "cell", 2: "poly"},
+    "cells-ragged-2d": {1: "cell", 2: "poly"},
+    "cells-3d": {1: "cell", 2: "poly", 3: "cell"},
+}
 
 
 def _inputs(case_id, d, ds, N, Msz, R, prec):
@@ -78,6 +91,29 @@ def test_forward_and_adjoint_parity(case, prec):
     erra = rel(a, refa)
     say(f"  adjoint rel err {erra:.3e} (tol {tol:.1e})")
     assert erra <= tol
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", sorted(PATHS))
+def test_cell_cases_take_the_intended_gather(name, prec):
+    """The cell cases above run through the gather paths they are meant to cover (their
+    parity is checked by test_forward_and_adjoint_parity)."""
+    import torch
+    case = next(c for c in CASES if c[0] == name)
+    _, d, ds, N, Msz, R, m, sigma = case
+    iset, x, fhat, y, offsets = _inputs(CASES.index(case), d, ds, N, Msz, R, prec)
+    p, keep = lib.make_problem(d, ds, N, M=x.shape[0] if offsets is None else 0, R=R, dtype=dtype_code(prec),
+                               offsets=offsets)
+    plan = lib.Plan(p, to_dev(x), keepalive=keep)
+    want = {"sorted": lib.GT_GATHER_SORTED, "cell": lib.GT_GATHER_CELL, "poly": lib.GT_GATHER_POLY}
+    for t, kind in PATHS[name].items():
+        if prec == "f64" and kind == "poly":
+            kind = "cell"
+        got = plan.gather_path(t)
+        say(f"[path] {name} {prec} order {t}: {got} (want {kind})")
+        assert got == want[kind]
+    plan.close()
+    torch.cuda.synchronize()
 
 
 def test_config1_fp64_full():
