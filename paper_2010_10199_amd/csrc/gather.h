@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
   const int tid = threadIdx.x, BS = blockDim.x;
   for (int i = tid; i < K * n; i += BS) {
     const int a = i / n, l = i - a * n, k = a < h ? a - h : a - h + 1;
-    int e = (int)(((int64_t)k * l) % n);
+    int e = (k * l) % n;
     e = e < 0 ? e + n : e;
     Wt[i] = cmake<float>(op.roots[2 * e], op.roots[2 * e + 1]);
   }

@@ -156,14 +156,6 @@ static __global__ void k_zero_n(int32_t *p, int n) {
 }
 
 // ------------------------------------------------------------------ K1 + K2 forward
-// Exponent index (k_a l) mod n of the pruned DFT over k_a = -h..-1, 1..h-1 (a = 0..K-1):
-// the value for a = 0, and the step a -> a + 1 (which skips k = 0).
-__device__ __forceinline__ int pack_phase0(int l, int n, int h) { return (int)(((int64_t)(n - h) * l) % n); }
-__device__ __forceinline__ int pack_step(int e, int a, int l, int n, int h) {
-  e += (a == h - 1) ? 2 * l : l;
-  while (e >= n) e -= n;
-  return e;
-}
 
 // One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
 // (N-1)^t non-zero frequencies onto the n^t grid, written in the halo layout.
@@ -184,17 +176,25 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
   C *dst = grids + (int64_t)r * grid_total + tm.grid_off;
   const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = op.m - 1;
-  // roots of unity staged in LDS after the DFT stages (first read after the first barrier)
+  // LDS: the DFT stage arrays, then the table of DFT factors
   const size_t stage = sizeof(C) * (ORDER == 1 ? (size_t)K
                                    : ORDER == 2 ? (size_t)K * K + (size_t)K * n
                                                 : (size_t)K * K * K + (size_t)K * K * n + (size_t)K * n * n);
-  T *Wl = reinterpret_cast<T *>(smem_raw + stage);
-  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
-  const T *W = Wl;
+  // DFT factors e^{2 pi i k_a l / n} (k_a = -h..-1, 1..h-1, a = 0..K-1) tabulated after the
+  // stage arrays (first read after the first barrier); order 1 (bandwidths up to several
+  // hundred) keeps only the n roots of unity there and steps the exponent (k_a l) mod n
+  C *Wt = reinterpret_cast<C *>(smem_raw + stage);
+  if (ORDER == 1) {
+    for (int i = tid; i < n; i += BS) Wt[i] = cmake<T>(op.roots[2 * i], op.roots[2 * i + 1]);
+  } else {
+    for (int i = tid; i < K * n; i += BS) {
+      const int a = i / n, l = i - a * n, k = a < h ? a - h : a - h + 1;
+      int e = (k * l) % n;
+      e = e < 0 ? e + n : e;
+      Wt[i] = cmake<T>(op.roots[2 * e], op.roots[2 * e + 1]);
+    }
+  }
   const T *__restrict__ Dc = op.deconv;
-  // exponent index (k_a * l) mod n for a = 0..K-1 stepping incrementally
-  auto phase0 = [&](int l) { return pack_phase0(l, n, h); };                       // k = -h
-  auto step = [&](int e, int a, int l) { return pack_step(e, a, l, n, h); };   // k_a -> k_{a+1}
   auto unpad = [&](int p) {
     int l = (p - mm1) % n;
     return l < 0 ? l + n : l;
@@ -211,13 +211,13 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int p = p0 + tid; p < p1; p += BS) {
       const int l = unpad(p);
       T re = 0, im = 0;
-      int e = phase0(l);
+      int e = (int)(((int64_t)(n - h) * l) % n);   // k = -h
       for (int a = 0; a < K; ++a) {
-        const C v = S[a];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a, l);
+        const C v = S[a], w = Wt[e];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
+        e += (a == h - 1) ? 2 * l : l;   // k_a -> k_{a+1}, skipping k = 0
+        while (e >= n) e -= n;
       }
       dst[p] = cmake<T>(re, im);
     }
@@ -234,13 +234,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int i = tid; i < K * n; i += BS) {
       const int a1 = i / n, l2 = i - a1 * n;
       T re = 0, im = 0;
-      int e = phase0(l2);
       for (int a2 = 0; a2 < K; ++a2) {
-        const C v = A[a1 * K + a2];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a2, l2);
+        const C v = A[a1 * K + a2], w = Wt[a2 * n + l2];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
       }
       B[i] = cmake<T>(re, im);
     }
@@ -249,13 +246,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int i = i0 + tid; i < i1; i += BS) {
       const int l1 = i / P, p2 = i - l1 * P, l2 = unpad(p2);
       T re = 0, im = 0;
-      int e = phase0(l1);
       for (int a1 = 0; a1 < K; ++a1) {
-        const C v = B[a1 * n + l2];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a1, l1);
+        const C v = B[a1 * n + l2], w = Wt[a1 * n + l1];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
       }
       dst[i] = cmake<T>(re, im);
     }
@@ -273,13 +267,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int i = tid; i < K * K * n; i += BS) {
       const int a12 = i / n, l3 = i - a12 * n;
       T re = 0, im = 0;
-      int e = phase0(l3);
       for (int a3 = 0; a3 < K; ++a3) {
-        const C v = A[a12 * K + a3];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a3, l3);
+        const C v = A[a12 * K + a3], w = Wt[a3 * n + l3];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
       }
       B[i] = cmake<T>(re, im);
     }
@@ -287,13 +278,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int i = tid; i < K * n * n; i += BS) {
       const int a1 = i / (n * n), rem = i - a1 * n * n, l2 = rem / n, l3 = rem - l2 * n;
       T re = 0, im = 0;
-      int e = phase0(l2);
       for (int a2 = 0; a2 < K; ++a2) {
-        const C v = B[(a1 * K + a2) * n + l3];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a2, l2);
+        const C v = B[(a1 * K + a2) * n + l3], w = Wt[a2 * n + l2];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
       }
       Cc[i] = cmake<T>(re, im);
     }
@@ -302,13 +290,10 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
     for (int i = i0 + tid; i < i1; i += BS) {
       const int l1 = i / (n * P), rem = i - l1 * n * P, l2 = rem / P, p3 = rem - l2 * P, l3 = unpad(p3);
       T re = 0, im = 0;
-      int e = phase0(l1);
       for (int a1 = 0; a1 < K; ++a1) {
-        const C v = Cc[(a1 * n + l2) * n + l3];
-        const T c = W[2 * e], s = W[2 * e + 1];
-        re = fma(v.x, c, fma(-v.y, s, re));
-        im = fma(v.x, s, fma(v.y, c, im));
-        e = step(e, a1, l1);
+        const C v = Cc[(a1 * n + l2) * n + l3], w = Wt[a1 * n + l1];
+        re = fma(v.x, w.x, fma(-v.y, w.y, re));
+        im = fma(v.x, w.y, fma(v.y, w.x, im));
       }
       dst[i] = cmake<T>(re, im);
     }
@@ -538,35 +523,39 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
   const int r = blockIdx.y;
   const int nt = op.term_end - op.term_begin;
   const int K = op.nfreq, n = op.n, h = op.N / 2;
-  // roots of unity staged in LDS after the DFT stages (first read after the first barrier)
+  // LDS: the DFT stage arrays, then the table of DFT factors (then, order 2, the column sums)
   const size_t stage = sizeof(C) * (ORDER == 1 ? (size_t)n
                                    : ORDER == 2 ? (size_t)n * n + (size_t)n * K
                                                 : (size_t)n * n * n + (size_t)n * n * K);
-  T *Wl = reinterpret_cast<T *>(smem_raw + stage);
-  for (int i = tid; i < 2 * n; i += BS) Wl[i] = op.roots[i];
-  const T *W = Wl;
+  // DFT factors e^{2 pi i k_a l / n} (k_a = -h..-1, 1..h-1, a = 0..K-1) tabulated after the
+  // stage arrays (first read after the first barrier); the sums below use their conjugates
+  C *Wt = reinterpret_cast<C *>(smem_raw + stage);
+  if (ORDER == 1) {   // order 1: the n roots of unity only, exponent stepped (as in k_pack_fwd)
+    for (int i = tid; i < n; i += BS) Wt[i] = cmake<T>(op.roots[2 * i], op.roots[2 * i + 1]);
+  } else {
+    for (int i = tid; i < K * n; i += BS) {   // Wt[l * K + a]: threads that differ in a read neighbours
+      const int l = i / K, a = i - l * K, k = a < h ? a - h : a - h + 1;
+      int e = (k * l) % n;
+      e = e < 0 ? e + n : e;
+      Wt[i] = cmake<T>(op.roots[2 * e], op.roots[2 * e + 1]);
+    }
+  }
   const T *__restrict__ Dc = op.deconv;
   C *dst = fhat + (int64_t)r * ncoef + tm.coef_off;
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
-  auto phase0 = [&](int l) { return (int)(((int64_t)(n - h) * l) % n); };
-  auto step = [&](int e, int a, int l) {
-    e += (a == h - 1) ? 2 * l : l;
-    while (e >= n) e -= n;
-    return e;
-  };
   const int outer = ORDER == 1 ? 1 : (ORDER == 2 ? n : n * n);
   C *G = S;
   if (ORDER == 2 && ntile != 0) {
     // order 2 from the tile spread: gsum holds the column-folded patches
     // hcol[ty][pr][l1] of this term; grid row l0 collects the patch rows that land on it
     // (start row of tile row ty plus pr, modulo n), tile rows in order
-    // (staged in LDS after the DFT stages and the roots of unity)
+    // (staged in LDS after the DFT stages and the table of DFT factors)
     // (read from global memory when it does not fit: ntile < 0 asks for that)
     const bool staged = ntile > 0;
     ntile = staged ? ntile : -ntile;
     const int mm1 = op.m - 1;
     const C *hc = gsum + ((int64_t)r * nt + tl) * ntile * 16 * n;
-    C *HCl = reinterpret_cast<C *>(smem_raw + stage + 2 * n * sizeof(T));
+    C *HCl = reinterpret_cast<C *>(smem_raw + stage + (size_t)K * n * sizeof(C));
     if (staged) {
       for (int i = tid; i < ntile * 16 * n; i += BS) HCl[i] = hc[i];
       __syncthreads();
@@ -606,7 +595,7 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
       int e = 0;
       for (int l = 0; l < n; ++l) {
         const C v = G[l];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = Wt[e].x, s = Wt[e].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
         e += km;
@@ -619,34 +608,26 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
     C *H = S + n * n;   // n x K
     for (int i = tid; i < n * K; i += BS) {
       const int l1 = i / K, a2 = i - l1 * K;
-      const int k = a2 - h + (a2 >= h ? 1 : 0);
-      const int km = k < 0 ? k + n : k;
+      const C *w = Wt + a2;
       T re = 0, im = 0;
-      int e = 0;
       for (int l2 = 0; l2 < n; ++l2) {
         const C v = G[l1 * n + l2];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = w[l2 * K].x, s = w[l2 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
-        e += km;
-        if (e >= n) e -= n;
       }
       H[i] = cmake<T>(re, im);
     }
     __syncthreads();
     for (int i = tid; i < K * K; i += BS) {
       const int a1 = i / K, a2 = i - a1 * K;
-      const int k = a1 - h + (a1 >= h ? 1 : 0);
-      const int km = k < 0 ? k + n : k;
+      const C *w = Wt + a1;
       T re = 0, im = 0;
-      int e = 0;
       for (int l1 = 0; l1 < n; ++l1) {
         const C v = H[l1 * K + a2];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = w[l1 * K].x, s = w[l1 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
-        e += km;
-        if (e >= n) e -= n;
       }
       const T sc = Dc[a1] * Dc[a2] * (cs ? cs[i] : (T)1);
       dst[i] = cmake<T>(re * sc, im * sc);
@@ -656,51 +637,39 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
     C *H2 = S;               // n x K x K (overwrites G after H1 is complete)
     for (int i = tid; i < n * n * K; i += BS) {
       const int l12 = i / K, a3 = i - l12 * K;
-      const int k = a3 - h + (a3 >= h ? 1 : 0);
-      const int km = k < 0 ? k + n : k;
+      const C *w = Wt + a3;
       T re = 0, im = 0;
-      int e = 0;
       for (int l3 = 0; l3 < n; ++l3) {
         const C v = G[l12 * n + l3];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = w[l3 * K].x, s = w[l3 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
-        e += km;
-        if (e >= n) e -= n;
       }
       H1[i] = cmake<T>(re, im);
     }
     __syncthreads();
     for (int i = tid; i < n * K * K; i += BS) {
       const int l1 = i / (K * K), rem = i - l1 * K * K, a2 = rem / K, a3 = rem - a2 * K;
-      const int k = a2 - h + (a2 >= h ? 1 : 0);
-      const int km = k < 0 ? k + n : k;
+      const C *w = Wt + a2;
       T re = 0, im = 0;
-      int e = 0;
       for (int l2 = 0; l2 < n; ++l2) {
         const C v = H1[(l1 * n + l2) * K + a3];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = w[l2 * K].x, s = w[l2 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
-        e += km;
-        if (e >= n) e -= n;
       }
       H2[i] = cmake<T>(re, im);
     }
     __syncthreads();
     for (int i = tid; i < K * K * K; i += BS) {
       const int a1 = i / (K * K), rem = i - a1 * K * K, a2 = rem / K, a3 = rem - a2 * K;
-      const int k = a1 - h + (a1 >= h ? 1 : 0);
-      const int km = k < 0 ? k + n : k;
+      const C *w = Wt + a1;
       T re = 0, im = 0;
-      int e = 0;
       for (int l1 = 0; l1 < n; ++l1) {
         const C v = H2[(l1 * K + a2) * K + a3];
-        const T c = W[2 * e], s = W[2 * e + 1];
+        const T c = w[l1 * K].x, s = w[l1 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
-        e += km;
-        if (e >= n) e -= n;
       }
       const T sc = Dc[a1] * Dc[a2] * Dc[a3] * (cs ? cs[i] : (T)1);
       dst[i] = cmake<T>(re * sc, im * sc);
@@ -916,7 +885,7 @@ static size_t pack_lds(const gt_plan *pl, int t) {
   const OrderHost &o = pl->ord[t];
   const size_t K = o.N - 1, n = o.n;
   const size_t c = sizeof(cx_t<T>);
-  return c * (t == 1 ? K : t == 2 ? K * K + K * n : K * K * K + K * K * n + K * n * n) + 2 * n * sizeof(T);
+  return c * (t == 1 ? K : t == 2 ? K * K + K * n : K * K * K + K * K * n + K * n * n) + c * (t == 1 ? n : K * n);
 }
 
 template <typename T>
@@ -924,7 +893,7 @@ static size_t adj_lds(const gt_plan *pl, int t) {
   const OrderHost &o = pl->ord[t];
   const size_t K = o.N - 1, n = o.n;
   const size_t c = sizeof(cx_t<T>);
-  return c * (t == 1 ? n : t == 2 ? n * n + n * K : n * n * n + n * n * K) + 2 * n * sizeof(T);
+  return c * (t == 1 ? n : t == 2 ? n * n + n * K : n * n * n + n * n * K) + c * (t == 1 ? n : K * n);
 }
 
 template <typename T>
