@@ -209,3 +209,43 @@ def test_solver_argument_errors():
     with pytest.raises(lib.GroupedError) as e:
         lib.lsqr_solve(p, x, y, [1.0], bad, 5, 0.0, out)
     assert e.value.code == lib.GT_EINVAL
+
+
+def test_fp32_solvers_on_cell_and_polynomial_gathers():
+    """Batched FP32 LSQR and FISTA on a node set whose cells are filled enough for the cell
+    gather (order 1) and the polynomial gather (order 2): LSQR against the dense normal
+    equations, FISTA against the oracle's iterates with the same step constant."""
+    d, ds, N, M = 3, 2, (8, 6), 20000
+    iset = oidx.grouped_index_set(d, ds, N)
+    x, ftrue, yy = W.trafo_inputs(35, d, ds, M, iset.n_coeffs, 1, "f32")
+    p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64)
+    plan = lib.Plan(p, to_dev(x), keepalive=keep)
+    paths = (plan.gather_path(1), plan.gather_path(2))
+    plan.close()
+    say(f"[solvers on cells] gather paths {paths}")
+    assert paths == (lib.GT_GATHER_CELL, lib.GT_GATHER_POLY)
+    y = yy[0]
+    A = otr.dense_matrix(iset, x)
+    lambdas = [1e-2, 10.0, 1000.0]
+    R = len(lambdas)
+    fg, info = _lsqr_gpu(d, ds, N, x, np.tile(y, R).reshape(R, M), lambdas, "f32", 200, tol=1e-8)
+    for r, lam in enumerate(lambdas):
+        ref = np.linalg.solve(A.conj().T @ A + 2 * lam * np.eye(iset.n_coeffs), A.conj().T @ y.astype(complex))
+        e = rel(fg[r], ref)
+        say(f"  lsqr lambda={lam} rel {e:.3e} iters {info[r].iters}")
+        assert e <= 1e-5
+    f = np.zeros(iset.n_coeffs, dtype=complex)
+    for ti in (1, 5):
+        f[iset.term_slice(ti)] = ftrue[0][iset.term_slice(ti)]
+    yf = (otr.forward(iset, x, f) + 0.05 * y).astype(np.complex64)
+    L = 1.05 * ofista.power_iteration(lambda v: otr.forward(iset, x, v), lambda q: otr.adjoint(iset, x, q),
+                                      iset.n_coeffs, 30)
+    K = 30
+    flam = [100.0, 2000.0]
+    fgf, _ = _fista_gpu(d, ds, N, x, np.tile(yf, 2).reshape(2, M), flam, "f32", K, L)
+    for r, lam in enumerate(flam):
+        ref = ofista.fista(lambda v: otr.forward(iset, x, v), lambda q: otr.adjoint(iset, x, q),
+                           yf.astype(np.complex128), iset.offsets, lam, L, K)
+        e = rel(fgf[r], ref.fhat)
+        say(f"  fista lambda={lam} rel {e:.3e}")
+        assert e <= 1e-5
