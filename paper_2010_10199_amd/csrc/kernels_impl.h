@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict
 // One workgroup per (term, right-hand side): the folded grid, pruned forward DFT to the
 // (N-1)^t non-zero frequencies, deconvolve, write in group order.
 template <typename T, int ORDER>
-__global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
+__global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
                                                      const DevTerm *__restrict__ terms, OrderParams<T> op,
                                                      const T *__restrict__ colscale, int64_t ncoef,
                                                      cx_t<T> *__restrict__ fhat, int ntile, int ts) {
@@ -605,32 +605,45 @@ __global__ __launch_bounds__(kPackBS) void k_dft_adj(const cx_t<T> *__restrict__
       dst[a] = cmake<T>(re * sc, im * sc);
     }
   } else if (ORDER == 2) {
+    // Each sum is split over adjacent lanes (two for the first stage, four for the second,
+    // lanes i with the same i >> 1 or i >> 2, always in the same loop iteration) and the
+    // parts are added by lane shuffles in a fixed order.
     C *H = S + n * n;   // n x K
-    for (int i = tid; i < n * K; i += BS) {
-      const int l1 = i / K, a2 = i - l1 * K;
+    for (int i = tid; i < 2 * n * K; i += BS) {
+      const int o = i >> 1, half = i & 1;
+      const int l1 = o / K, a2 = o - l1 * K;
       const C *w = Wt + a2;
       T re = 0, im = 0;
-      for (int l2 = 0; l2 < n; ++l2) {
+      for (int l2 = (half * n) >> 1; l2 < ((half + 1) * n) >> 1; ++l2) {
         const C v = G[l1 * n + l2];
         const T c = w[l2 * K].x, s = w[l2 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
       }
-      H[i] = cmake<T>(re, im);
+      re += __shfl_xor(re, 1);
+      im += __shfl_xor(im, 1);
+      if (half == 0) H[o] = cmake<T>(re, im);
     }
     __syncthreads();
-    for (int i = tid; i < K * K; i += BS) {
-      const int a1 = i / K, a2 = i - a1 * K;
+    for (int i = tid; i < 4 * K * K; i += BS) {
+      const int o = i >> 2, part = i & 3;
+      const int a1 = o / K, a2 = o - a1 * K;
       const C *w = Wt + a1;
       T re = 0, im = 0;
-      for (int l1 = 0; l1 < n; ++l1) {
+      for (int l1 = (part * n) >> 2; l1 < ((part + 1) * n) >> 2; ++l1) {
         const C v = H[l1 * K + a2];
         const T c = w[l1 * K].x, s = w[l1 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
       }
-      const T sc = Dc[a1] * Dc[a2] * (cs ? cs[i] : (T)1);
-      dst[i] = cmake<T>(re * sc, im * sc);
+      re += __shfl_xor(re, 1);
+      im += __shfl_xor(im, 1);
+      re += __shfl_xor(re, 2);
+      im += __shfl_xor(im, 2);
+      if (part == 0) {
+        const T sc = Dc[a1] * Dc[a2] * (cs ? cs[o] : (T)1);
+        dst[o] = cmake<T>(re * sc, im * sc);
+      }
     }
   } else {
     C *H1 = S + n * n * n;   // n x n x K
@@ -1162,7 +1175,7 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
                          colscale, pl->ncoef, (C *)fhat, 0, 0);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(kPackBS), lds, st, (const C *)o.d_tsum, pl->d_terms, op,
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(2 * kPackBS), lds, st, (const C *)o.d_tsum, pl->d_terms, op,
                          colscale, pl->ncoef, (C *)fhat, stage_h ? o.ntile : -o.ntile, o.ts);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
