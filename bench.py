@@ -256,8 +256,8 @@ def main():
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not run", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU "
+              "path to time", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -52,7 +52,7 @@ typedef enum {
   GT_EINVAL = -1,        /* invalid argument (message in gt_last_error) */
   GT_ENOMEM = -2,        /* device or host allocation failed */
   GT_EHIP = -3,          /* a HIP runtime call failed */
-  GT_EUNSUPPORTED = -4   /* valid but outside what this build implements (e.g. d_s > 3) */
+  GT_EUNSUPPORTED = -4   /* valid but outside what this library implements (e.g. d_s > 3) */
 } gt_status;
 
 enum { GT_C64 = 1, GT_C128 = 2 };   /* complex float (FP32 path) / complex double (FP64 path) */
