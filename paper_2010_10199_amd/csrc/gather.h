@@ -295,9 +295,9 @@ __global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ 
   const bool act = l < it.count;
   const int c0 = it.cell[0], c1 = it.cell[1];
   const C *__restrict__ K = kpoly + ((((int64_t)r * nt + it.tl) * n + c0) * n + c1) * (NQ * NQ);
-  const int q = it.q0 + (act ? l : 0);
-  const int32_t node = perm[q];
-  const cx_t<float> xv = reinterpret_cast<const cx_t<float> *>(xs)[q];
+  const int pos = it.q0 + (act ? l : 0);
+  const int32_t node = perm[pos];
+  const cx_t<float> xv = reinterpret_cast<const cx_t<float> *>(xs)[pos];
   const float nf = (float)n;
   const float z0 = fmaf(nf, xv.x, (float)(n / 2 - c0)) * 2.f - 1.f;
   const float z1 = fmaf(nf, xv.y, (float)(n / 2 - c1)) * 2.f - 1.f;
