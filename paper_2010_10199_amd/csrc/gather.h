@@ -271,6 +271,27 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
   poly2_passes<MH>(Gs, H, n, P, op.poly, F0, nt, tl, r, kpoly);
 }
 
+typedef float v16f_t __attribute__((ext_vector_type(16)));
+
+// Four consecutive 64-byte rows at a wavefront-uniform, 64-byte aligned address into scalar
+// registers, as one round trip: the four scalar loads are issued back to back and waited for
+// inside the same statement (the compiler otherwise waits after each row).  The outputs are
+// early-clobber, so no row overlaps the address registers while the loads are in flight.
+// The statement takes two values as (unused) inputs and so follows their computation: a
+// second group takes the partial sums of the first, so each group is consumed as soon as it
+// arrives and two groups are never live at once.
+__device__ __forceinline__ void sload_rows4(const void *p, v16f_t (&r)[4], float dep0, float dep1) {
+  asm volatile(
+      "s_load_dwordx16 %0, %4, 0x0\n\t"
+      "s_load_dwordx16 %1, %4, 0x40\n\t"
+      "s_load_dwordx16 %2, %4, 0x80\n\t"
+      "s_load_dwordx16 %3, %4, 0xc0\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&s"(r[0]), "=&s"(r[1]), "=&s"(r[2]), "=&s"(r[3])
+      : "s"(p), "v"(dep0), "v"(dep1)
+      : "memory");
+}
+
 // One wavefront per run of at most 64 nodes of one cell (the cell gather's work items): the
 // cell's (D+1)^2 coefficients are read with scalar loads and enter the lanes' Horner sums
 // as scalar operands; the node coordinates come from the binning's sorted copy (xs, two
@@ -296,23 +317,35 @@ __global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ 
   const int c0 = it.cell[0], c1 = it.cell[1];
   const C *__restrict__ K = kpoly + ((((int64_t)r * nt + it.tl) * n + c0) * n + c1) * (NQ * NQ);
   const int pos = it.q0 + (act ? l : 0);
-  const int32_t node = perm[pos];
-  const cx_t<float> xv = reinterpret_cast<const cx_t<float> *>(xs)[pos];
+  // The node index and coordinates are read with relaxed workgroup-scope loads (plain global
+  // loads): unlike reads through the read-only arguments, they keep their place ahead of the
+  // coefficient loads, so both are in flight together.
+  const int32_t node = __hip_atomic_load(perm + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const unsigned long long xb = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(xs) + pos,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const cx_t<float> xv = cmake<float>(__uint_as_float((unsigned)xb), __uint_as_float((unsigned)(xb >> 32)));
   const float nf = (float)n;
   const float z0 = fmaf(nf, xv.x, (float)(n / 2 - c0)) * 2.f - 1.f;
   const float z1 = fmaf(nf, xv.y, (float)(n / 2 - c1)) * 2.f - 1.f;
+  static_assert(NQ == 8, "four 64-byte coefficient rows per load group");
   float fr = 0.f, fi = 0.f;
+  // rows NQ-1 .. 4 of K, then rows 3 .. 0: two round trips for the cell's coefficients
 #pragma unroll
-  for (int qq = NQ - 1; qq >= 0; --qq) {
-    const C *kr = K + qq * NQ;
-    float tr = kr[NQ - 1].x, ti = kr[NQ - 1].y;
+  for (int grp = 1; grp >= 0; --grp) {
+    v16f_t rows[4];
+    sload_rows4(K + grp * 4 * NQ, rows, fr, fi);
 #pragma unroll
-    for (int q = NQ - 2; q >= 0; --q) {
-      tr = fmaf(tr, z1, kr[q].x);
-      ti = fmaf(ti, z1, kr[q].y);
+    for (int qq = 3; qq >= 0; --qq) {
+      const v16f_t &kr = rows[qq];
+      float tr = kr[2 * NQ - 2], ti = kr[2 * NQ - 1];
+#pragma unroll
+      for (int q = NQ - 2; q >= 0; --q) {
+        tr = fmaf(tr, z1, kr[2 * q]);
+        ti = fmaf(ti, z1, kr[2 * q + 1]);
+      }
+      fr = fmaf(fr, z0, tr);
+      fi = fmaf(fi, z0, ti);
     }
-    fr = fmaf(fr, z0, tr);
-    fi = fmaf(fi, z0, ti);
   }
   if (act) slots[(int64_t)(slot_base + op.term_begin + it.tl) * Vtot + (int64_t)r * vstride + node] = cmake<float>(fr, fi);
 }

@@ -1153,7 +1153,13 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (t == 2) {
       prof_begin(st, "fold_2d");
       const int64_t ncol = (int64_t)nt * o.ntile * 16 * o.n;
-      hipLaunchKernelGGL((k_fold_cols<T>), dim3((unsigned)((ncol + 255) / 256), pl->R), dim3(256), 0, st,
+      // flattened form when a column has at most two halo positions (P <= 2n); tiles covering
+      // one halo column: at most 15 / ts + 1
+      auto fold = o.P > 2 * o.n ? k_fold_cols_seq<T>
+                  : o.ts >= 5   ? k_fold_cols<T, 4>
+                  : o.ts >= 3   ? k_fold_cols<T, 6>
+                                : k_fold_cols<T, 16>;
+      hipLaunchKernelGGL(fold, dim3((unsigned)((ncol + 255) / 256), pl->R), dim3(256), 0, st,
                          (const C *)o.d_patch, o.d_tileseg, op, tile2_args(pl), pl->ragged ? pl->R : 1, o.ts,
                          (C *)o.d_tsum);
       prof_end(st);

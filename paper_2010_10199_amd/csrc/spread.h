@@ -377,13 +377,95 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__res
 // fixed summation order (so the result is deterministic): the columns here, the rows at the
 // start of the order-2 adjoint DFT (k_dft_adj).
 // k_fold_cols: one thread per (right-hand side, term, tile row ty, patch row pr, grid column
-//   l1) adds, over the tile columns tx whose patch covers halo column p = l1 + m - 1 (mod n)
-//   and over each tile's patches in slot order, the patch entries (pr, p - tx ts):
+//   l1) adds, over the halo columns p = l1 + m - 1 (mod n), the tile columns tx whose patch
+//   covers p and each tile's patches in slot order, the patch entries (pr, p - tx ts):
 //   hcol[(r * terms + tl) * ntile + ty][pr][l1].
-template <typename T>
+//   The (p, tx, slot) sequence is flattened: the tiles' slot ranges are read first, all at
+//   once, and the patch entries are then loaded eight at a time and added in sequence order,
+//   so a thread has its loads in flight together instead of one per loop step.
+//   Needs P <= 2n (at most two halo positions per column); NX >= 15 / ts + 1 bounds the
+//   tiles covering one halo column.
+template <typename T, int NX>
 __global__ __launch_bounds__(256) void k_fold_cols(const cx_t<T> *__restrict__ patch,
                                                    const int32_t *__restrict__ tileseg, OrderParams<T> op,
                                                    Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+  constexpr int NC = 2 * NX, U = 8;   // (p, tx) combinations; loads per step
+  const int n = op.n, P = op.P, mm1 = op.m - 1, ntile = ta.ntile, ntiles = ntile * ntile;
+  const int nt = op.term_end - op.term_begin;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // ((tl * ntile + ty) * 16 + pr) * n + l1
+  if (idx >= (int64_t)nt * ntile * 16 * n) return;
+  const int r = blockIdx.y;
+  const int l1 = (int)(idx % n);
+  const int pr = (int)((idx / n) & 15);
+  const int64_t tty = idx / (16 * n);   // tl * ntile + ty
+  const int tl = (int)(tty / ntile), ty = (int)(tty - (int64_t)tl * ntile);
+  const int b = ta.ragged ? r : 0;
+  const int64_t pbase = ta.ragged ? 0 : (int64_t)r * ta.nseg;
+  const int32_t *tsg = tileseg + ((int64_t)tl * B + b) * ntiles + ty * ntile;
+  // combination c = (pi, k): halo column p = p0 + pi n (if p < P), tile tx = tx0(p) + k (if
+  // tx <= tx1(p)); its slots [cs, cs + cc) and patch column co = p - tx ts
+  const int p0 = (l1 + mm1) % n;
+  int txa[2], txb[2];
+#pragma unroll
+  for (int pi = 0; pi < 2; ++pi) {   // first tile ceil((p - 15) / ts) clamped at 0, last floor(p / ts)
+    const int p = p0 + pi * n;
+    txa[pi] = max(0, p - 16 + ts) / ts;
+    txb[pi] = p < P ? min(p / ts, ntile - 1) : -1;
+  }
+  int s0[NC], s1[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {   // every bound load issued before the first use
+    const int tx = txa[c / NX] + c % NX;
+    const int txc = tx <= txb[c / NX] ? tx : 0;   // valid rows of tsg hold ntile + 1 bounds
+    s0[c] = tsg[txc];
+    s1[c] = tsg[txc + 1];
+  }
+  int cs[NC], cc[NC], co[NC], pre[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int tx = txa[c / NX] + c % NX;
+    cs[c] = s0[c];
+    cc[c] = tx <= txb[c / NX] ? s1[c] - s0[c] : 0;
+    co[c] = p0 + (c / NX) * n - tx * ts;
+  }
+  int total = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    pre[c] = total;
+    total += cc[c];
+  }
+  const cx_t<T> *src = patch + pbase * 256 + pr * 16;
+  T re = 0, im = 0;
+  for (int j0 = 0; j0 < total; j0 += U) {
+    cx_t<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u < total ? j0 + u : total - 1;   // past the end: reload the last entry
+      int sg = 0, col = 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)   // the last combination starting at or before j (never empty)
+        if (j >= pre[c]) {
+          sg = cs[c] + (j - pre[c]);
+          col = co[c];
+        }
+      v[u] = src[(int64_t)sg * 256 + col];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + u < total) {
+        re += v[u].x;
+        im += v[u].y;
+      }
+  }
+  hcol[((int64_t)r * nt * ntile + tty) * 16 * n + pr * n + l1] = cmake<T>(re, im);
+}
+
+// k_fold_cols_seq: the same sums, one (p, tx, slot) step at a time, for grids narrower than
+//   the halo (n < 2m - 1, where a column has more than two halo positions).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_cols_seq(const cx_t<T> *__restrict__ patch,
+                                                       const int32_t *__restrict__ tileseg, OrderParams<T> op,
+                                                       Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
   const int n = op.n, P = op.P, mm1 = op.m - 1, ntile = ta.ntile, ntiles = ntile * ntile;
   const int nt = op.term_end - op.term_begin;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // ((tl * ntile + ty) * 16 + pr) * n + l1
