@@ -1153,15 +1153,20 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (t == 2) {
       prof_begin(st, "fold_2d");
       const int64_t ncol = (int64_t)nt * o.ntile * 16 * o.n;
-      // flattened form when a column has at most two halo positions (P <= 2n); tiles covering
-      // one halo column: at most 15 / ts + 1
-      auto fold = o.P > 2 * o.n ? k_fold_cols_seq<T>
-                  : o.ts >= 5   ? k_fold_cols<T, 4>
-                  : o.ts >= 3   ? k_fold_cols<T, 6>
-                                : k_fold_cols<T, 16>;
-      hipLaunchKernelGGL(fold, dim3((unsigned)((ncol + 255) / 256), pl->R), dim3(256), 0, st,
-                         (const C *)o.d_patch, o.d_tileseg, op, tile2_args(pl), pl->ragged ? pl->R : 1, o.ts,
-                         (C *)o.d_tsum);
+      if (o.P <= 2 * o.n && o.ntile <= 32) {
+        // coalesced form: one wavefront per (term, tile row, four patch rows), tile sums in LDS
+        hipLaunchKernelGGL((k_fold_tilesum<T>), dim3((unsigned)(nt * o.ntile * 4), pl->R), dim3(64),
+                           (size_t)o.ntile * 64 * sizeof(C), st, (const C *)o.d_patch, o.d_tileseg, op,
+                           tile2_args(pl), pl->ragged ? pl->R : 1, o.ts, (C *)o.d_tsum);
+      } else {
+        // flattened form when a column has at most two halo positions (P <= 2n), else one step
+        // at a time.  Tiles covering one halo column: at most 15 / ts + 1 <= 16.  (Rows of more
+        // than 32 tiles only occur for ts = 1 within the grid sizes the plan accepts.)
+        auto fold = o.P > 2 * o.n ? k_fold_cols_seq<T> : k_fold_cols<T, 16>;
+        hipLaunchKernelGGL(fold, dim3((unsigned)((ncol + 255) / 256), pl->R), dim3(256), 0, st,
+                           (const C *)o.d_patch, o.d_tileseg, op, tile2_args(pl), pl->ragged ? pl->R : 1, o.ts,
+                           (C *)o.d_tsum);
+      }
       prof_end(st);
       if (int rc = check_launch("k_fold_cols")) return rc;
     } else {

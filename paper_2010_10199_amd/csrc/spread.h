@@ -460,6 +460,82 @@ __global__ __launch_bounds__(256) void k_fold_cols(const cx_t<T> *__restrict__ p
   hcol[((int64_t)r * nt * ntile + tty) * 16 * n + pr * n + l1] = cmake<T>(re, im);
 }
 
+// k_fold_tilesum: the same column sums with coalesced patch reads, one wavefront per (right-
+//   hand side, term, tile row ty, group of four patch rows).  The patches of one tile row are
+//   the consecutive slots of its tiles, so lane (pr, k) reads entry (pr, k) of every slot of
+//   the row in turn (a load instruction covers four whole patch rows), sixteen slots in
+//   flight; the tile of a slot comes from a ballot over the row's tile bounds.  Each lane
+//   sums its entry over the slots of each tile, in slot order, into LDS (tile sums, zero for
+//   tiles without patches); the wavefront then forms every output column of its rows as the
+//   sum over the halo columns p = l1 + m - 1 (mod n), ascending, and over the tiles tx
+//   covering p, ascending, of the tile sums at (pr, p - tx ts).
+//   Needs P <= 2n and ntile <= 32 (LDS: ntile x 64 entries).
+template <typename T>
+__global__ __launch_bounds__(64) void k_fold_tilesum(const cx_t<T> *__restrict__ patch,
+                                                     const int32_t *__restrict__ tileseg, OrderParams<T> op,
+                                                     Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+  using C = cx_t<T>;
+  constexpr int U = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tsum = reinterpret_cast<C *>(smem_raw);   // [tx][row of the group][column], 64 per tile
+  const int n = op.n, P = op.P, mm1 = op.m - 1, ntile = ta.ntile, ntiles = ntile * ntile;
+  const int nt = op.term_end - op.term_begin;
+  const int lane = threadIdx.x;
+  const int g = blockIdx.x & 3;                // patch rows 4g .. 4g + 3
+  const int tty = blockIdx.x >> 2;             // tl * ntile + ty
+  const int tl = tty / ntile, ty = tty - tl * ntile;
+  const int r = blockIdx.y;
+  const int b = ta.ragged ? r : 0;
+  const int64_t pbase = ta.ragged ? 0 : (int64_t)r * ta.nseg;
+  const int32_t *tsg = tileseg + ((int64_t)tl * B + b) * ntiles + ty * ntile;
+  const int bound = lane < ntile ? tsg[lane] : 0x7fffffff;   // first slot of tile `lane`
+  const int sbeg = tsg[0], send = tsg[ntile];
+  for (int tx = 0; tx < ntile; ++tx) tsum[tx * 64 + lane] = cmake<T>((T)0, (T)0);
+  const C *src = patch + (pbase + sbeg) * 256 + 64 * g + lane;
+  T sr = 0, si = 0;
+  int ct = -1;   // tile being summed
+  for (int j0 = sbeg; j0 < send; j0 += U) {
+    C v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u < send ? j0 + u : send - 1;   // past the end: reload the last slot
+      v[u] = src[(int64_t)(j - sbeg) * 256];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u;
+      if (j < send) {
+        // tile of slot j: the last tile whose first slot is <= j (bounds are nondecreasing)
+        const int tx = __popcll(__ballot(bound <= j)) - 1;
+        if (tx != ct) {
+          if (ct >= 0) tsum[ct * 64 + lane] = cmake<T>(sr, si);
+          sr = 0;
+          si = 0;
+          ct = tx;
+        }
+        sr += v[u].x;
+        si += v[u].y;
+      }
+    }
+  }
+  if (ct >= 0) tsum[ct * 64 + lane] = cmake<T>(sr, si);
+  __syncthreads();
+  for (int o = lane; o < 4 * n; o += 64) {
+    const int rl = o / n, l1 = o - rl * n;
+    const int p0 = (l1 + mm1) % n;
+    T re = 0, im = 0;
+    for (int p = p0; p < P; p += n) {
+      const int tx0 = max(0, p - 16 + ts) / ts, tx1 = min(p / ts, ntile - 1);
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const C t = tsum[tx * 64 + rl * 16 + (p - tx * ts)];
+        re += t.x;
+        im += t.y;
+      }
+    }
+    hcol[((int64_t)r * nt * ntile + tty) * 16 * n + (4 * g + rl) * n + l1] = cmake<T>(re, im);
+  }
+}
+
 // k_fold_cols_seq: the same sums, one (p, tx, slot) step at a time, for grids narrower than
 //   the halo (n < 2m - 1, where a column has more than two halo positions).
 template <typename T>

@@ -32,6 +32,9 @@ CASES = [
     ("cells-2d-R2", 3, 2, (8, 6), 20000, 2, 0, 0.0),
     ("cells-ragged-2d", 3, 2, (6, 4), [10000, 12000], 2, 0, 0.0),
     ("cells-3d", 3, 3, (4, 4, 4), 30000, 1, 0, 0.0),
+    # an order-2 grid with more than 32 tiles per row (the flattened column fold): m = 8,
+    # tiles of one cell
+    ("wide-grid-m8", 2, 2, (4, 24), 600, 1, 8, 2.0),
 ]
 
 # forward gather path per order of the cell cases: FP32 takes the polynomial gather for
