@@ -395,12 +395,25 @@ __global__ __launch_bounds__(256) void k_reduce_f(const cx_t<T> *__restrict__ fh
   const bool active = node < it.count;
   const int64_t v = it.v0 + node;
   T re = 0, im = 0;
-  if (active)
-    for (int b = p; b < nslots; b += 4) {
-      const cx_t<T> q = slots[(int64_t)b * Vtot + v];
-      re += q.x;
-      im += q.y;
+  if (active) {
+    // slots p, p + 4, ... in order; sixteen loads in flight per step (past the end: reload
+    // the step's first slot, not added)
+    constexpr int U = 16;
+    for (int b0 = p; b0 < nslots; b0 += 4 * U) {
+      cx_t<T> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = b0 + 4 * u < nslots ? b0 + 4 * u : b0;
+        q[u] = slots[(int64_t)b * Vtot + v];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b0 + 4 * u < nslots) {
+          re += q[u].x;
+          im += q[u].y;
+        }
     }
+  }
   part[p][threadIdx.x & 63] = cmake<T>(re, im);
   __syncthreads();
   if (p == 0 && active) {
@@ -513,12 +526,14 @@ template <typename T, int ORDER>
 __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
                                                      const DevTerm *__restrict__ terms, OrderParams<T> op,
                                                      const T *__restrict__ colscale, int64_t ncoef,
-                                                     cx_t<T> *__restrict__ fhat, int ntile, int ts) {
+                                                     cx_t<T> *__restrict__ fhat, int ntile, int ts, int nsplit) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
   const int tid = threadIdx.x, BS = blockDim.x;
-  const int tl = blockIdx.x;
+  // order 2: nsplit workgroups per term, workgroup sp computing the coefficient columns
+  // a2 in [sp K / nsplit, (sp + 1) K / nsplit) (both DFT stages split along a2)
+  const int tl = blockIdx.x / nsplit, sp = blockIdx.x - tl * nsplit;
   const DevTerm tm = terms[op.term_begin + tl];
   const int r = blockIdx.y;
   const int nt = op.term_end - op.term_begin;
@@ -557,7 +572,15 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
     const C *hc = gsum + ((int64_t)r * nt + tl) * ntile * 16 * n;
     C *HCl = reinterpret_cast<C *>(smem_raw + stage + (size_t)K * n * sizeof(C));
     if (staged) {
-      for (int i = tid; i < ntile * 16 * n; i += BS) HCl[i] = hc[i];
+      const int nh = ntile * 16 * n;
+      for (int i0 = tid; i0 < nh; i0 += 4 * BS) {   // four loads in flight per thread
+        C v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = hc[i0 + u * BS < nh ? i0 + u * BS : i0];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u * BS < nh) HCl[i0 + u * BS] = v[u];
+      }
       __syncthreads();
     }
     const C *HC = staged ? HCl : hc;
@@ -608,10 +631,11 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
     // Each sum is split over adjacent lanes (two for the first stage, four for the second,
     // lanes i with the same i >> 1 or i >> 2, always in the same loop iteration) and the
     // parts are added by lane shuffles in a fixed order.
-    C *H = S + n * n;   // n x K
-    for (int i = tid; i < 2 * n * K; i += BS) {
+    const int a2lo = sp * K / nsplit, KW = (sp + 1) * K / nsplit - a2lo;   // this workgroup's columns
+    C *H = S + n * n;   // n x KW
+    for (int i = tid; i < 2 * n * KW; i += BS) {
       const int o = i >> 1, half = i & 1;
-      const int l1 = o / K, a2 = o - l1 * K;
+      const int l1 = o / KW, a2 = a2lo + (o - l1 * KW);
       const C *w = Wt + a2;
       T re = 0, im = 0;
       for (int l2 = (half * n) >> 1; l2 < ((half + 1) * n) >> 1; ++l2) {
@@ -625,13 +649,13 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
       if (half == 0) H[o] = cmake<T>(re, im);
     }
     __syncthreads();
-    for (int i = tid; i < 4 * K * K; i += BS) {
-      const int o = i >> 2, part = i & 3;
-      const int a1 = o / K, a2 = o - a1 * K;
+    for (int i = tid; i < 4 * K * KW; i += BS) {
+      const int oo = i >> 2, part = i & 3;
+      const int a1 = oo / KW, a2w = oo - a1 * KW, a2 = a2lo + a2w, o = a1 * K + a2;
       const C *w = Wt + a1;
       T re = 0, im = 0;
       for (int l1 = (part * n) >> 2; l1 < ((part + 1) * n) >> 2; ++l1) {
-        const C v = H[l1 * K + a2];
+        const C v = H[l1 * KW + a2w];
         const T c = w[l1 * K].x, s = w[l1 * K].y;
         re = fma(v.x, c, fma(v.y, s, re));
         im = fma(v.y, c, fma(-v.x, s, im));
@@ -1183,15 +1207,18 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (t == 1) {
       if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, 0, 0);
+                         colscale, pl->ncoef, (C *)fhat, 0, 0, 1);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_dft_adj<T, 2>), grid, dim3(2 * kPackBS), lds, st, (const C *)o.d_tsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, stage_h ? o.ntile : -o.ntile, o.ts);
+      // up to four workgroups per term (column ranges of at least 8 frequencies)
+      const int nsplit = std::max(1, std::min(4, (o.N - 1) / 8));
+      hipLaunchKernelGGL((k_dft_adj<T, 2>), dim3(nt * nsplit, pl->R), dim3(2 * kPackBS), lds, st,
+                         (const C *)o.d_tsum, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat,
+                         stage_h ? o.ntile : -o.ntile, o.ts, nsplit);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, 0, 0);
+                         colscale, pl->ncoef, (C *)fhat, 0, 0, 1);
     }
     prof_end(st);
     if (int rc = check_launch("k_dft_adj")) return rc;
