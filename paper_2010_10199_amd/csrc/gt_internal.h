@@ -34,6 +34,7 @@ constexpr int kGatherNodes = 4;   // sorted nodes per gather thread
 constexpr int kSpreadWaves = 8;   // wavefronts per spread workgroup
 constexpr int kTileBatch = 32;    // nodes per batch of the order-2 tile spread
 constexpr int kTileWaves = 4;     // wavefronts per workgroup of the order-2 tile spread
+constexpr int kTileWavesPerCU = 20;   // order-2 tile spread: at most this many wavefronts per compute unit
 constexpr int kTileRow = 17;      // padded staging row (elements) of the order-2 tile spread
 constexpr double kCellGatherFill = 0.6;   // smallest lane fill of the cell gather's work items
 constexpr size_t kPolyMaxBytes = size_t(1) << 30;   // largest coefficient buffer of the order-2 polynomial gather
@@ -120,6 +121,7 @@ struct OrderHost {
   void *d_xs = nullptr;               // order 2: terms x Mtot x 2 coordinates of the term's axes, sorted order
   // order 2 tile spread: wavefront work list and tile patches (built after the binning)
   int32_t nwaves2 = 0;                // wavefronts (per right-hand side when nodes are shared)
+  int32_t tile_wg_cu = 1;             // workgroups of the tile spread resident per compute unit
   int64_t nseg2 = 0;                  // (wavefront, tile) segments = patches per right-hand side
   int32_t *d_waves2 = nullptr;        // nwaves2 x 4: first position, end position, first segment, dataset
   int32_t *d_tileseg = nullptr;       // (terms x datasets x ntile^2) + 1: first segment of each tile

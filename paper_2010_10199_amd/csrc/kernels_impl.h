@@ -1148,7 +1148,9 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     const Tile2Args ta = tile2_args(pl);
 #define GT_LAUNCH_TILE2(MH)                                                                                       \
   {                                                                                                               \
-    const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T));                    \
+    /* padded so that at most tile_wg_cu workgroups share a compute unit */                                   \
+    const size_t lds2 = std::max<size_t>((size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T)),    \
+                                         pl->lds_limit / o.tile_wg_cu);                                           \
     if (int rc = set_lds(k_spread_tile2<T, MH>, lds2)) return rc;                                                 \
     hipLaunchKernelGGL((k_spread_tile2<T, MH>), dim3((unsigned)((o.nwaves2 + kTileWaves - 1) / kTileWaves),     \
                        (unsigned)(pl->ragged ? 1 : pl->R)), dim3(64 * kTileWaves), lds2, st, (const T *)o.d_xs,      \

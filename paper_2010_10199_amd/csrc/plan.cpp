@@ -292,9 +292,12 @@ void free_plan(gt_plan *pl) {
 
 
 // Work list of the order-2 tile spread (needs the binning's tile boundaries on the host).
-// Each (term, dataset) gets ceil(nodes / target) wavefronts over equal runs of its sorted
-// positions, sized so that all wavefronts of all right-hand sides fit in one resident round
-// (at least 256 nodes each).  A wavefront writes one 16 x 16 patch per tile it meets, in
+// The wavefronts of all right-hand sides make one resident round of tile_wg_cu workgroups
+// per compute unit (as many as the staging LDS allows, at most kTileWavesPerCU / kTileWaves);
+// the launch pads the LDS so that no compute unit takes more, since a few compute units
+// with an extra workgroup would finish last.  Each (term, dataset) gets its share of the
+// wavefronts, rounded down (at least one, at least 256 nodes each), over equal runs of its
+// sorted positions.  A wavefront writes one 16 x 16 patch per tile it meets, in
 // tile order, so its segments are numbered consecutively from its first segment; the
 // segments of one tile are consecutive too (waves follow the sorted order), which gives the
 // fold its per-tile segment ranges.
@@ -312,8 +315,10 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "tile boundaries");
   const int64_t total = (int64_t)nt * pl->Mtot;
   const int reff = pl->ragged ? 1 : pl->R;
-  const int64_t want_waves = std::max<int64_t>(1, (int64_t)pl->num_cu * 20 / reff);
-  const int64_t target = std::max<int64_t>(256, (total + want_waves - 1) / want_waves);
+  // (the LDS of a compute unit equals the per-workgroup limit on this GPU)
+  const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * 3 * pl->rsize;   // complex + real rows
+  o.tile_wg_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(kTileWavesPerCU / kTileWaves, pl->lds_limit / lds2));
+  const int64_t want_waves = std::max<int64_t>(1, (int64_t)pl->num_cu * kTileWaves * o.tile_wg_cu / reff);
   std::vector<int32_t> waves;
   std::vector<int32_t> tileseg((size_t)nt * B * ntiles + 1, 0);
   int64_t nseg = 0;
@@ -323,7 +328,7 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
       const int64_t tb0 = ((int64_t)tl * B + b) * ntiles;
       const int64_t P0 = cs[key0], P1 = cs[key0 + ntiles * TT];
       const int64_t Mb = P1 - P0;
-      const int64_t nw = Mb > 0 ? (Mb + target - 1) / target : 0;
+      const int64_t nw = Mb > 0 ? std::max<int64_t>(1, std::min<int64_t>((Mb + 255) / 256, Mb * want_waves / total)) : 0;
       std::vector<int32_t> tfirst(ntiles, -1);
       int64_t tile = 0;
       for (int64_t w = 0; w < nw; ++w) {
