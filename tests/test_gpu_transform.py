@@ -35,6 +35,9 @@ CASES = [
     # an order-2 grid with more than 32 tiles per row (the flattened column fold): m = 8,
     # tiles of one cell
     ("wide-grid-m8", 2, 2, (4, 24), 600, 1, 8, 2.0),
+    # column sums of an order-2 term too large for the adjoint DFT's LDS (n = 64, 13 tiles per
+    # row): the separate tile-sum fold kernel
+    ("unstaged-fold-2d", 2, 2, (4, 32), 800, 1, 6, 2.0),
 ]
 
 # forward gather path per order of the cell cases: FP32 takes the polynomial gather for
