@@ -500,12 +500,41 @@ __global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict
   double re = 0, im = 0;
   if (active) {
     const DevTerm tm = terms[op.term_begin + tl];
-    for (int s = item_begin[r] + q; s < item_begin[r + 1]; s += 4) {
-      const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
-      for (int p = (l + mm1) % n; p < P; p += n) {
-        const cx_t<T> v = src[p];
-        re += (double)v.x;
-        im += (double)v.y;
+    const int s0 = item_begin[r] + q, s1 = item_begin[r + 1];
+    const int p0 = (l + mm1) % n;
+    if (P <= 2 * n) {
+      // at most two halo copies p0, p0 + n: items q, q + 4, ... eight at a time, both copies'
+      // loads in flight together (past the end: reload the step's first item, not added)
+      constexpr int U = 8;
+      const bool two = p0 + n < P;
+      for (int sa = s0; sa < s1; sa += 4 * U) {
+        cx_t<T> v0[U], v1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int s = sa + 4 * u < s1 ? sa + 4 * u : sa;
+          const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
+          v0[u] = src[p0];
+          v1[u] = src[two ? p0 + n : p0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (sa + 4 * u < s1) {
+            re += (double)v0[u].x;
+            im += (double)v0[u].y;
+            if (two) {
+              re += (double)v1[u].x;
+              im += (double)v1[u].y;
+            }
+          }
+      }
+    } else {
+      for (int s = s0; s < s1; s += 4) {
+        const cx_t<T> *src = gpart + (int64_t)s * gstride + tm.gpart_off + o * P;
+        for (int p = p0; p < P; p += n) {
+          const cx_t<T> v = src[p];
+          re += (double)v.x;
+          im += (double)v.y;
+        }
       }
     }
   }
@@ -610,13 +639,17 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
   __syncthreads();
   // conj twiddles: e^{-2 pi i k l / n}
   if (ORDER == 1) {
-    for (int a = tid; a < K; a += BS) {
+    // each sum split over 8 adjacent lanes (lanes i with the same i >> 3, l in eighths of
+    // [0, n)), the parts added by lane shuffles in a fixed order
+    for (int i = tid; i < 8 * K; i += BS) {
+      const int a = i >> 3, part = i & 7;
       T re = 0, im = 0;
       // walk l with exponent (k_a * l) mod n
       const int k = a - h + (a >= h ? 1 : 0);
       const int km = k < 0 ? k + n : k;
-      int e = 0;
-      for (int l = 0; l < n; ++l) {
+      const int la = (part * n) >> 3, lb = ((part + 1) * n) >> 3;
+      int e = (int)(((int64_t)km * la) % n);
+      for (int l = la; l < lb; ++l) {
         const C v = G[l];
         const T c = Wt[e].x, s = Wt[e].y;
         re = fma(v.x, c, fma(v.y, s, re));
@@ -624,8 +657,16 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
         e += km;
         if (e >= n) e -= n;
       }
-      const T sc = Dc[a] * (cs ? cs[a] : (T)1);
-      dst[a] = cmake<T>(re * sc, im * sc);
+      re += __shfl_xor(re, 1);
+      im += __shfl_xor(im, 1);
+      re += __shfl_xor(re, 2);
+      im += __shfl_xor(im, 2);
+      re += __shfl_xor(re, 4);
+      im += __shfl_xor(im, 4);
+      if (part == 0) {
+        const T sc = Dc[a] * (cs ? cs[a] : (T)1);
+        dst[a] = cmake<T>(re * sc, im * sc);
+      }
     }
   } else if (ORDER == 2) {
     // Each sum is split over adjacent lanes (two for the first stage, four for the second,
