@@ -71,6 +71,10 @@ typedef struct gt_problem {
   int32_t m;                   /* window half-width (Kaiser-Bessel support 2m grid points), 0 = chosen per order
                                   from the precision; otherwise 2..8 */
   double sigma;                /* oversampling factor n/N >= 1.5 of the FFT grids, 0 = 2.0 */
+  const uint8_t *term_mask;    /* host, NULL (all of U_{d_s}) or gt_num_terms(d, ds) flags in the coefficient
+                                  order of the unmasked index set: 0 drops the term, whose coefficients are then
+                                  absent from every coefficient vector (an index set I_N(U) for a subset U, as the
+                                  refit on an active set uses, eq. activeset); the empty set is always kept */
 } gt_problem;
 
 /* Solver report, one entry per right-hand side. */
@@ -101,8 +105,13 @@ int64_t gt_num_terms(int32_t d, int32_t ds);
 int64_t gt_num_coeffs(int32_t d, int32_t ds, const int32_t *N);
 
 /* Term table in coefficient order.  coords: host, |U| x 3 int32, coordinates of each term
- * ascending, -1 padded; offsets: host, |U|+1 coefficient offsets.  Either may be NULL. */
+ * ascending, -1 padded; offsets: host, |U|+1 coefficient offsets.  Either may be NULL.
+ * With a term mask, only the kept terms (|U| = gt_problem_size's nterms). */
 int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets);
+
+/* Terms |U| and coefficients |I_N(U)| of the problem's index set (its term mask applied).
+ * Either output may be NULL. */
+int gt_problem_size(const gt_problem *p, int64_t *nterms, int64_t *ncoeffs);
 
 /* ------------------------------------------------------------------ one-shot transforms
  * Each call builds a plan for (p, x), runs it on `stream`, synchronises `stream` and
@@ -176,6 +185,23 @@ int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *
 int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda,
                       const void *omega, int32_t max_iter, double L, double eta, double tol,
                       void *fhat, gt_solve_info *info, void *stream);
+
+/* ------------------------------------------------------------------ sensitivity analysis
+ * gt_sensitivity: global sensitivity indices (eq. gsi) of the approximation with
+ * coefficients fhat, by Parseval's identity: for every right-hand side r and term u of the
+ * problem's index set, rho[r][u] = sum of |fhat_{u,k}|^2 over the term's coefficients
+ * divided by the variance, the same sum over every term u != empty set (rho[r][0] = 0 for the
+ * empty set; a zero variance gives rho = 0).  Sums in FP64, in a fixed order.
+ *   fhat device, complex (dtype), R x |I|;  rho device, double, R x |U| (output).
+ * Synchronises `stream`.
+ * gt_active_set: the active set U* of eq. activeset from one right-hand side's indices:
+ * the empty set and every term u of the problem with rho[u] > eps[|u| - 1].
+ *   rho host, |U| doubles (the problem's terms);  eps host, ds thresholds;
+ *   mask host, gt_num_terms(d, ds) flags (output), indexed like gt_problem.term_mask, so a
+ *   problem with this mask (and new bandwidths N) gives the refit's index set I_N(U*);
+ *   nactive host, terms in U* (output, may be NULL). */
+int gt_sensitivity(const gt_problem *p, const void *fhat, double *rho, void *stream);
+int gt_active_set(const gt_problem *p, const double *rho, const double *eps, uint8_t *mask, int64_t *nactive);
 
 /* Power-iteration estimate of ||F||_2^2 (50 steps from the all-ones vector, FP64 scalars);
  * synchronises `stream`.  Uses right-hand side 0 of the plan. */

@@ -82,12 +82,18 @@ class GroupedIndexSet:
         return out
 
 
-def grouped_index_set(d: int, ds: int, N: Sequence[int]) -> GroupedIndexSet:
-    """I_N(U_{d_s}) with N_u = N[|u|-1] (eq. groupedset with order-dependent bandwidths)."""
+def grouped_index_set(d: int, ds: int, N: Sequence[int], keep=None) -> GroupedIndexSet:
+    """I_N(U) with N_u = N[|u|-1] (eq. groupedset with order-dependent bandwidths), for
+    U = U_{d_s}, or for the subset of U_{d_s} whose flags in `keep` (one per term of
+    anova_terms(d, ds), in that order) are nonzero; the empty set is always kept."""
     N = tuple(int(n) for n in N)
     if len(N) < ds:
         raise ValueError("need one bandwidth per order 1..ds")
     terms = anova_terms(d, ds)
+    if keep is not None:
+        if len(keep) != len(terms):
+            raise ValueError("keep needs one flag per term of U_{d_s}")
+        terms = [u for u, k in zip(terms, keep) if k or not u]
     freqs = []
     sizes = []
     for u in terms:

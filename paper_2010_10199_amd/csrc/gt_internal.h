@@ -209,6 +209,9 @@ template <typename T> int launch_prepare_nodes(gt_plan *pl, const void *x, hipSt
 template <typename T> int launch_binning(gt_plan *pl, hipStream_t s);   // binning.hip
 
 // ---- solver drivers (solvers.hip) ----
+// Sensitivity indices (eq. gsi) from term offsets goff (device, nterms + 1): rho[r][u].
+template <typename T> int run_sensitivity(const int64_t *goff, int nterms, int64_t ncoef, int R, const void *fhat,
+                                          double *rho, hipStream_t s);
 template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega,
                                    int max_iter, double tol, void *fhat, gt_solve_info *info, hipStream_t s);
 template <typename T> int run_fista(gt_plan *pl, const void *y, const double *lambda, const void *omega,

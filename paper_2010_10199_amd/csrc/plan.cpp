@@ -90,6 +90,26 @@ void dev_free(void *p, hipStream_t) {
 }
 
 // ------------------------------------------------------------------ index set
+// Terms of U_{d_s} in coefficient order (by order, then the sorted coordinates
+// lexicographically), fn(ci, t, c) for each with its index ci in this enumeration (the index
+// of a term mask) and its coordinates c[0..t-1].
+template <typename F>
+static void for_each_term(int d, int ds, F fn) {
+  int64_t ci = 0;
+  for (int t = 0; t <= ds; ++t) {
+    int c[3] = {0, 1, 2};
+    while (true) {
+      fn(ci++, t, (const int *)c);
+      if (t == 0) break;
+      int i = t - 1;
+      while (i >= 0 && c[i] == d - t + i) --i;
+      if (i < 0) break;
+      ++c[i];
+      for (int k = i + 1; k < t; ++k) c[k] = c[k - 1] + 1;
+    }
+  }
+}
+
 static int64_t binom(int n, int k) {
   if (k < 0 || k > n) return 0;
   int64_t r = 1;
@@ -487,8 +507,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     pl->ev_fork = pl->ev_join = nullptr;
   }
 
-  // ---- terms in coefficient order
-  int64_t coef = 0, grid = 0;
+  // ---- terms in coefficient order (ci: index in the unmasked enumeration, for the term mask)
+  int64_t coef = 0, grid = 0, ci = 0;
   for (int t = 0; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
     o.term_begin = (int32_t)pl->terms.size();
@@ -506,7 +526,9 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     int64_t gsz = 1;
     for (int k = 0; k < t; ++k) gsz *= (o.N - 1);
     while (true) {
-      if (t == 0 || c[t - 1] < p->d) {
+      const bool keep = t == 0 || !p->term_mask || p->term_mask[ci];
+      ++ci;
+      if (keep && (t == 0 || c[t - 1] < p->d)) {
         DevTerm dt{};
         dt.t = t;
         dt.c0 = t > 0 ? c[0] : -1;
@@ -812,29 +834,81 @@ int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets) {
   if (!p) return fail(GT_EINVAL, "problem is NULL");
   if (p->d < 1 || p->ds < 0 || p->ds > p->d) return fail(GT_EINVAL, "need d >= 1 and 0 <= ds <= d");
   if (p->ds > kMaxOrder) return fail(GT_EUNSUPPORTED, "terms of order > 3 are not implemented");
+  for (int t = 1; t <= p->ds; ++t)
+    if (p->N[t - 1] < 2 || p->N[t - 1] % 2) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
   int64_t i = 0, off = 0;
-  for (int t = 0; t <= p->ds; ++t) {
-    if (t > 0 && (p->N[t - 1] < 2 || p->N[t - 1] % 2)) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
+  for_each_term(p->d, p->ds, [&](int64_t ci, int t, const int *c) {
+    if (t > 0 && p->term_mask && !p->term_mask[ci]) return;
     int64_t g = 1;
     for (int k = 0; k < t; ++k) g *= (p->N[t - 1] - 1);
-    std::vector<int> c(t);
-    for (int k = 0; k < t; ++k) c[k] = k;
-    while (true) {
-      if (coords)
-        for (int k = 0; k < 3; ++k) coords[i * 3 + k] = k < t ? c[k] : -1;
-      if (offsets) offsets[i] = off;
-      off += g;
-      ++i;
-      if (t == 0) break;
-      int q = t - 1;
-      while (q >= 0 && c[q] == p->d - t + q) --q;
-      if (q < 0) break;
-      ++c[q];
-      for (int k = q + 1; k < t; ++k) c[k] = c[k - 1] + 1;
-    }
-  }
+    if (coords)
+      for (int k = 0; k < 3; ++k) coords[i * 3 + k] = k < t ? c[k] : -1;
+    if (offsets) offsets[i] = off;
+    off += g;
+    ++i;
+  });
   if (offsets) offsets[i] = off;
   return GT_OK;
+}
+
+int gt_problem_size(const gt_problem *p, int64_t *nterms, int64_t *ncoeffs) {
+  if (!p) return fail(GT_EINVAL, "problem is NULL");
+  if (p->d < 1 || p->ds < 0 || p->ds > p->d) return fail(GT_EINVAL, "need d >= 1 and 0 <= ds <= d");
+  if (p->ds > kMaxOrder) return fail(GT_EUNSUPPORTED, "terms of order > 3 are not implemented");
+  for (int t = 1; t <= p->ds; ++t)
+    if (p->N[t - 1] < 2 || p->N[t - 1] % 2) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
+  int64_t nu = 0, ni = 0;
+  for_each_term(p->d, p->ds, [&](int64_t ci, int t, const int *) {
+    if (t > 0 && p->term_mask && !p->term_mask[ci]) return;
+    int64_t g = 1;
+    for (int k = 0; k < t; ++k) g *= (p->N[t - 1] - 1);
+    ++nu;
+    ni += g;
+  });
+  if (nterms) *nterms = nu;
+  if (ncoeffs) *ncoeffs = ni;
+  return GT_OK;
+}
+
+int gt_active_set(const gt_problem *p, const double *rho, const double *eps, uint8_t *mask, int64_t *nactive) {
+  if (!rho || !mask || (!eps && p && p->ds > 0)) return fail(GT_EINVAL, "NULL argument");
+  int64_t nu = 0;
+  if (int rc = gt_problem_size(p, &nu, nullptr)) return rc;
+  int64_t k = 0, na = 0;   // k: index among the problem's terms (rho's index)
+  for_each_term(p->d, p->ds, [&](int64_t ci, int t, const int *) {
+    const bool kept = t == 0 || !p->term_mask || p->term_mask[ci];
+    bool act = false;
+    if (kept) {
+      act = t == 0 || rho[k] > eps[t - 1];
+      ++k;
+    }
+    mask[ci] = act ? 1 : 0;
+    na += act;
+  });
+  if (nactive) *nactive = na;
+  return GT_OK;
+}
+
+int gt_sensitivity(const gt_problem *p, const void *fhat, double *rho, void *stream) {
+  if (!fhat || !rho) return fail(GT_EINVAL, "NULL argument");
+  if (int rc = validate_problem(p)) return rc;
+  int64_t nu = 0;
+  if (int rc = gt_problem_size(p, &nu, nullptr)) return rc;
+  std::vector<int64_t> offs(nu + 1);
+  if (int rc = gt_term_table(p, nullptr, offs.data())) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  int64_t *d_offs = nullptr;
+  hipError_t e = hipMalloc(&d_offs, offs.size() * sizeof(int64_t));
+  if (e != hipSuccess) return hip_fail(e, "term offsets");
+  e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  int rc = e == hipSuccess ? GT_OK : hip_fail(e, "term offsets");
+  if (rc == GT_OK)
+    rc = p->dtype == GT_C64 ? run_sensitivity<float>(d_offs, (int)nu, offs[nu], p->R, fhat, rho, s)
+                            : run_sensitivity<double>(d_offs, (int)nu, offs[nu], p->R, fhat, rho, s);
+  e = hipStreamSynchronize(s);
+  if (rc == GT_OK && e != hipSuccess) rc = hip_fail(e, "sensitivity indices");
+  (void)hipFree(d_offs);
+  return rc;
 }
 
 int gt_plan_create(const gt_problem *p, const void *x, void *stream, gt_plan **out) {

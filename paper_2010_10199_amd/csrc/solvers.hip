@@ -810,6 +810,53 @@ int run_fista(gt_plan *pl, const void *y, const double *lambda, const void *omeg
   return GT_OK;
 }
 
+// ---------------------------------------------------------------- sensitivity indices
+// Global sensitivity indices (eq. gsi) by Parseval's identity: the squared L2 norm of ANOVA
+// term u of the approximation is the sum of |fhat_{u,k}|^2 over the term's coefficients,
+// and the variance is that sum over every term but the empty set.
+// k_term_energy: one workgroup per (term, right-hand side), FP64 sum over the term's
+// coefficients in a fixed order (strided per thread, then the block sum), into rho.
+template <typename T>
+__global__ __launch_bounds__(kVecBS) void k_term_energy(const cx_t<T> *__restrict__ fhat, int64_t ncoef,
+                                                       const int64_t *__restrict__ goff, int nterms,
+                                                       double *__restrict__ rho) {
+  __shared__ double sh[kVecBS / 64 + 1];
+  const int u = blockIdx.x, r = blockIdx.y;
+  const cx_t<T> *f = fhat + (int64_t)r * ncoef;
+  double e = 0;
+  for (int64_t i = goff[u] + threadIdx.x; i < goff[u + 1]; i += blockDim.x) {
+    const cx_t<T> c = f[i];
+    e += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
+  }
+  e = block_sum_all(e, sh);
+  if (threadIdx.x == 0) rho[(int64_t)r * nterms + u] = e;
+}
+
+// k_term_gsi: one workgroup per right-hand side: the variance (terms 1 .. nterms-1, fixed
+// order), then rho[u] = energy[u] / variance in place (0 for the empty set and for a zero
+// variance).  Every energy is read before the block sum's barriers and overwritten after.
+__global__ __launch_bounds__(kVecBS) void k_term_gsi(int nterms, double *__restrict__ rho) {
+  __shared__ double sh[kVecBS / 64 + 1];
+  double *q = rho + (int64_t)blockIdx.x * nterms;
+  double v = 0;
+  for (int u = 1 + threadIdx.x; u < nterms; u += blockDim.x) v += q[u];
+  v = block_sum_all(v, sh);
+  for (int u = threadIdx.x; u < nterms; u += blockDim.x) q[u] = (u > 0 && v > 0) ? q[u] / v : 0.0;
+}
+
+template <typename T>
+int run_sensitivity(const int64_t *goff, int nterms, int64_t ncoef, int R, const void *fhat, double *rho,
+                    hipStream_t s) {
+  if (nterms <= 0) return GT_OK;
+  hipLaunchKernelGGL((k_term_energy<T>), dim3(nterms, R), dim3(kVecBS), 0, s, (const cx_t<T> *)fhat, ncoef, goff,
+                     nterms, rho);
+  hipLaunchKernelGGL(k_term_gsi, dim3(R), dim3(kVecBS), 0, s, nterms, rho);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GT_OK : hip_fail(e, "sensitivity kernels");
+}
+
+template int run_sensitivity<float>(const int64_t *, int, int64_t, int, const void *, double *, hipStream_t);
+template int run_sensitivity<double>(const int64_t *, int, int64_t, int, const void *, double *, hipStream_t);
 template int run_lsqr<float>(gt_plan *, const void *, const double *, const void *, int, double, void *, gt_solve_info *,
                              hipStream_t);
 template int run_lsqr<double>(gt_plan *, const void *, const double *, const void *, int, double, void *,

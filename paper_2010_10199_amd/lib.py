@@ -24,10 +24,10 @@ GT_GATHER_SORTED, GT_GATHER_CELL, GT_GATHER_POLY = 0, 1, 2
 
 # every symbol include/grouped.h declares
 EXPORTS = [
-    "gt_num_terms", "gt_num_coeffs", "gt_term_table", "grouped_trafo", "grouped_adjoint",
+    "gt_num_terms", "gt_num_coeffs", "gt_term_table", "gt_problem_size", "grouped_trafo", "grouped_adjoint",
     "gt_plan_create", "gt_plan_destroy", "gt_plan_trafo", "gt_plan_adjoint", "gt_plan_node_grad",
     "gt_plan_order_info", "gt_plan_gather_path", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
-    "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
+    "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
 ]
 
 
@@ -35,7 +35,7 @@ class GtProblem(C.Structure):
     _fields_ = [
         ("d", C.c_int32), ("ds", C.c_int32), ("N", C.c_int32 * GT_MAX_ORDER), ("M", C.c_int64),
         ("R", C.c_int32), ("offsets", C.POINTER(C.c_int64)), ("dtype", C.c_int32), ("m", C.c_int32),
-        ("sigma", C.c_double),
+        ("sigma", C.c_double), ("term_mask", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -60,6 +60,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} not built: run python -m paper_2010_10199_amd.build")
+    # torch carries its own HIP runtime; loading it first makes the library bind to that same
+    # runtime (the shared-object name is the same), so device memory and streams are shared.
+    # Loaded the other way round, the process holds two runtimes and the library's finds no
+    # device once torch has initialised its own.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER(GtProblem)
@@ -67,6 +75,9 @@ def load(path: str = LIB_PATH):
         "gt_num_terms": (i64, [i32, i32]),
         "gt_num_coeffs": (i64, [i32, i32, C.POINTER(i32)]),
         "gt_term_table": (C.c_int, [P, C.POINTER(i32), C.POINTER(i64)]),
+        "gt_problem_size": (C.c_int, [P, C.POINTER(i64), C.POINTER(i64)]),
+        "gt_sensitivity": (C.c_int, [P, vp, vp, vp]),
+        "gt_active_set": (C.c_int, [P, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(C.c_uint8), C.POINTER(i64)]),
         "grouped_trafo": (C.c_int, [P, vp, vp, vp, vp]),
         "grouped_adjoint": (C.c_int, [P, vp, vp, vp, vp]),
         "gt_plan_create": (C.c_int, [P, vp, vp, C.POINTER(vp)]),
@@ -99,19 +110,30 @@ def _check(rc: int):
 
 
 def make_problem(d: int, ds: int, N: Sequence[int], M: int = 0, R: int = 1, dtype: int = GT_C64,
-                 m: int = 0, sigma: float = 0.0, offsets: Optional[Sequence[int]] = None):
-    """Build a GtProblem; returns (problem, keepalive) - keep the second alive while in use."""
+                 m: int = 0, sigma: float = 0.0, offsets: Optional[Sequence[int]] = None,
+                 term_mask: Optional[Sequence[int]] = None):
+    """Build a GtProblem; returns (problem, keepalive) - keep the second alive while in use.
+    term_mask: None, or gt_num_terms(d, ds) flags (0 drops the term; see gt_problem)."""
     p = GtProblem()
     p.d, p.ds = int(d), int(ds)
     for i in range(GT_MAX_ORDER):
         p.N[i] = int(N[i]) if i < len(N) else 0
     p.M, p.R, p.dtype, p.m, p.sigma = int(M), int(R), int(dtype), int(m), float(sigma)
-    keep = None
+    keep = []
     if offsets is not None:
-        keep = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
-        p.offsets = keep.ctypes.data_as(C.POINTER(C.c_int64))
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        keep.append(offs)
+        p.offsets = offs.ctypes.data_as(C.POINTER(C.c_int64))
     else:
         p.offsets = None
+    if term_mask is not None:
+        mk = np.ascontiguousarray(np.asarray(term_mask, dtype=np.uint8))
+        if mk.shape != (gt_num_terms(d, ds),):
+            raise ValueError("term_mask needs gt_num_terms(d, ds) entries")
+        keep.append(mk)
+        p.term_mask = mk.ctypes.data_as(C.POINTER(C.c_uint8))
+    else:
+        p.term_mask = None
     return p, keep
 
 
@@ -138,15 +160,42 @@ def gt_num_coeffs(d: int, ds: int, N: Sequence[int]) -> int:
     return int(load().gt_num_coeffs(d, ds, arr))
 
 
-def gt_term_table(d: int, ds: int, N: Sequence[int]):
-    """(coords |U| x 3 int32 with -1 padding, offsets |U|+1 int64)."""
-    p, _ = make_problem(d, ds, N, M=1)
-    nt = gt_num_terms(d, ds)
+def gt_term_table(d: int, ds: int, N: Sequence[int], term_mask: Optional[Sequence[int]] = None):
+    """(coords |U| x 3 int32 with -1 padding, offsets |U|+1 int64); with a term mask, the
+    kept terms only."""
+    p, _keep = make_problem(d, ds, N, M=1, term_mask=term_mask)
+    nt = problem_size(p)[0]
     coords = np.zeros((nt, 3), dtype=np.int32)
     offs = np.zeros(nt + 1, dtype=np.int64)
     _check(load().gt_term_table(C.byref(p), coords.ctypes.data_as(C.POINTER(C.c_int32)),
                                 offs.ctypes.data_as(C.POINTER(C.c_int64))))
     return coords, offs
+
+
+def problem_size(problem):
+    """(terms, coefficients) of the problem's index set (term mask applied)."""
+    nt, nc = C.c_int64(), C.c_int64()
+    _check(load().gt_problem_size(C.byref(problem), C.byref(nt), C.byref(nc)))
+    return int(nt.value), int(nc.value)
+
+
+# ---------------------------------------------------------------- sensitivity analysis
+def sensitivity(problem, fhat, rho, stream=None):
+    """Global sensitivity indices into rho (device float64, R x |U|); synchronises."""
+    _check(load().gt_sensitivity(C.byref(problem), _ptr(fhat), _ptr(rho), _stream(stream)))
+
+
+def active_set(problem, rho, eps):
+    """Active-set mask (gt_num_terms(d, ds) uint8) from one right-hand side's indices
+    (host array of the problem's |U| values) and ds thresholds; returns (mask, count)."""
+    r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+    e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(-1))
+    mask = np.zeros(gt_num_terms(problem.d, problem.ds), dtype=np.uint8)
+    na = C.c_int64()
+    _check(load().gt_active_set(C.byref(problem), r.ctypes.data_as(C.POINTER(C.c_double)),
+                                e.ctypes.data_as(C.POINTER(C.c_double)),
+                                mask.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(na)))
+    return mask, int(na.value)
 
 
 # ---------------------------------------------------------------- one-shot transforms

@@ -6,7 +6,7 @@ plants plausible mistakes in the oracle and checks that some pin then fails.
 None of these re-types the oracle's formula: they compare with numpy.fft, with exact
 orthogonality of rank-1 lattices, with independent enumeration rules, with the dense
 d-dimensional matrix built from full frequency vectors, with scipy's LSQR, with dense
-linear algebra and with finite differences.
+linear algebra, with finite differences and with exact grid quadrature.
 """
 from __future__ import annotations
 
@@ -20,6 +20,7 @@ import numpy as np
 from oracle import fista as ofista
 from oracle import index_set as oidx
 from oracle import lsqr as olsqr
+from oracle import sensitivity as osens
 from oracle import transform as otr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -447,6 +448,77 @@ def pin_fista_rate(lam=3.0, K=60) -> float:
 
 # ---------------------------------------------------------------- pin table
 # (name, function, keyword arguments, tolerance): the pin holds when error <= tolerance.
+# ---------------------------------------------------------------- sensitivity analysis
+def _random_fhat(iset, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+
+
+def pin_gsi_quadrature(seed=41, d=3, ds=2, N=(6, 4), K=8) -> float:
+    """rho(u) of eq. gsi against the variances of the evaluated term functions: on the
+    tensor grid {j/K}^d with K >= N, the grid mean of |g|^2 is exactly the squared L2 norm of
+    a trigonometric polynomial g with frequencies in [-N/2, N/2), so ||f_u||^2 and sigma^2(f)
+    come from the transform evaluated on the grid, not from the coefficients."""
+    iset = oidx.grouped_index_set(d, ds, N)
+    fh = _random_fhat(iset, seed)
+    fh[0] = 3.0 - 2.0j                                   # the empty set's value must not count
+    axis = np.arange(K) / K - 0.5
+    x = np.array(list(itertools.product(axis, repeat=d)))
+    f = otr.forward(iset, x, fh)
+    var = np.mean(np.abs(f - np.mean(f)) ** 2)
+    want = np.zeros(iset.n_terms)
+    for i in range(1, iset.n_terms):
+        fu = np.zeros_like(fh)
+        fu[iset.term_slice(i)] = fh[iset.term_slice(i)]
+        want[i] = np.mean(np.abs(otr.forward(iset, x, fu)) ** 2) / var
+    return rel(osens.sensitivity_indices(iset, fh), want)
+
+
+def pin_gsi_invariants(seed=42, d=5, ds=3, N=(8, 6, 4)) -> float:
+    """The indices of the non-empty terms add up to 1; they do not change when the
+    coefficients are scaled or the empty set's coefficient changes; rho(empty set) = 0."""
+    iset = oidx.grouped_index_set(d, ds, N)
+    fh = _random_fhat(iset, seed)
+    rho = osens.sensitivity_indices(iset, fh)
+    g = fh * (0.3 - 1.7j)
+    g[0] = 11.0
+    rho2 = osens.sensitivity_indices(iset, g)
+    return max(abs(np.sum(rho[1:]) - 1.0), float(np.max(np.abs(rho2 - rho))), abs(rho[0]))
+
+
+def pin_active_set_rule() -> float:
+    """eq. activeset on a worked example (d = 3, d_s = 2): terms empty, {0}, {1}, {2},
+    {0,1}, {0,2}, {1,2}; thresholds 0.1 (order 1) and 0.05 (order 2); an index equal to its
+    threshold is not above it."""
+    iset = oidx.grouped_index_set(3, 2, (4, 4))
+    rho = np.array([0.0, 0.5, 0.09, 0.1, 0.2, 0.05, 0.06])
+    got = osens.active_set(iset, rho, (0.1, 0.05))
+    return float(np.sum(got != np.array([1, 1, 0, 0, 1, 0, 1])))
+
+
+def pin_subset_transform(seed=43, d=4, ds=3, N=(8, 6, 4), M=40) -> float:
+    """The transform on I_N(U) for a subset U equals the full transform with the dropped
+    groups' coefficients zero, and its adjoint is the full adjoint restricted to U.  The
+    empty set's flag is 0 here: the empty set stays in every index set whatever its flag."""
+    full = oidx.grouped_index_set(d, ds, N)
+    keep = [0, 1, 0, 1, 1, 0, 0, 1, 1, 1, 0, 1, 0, 1, 0]
+    sub = oidx.grouped_index_set(d, ds, N, keep=keep)
+    g = np.random.default_rng(seed)
+    x = g.random((M, d)) - 0.5
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    fs = _random_fhat(sub, seed + 1)
+    ff = np.zeros(full.n_coeffs, complex)
+    rows = []
+    for i, u in enumerate(sub.terms):
+        j = full.terms.index(u)
+        ff[full.term_slice(j)] = fs[sub.term_slice(i)]
+        rows.append(np.arange(full.offsets[j], full.offsets[j + 1]))
+    rows = np.concatenate(rows)
+    has_empty = 0.0 if sub.terms and sub.terms[0] == () else 1.0   # U* contains the empty set (eq. activeset)
+    return max(rel(otr.forward(sub, x, fs), otr.forward(full, x, ff)),
+               rel(otr.adjoint(sub, x, y), otr.adjoint(full, x, y)[rows]), has_empty)
+
+
 PINS = [
     ("printed_counts", pin_printed_counts, {}, 0.0),
     ("ordering", pin_ordering, {}, 0.0),
@@ -479,4 +551,8 @@ PINS = [
     ("fista_first_steps", pin_fista_first_steps, {}, 1e-13),
     ("fista_rate", pin_fista_rate, {}, 0.0),
     ("power_iteration", pin_power_iteration, {}, 1e-6),
+    ("gsi_quadrature", pin_gsi_quadrature, {}, 1e-12),
+    ("gsi_invariants", pin_gsi_invariants, {}, 1e-13),
+    ("active_set_rule", pin_active_set_rule, {}, 0.0),
+    ("subset_transform", pin_subset_transform, {}, 1e-12),
 ]

@@ -51,3 +51,39 @@ def test_invalid_index_arguments():
     with pytest.raises(lib.GroupedError) as e:
         lib.gt_term_table(6, 4, [8, 6, 4, 4])
     assert e.value.code == lib.GT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("d,ds,N,seed", [(4, 3, [6, 4, 4], 1), (7, 2, [16, 8], 2), (20, 3, [32, 12, 6], 3)])
+def test_masked_index_set_matches_oracle(d, ds, N, seed):
+    """A term mask (the empty set's flag cleared: it stays anyway) gives the oracle's
+    subset index set: sizes, coordinates and coefficient offsets."""
+    nt = lib.gt_num_terms(d, ds)
+    mask = (np.random.default_rng(seed).random(nt) < 0.5).astype(np.uint8)
+    mask[0] = 0
+    p, keep = lib.make_problem(d, ds, N, M=1, term_mask=mask)
+    sub = oidx.grouped_index_set(d, ds, N, keep=mask)
+    assert lib.problem_size(p) == (sub.n_terms, sub.n_coeffs)
+    coords, offs = lib.gt_term_table(d, ds, N, term_mask=mask)
+    want = np.array([list(u) + [-1] * (3 - len(u)) for u in sub.terms], dtype=np.int32)
+    assert np.array_equal(coords, want)
+    assert np.array_equal(offs, sub.offsets)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_active_set_matches_oracle(masked):
+    """gt_active_set against the oracle's rule (eq. activeset) on random indices, with and
+    without a term mask on the problem the indices belong to."""
+    from oracle import sensitivity as osens
+    d, ds, N = 6, 3, [8, 6, 4]
+    g = np.random.default_rng(7)
+    nt = lib.gt_num_terms(d, ds)
+    mask = (g.random(nt) < 0.6).astype(np.uint8) if masked else None
+    p, keep = lib.make_problem(d, ds, N, M=1, term_mask=mask)
+    sub = oidx.grouped_index_set(d, ds, N, keep=mask)
+    rho = g.random(sub.n_terms) * 0.2
+    rho[0] = 0.0
+    eps = [0.1, 0.05, 0.15]
+    got, na = lib.active_set(p, rho, eps)
+    want = osens.active_set(sub, rho, eps)
+    assert np.array_equal(got, want)
+    assert na == int(want.sum())

@@ -36,6 +36,14 @@ MUTATIONS = [
     ("oracle.fista", "ofista", "h = f + ((t - 1.0) / t_next) * (f - f_prev)", "h = f + (t / t_next) * (f - f_prev)",
      "momentum coefficient"),
     ("oracle.fista", "ofista", "grad = rmatvec(Fh - y)", "grad = rmatvec(y - Fh)", "gradient sign"),
+    ("oracle.sensitivity", "osens", "var = np.sum(e[..., 1:], axis=-1, keepdims=True)",
+     "var = np.sum(e, axis=-1, keepdims=True)", "variance including the empty set"),
+    ("oracle.sensitivity", "osens", "out[..., i] = np.sum(g.real ** 2 + g.imag ** 2, axis=-1)",
+     "out[..., i] = np.sum(np.abs(g), axis=-1) ** 2", "term norm as the squared l1 norm"),
+    ("oracle.sensitivity", "osens", "mask[c] = 1 if rho[where[u]] > eps[len(u) - 1] else 0",
+     "mask[c] = 1 if rho[where[u]] >= eps[len(u) - 1] else 0", "threshold not strict"),
+    ("oracle.index_set", "oidx", "terms = [u for u, k in zip(terms, keep) if k or not u]",
+     "terms = [u for u, k in zip(terms, keep) if k]", "subset drops the empty set"),
 ]
 
 
