@@ -7,6 +7,8 @@ Paper passages:
   by Parseval's identity ||f_u||^2 = sum of |fhat_k|^2 over the group, and sigma^2(f) is the
   sum over every group but the empty set's
 * U* = {empty set} union {u : rho(u, S f) > eps_{|u|}}                          (eq. activeset)
+* eps(X, I_N(U)) = ||f - S f|| / ||f||, by Parseval
+  ||f - S f||^2 = ||f||^2 + sum_{k in I} |fhat_k - c_k(f)|^2 - sum_{k in I} |c_k(f)|^2  (Sec. 4, eq. L2error)
 """
 from __future__ import annotations
 
@@ -46,3 +48,14 @@ def active_set(iset: GroupedIndexSet, rho: np.ndarray, eps) -> np.ndarray:
         elif u in where:
             mask[c] = 1 if rho[where[u]] > eps[len(u) - 1] else 0
     return mask
+
+
+def l2_error(iset: GroupedIndexSet, fhat: np.ndarray, exact: np.ndarray, norm2: float) -> float:
+    """eps(X, I_N(U)) of eq. L2error from the approximation's coefficients fhat, the
+    target's exact coefficients on the same index set and its squared L2 norm."""
+    fhat = np.asarray(fhat, dtype=np.complex128)
+    exact = np.asarray(exact, dtype=np.complex128)
+    if fhat.shape[-1] != iset.n_coeffs or exact.shape[-1] != iset.n_coeffs:
+        raise ValueError("coefficient vectors must match the index set")
+    e2 = norm2 + np.sum(np.abs(fhat - exact) ** 2, axis=-1) - np.sum(np.abs(exact) ** 2, axis=-1)
+    return np.sqrt(np.maximum(e2, 0.0) / norm2)

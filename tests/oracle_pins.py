@@ -519,6 +519,61 @@ def pin_subset_transform(seed=43, d=4, ds=3, N=(8, 6, 4), M=40) -> float:
                rel(otr.adjoint(sub, x, y), otr.adjoint(full, x, y)[rows]), has_empty)
 
 
+# ---------------------------------------------------------------- the paper's test function
+def pin_bspline_closed_form(j=4, K=4000, pts=57) -> float:
+    """The closed-form B-spline pieces of the test function (workloads) against their Fourier
+    series as printed (Sec. 4, after eq. testfun), truncated at |k| < K; B2 against 2 sqrt(3)|x|."""
+    import workloads as W
+    x = np.linspace(-0.5, 0.5, pts, endpoint=False) + 0.0041
+    if j == 2:
+        return float(np.max(np.abs(W.bspline(x, 2) - 2.0 * math.sqrt(3.0) * np.abs(x))))
+    k = np.arange(-K, K)
+    ser = np.exp(2j * np.pi * np.outer(x, k)) @ W.bspline_coeff(k, j)
+    return float(np.max(np.abs(ser.real - W.bspline(x, j))))
+
+
+def pin_bspline_unit_norm(K=200000) -> float:
+    """The printed normalisation constants give ||B_j|| = 1 (Parseval, |k| <= K)."""
+    import workloads as W
+    k = np.arange(-K, K + 1)
+    return max(abs(float(np.sum(W.bspline_coeff(k, j) ** 2)) - 1.0) for j in (2, 4, 6))
+
+
+def pin_testfun_anova() -> float:
+    """The exact coefficients of the test function: f_empty = 3 c2 c4 c6 (printed), and the
+    terms with non-zero coefficients are exactly U* = P({1,3,8}) u P({2,5,6}) u P({4,7,9})
+    (1-based, printed): 9 one-, 9 two- and 3 three-dimensional terms."""
+    import workloads as W
+    iset = oidx.grouped_index_set(9, 3, (6, 4, 4))
+    c = W.testfun_coeffs(iset.terms, iset.freqs)
+    prod = W.BSPLINE_NORM[2] * W.BSPLINE_NORM[4] * W.BSPLINE_NORM[6]
+    err = abs(c[0] - 3.0 * prod)
+    groups = [(1, 3, 8), (2, 5, 6), (4, 7, 9)]
+    want = set()
+    for g in groups:
+        for t in range(1, 4):
+            want.update(tuple(i - 1 for i in s) for s in itertools.combinations(g, t))
+    got = {u for i, u in enumerate(iset.terms) if u and np.any(np.abs(c[iset.term_slice(i)]) > 0)}
+    counts = [sum(1 for u in got if len(u) == t) for t in (1, 2, 3)]
+    return float(err + len(got ^ want) + (counts != [9, 9, 3]))
+
+
+def pin_l2_error_quadrature(seed=44, N=8, K=20000) -> float:
+    """eq. L2error by Parseval against direct quadrature of |B4 - S B4|^2 on a fine grid
+    (d = 1, a random trigonometric polynomial S on I_N)."""
+    import workloads as W
+    iset = oidx.grouped_index_set(1, 1, (N,))
+    g = np.random.default_rng(seed)
+    fh = (g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)) * 0.1
+    exact = np.concatenate([[W.BSPLINE_NORM[4]], W.bspline_coeff(iset.freqs[1][:, 0], 4)])
+    fh += exact
+    e = osens.l2_error(iset, fh, exact, 1.0)
+    x = (np.arange(K) / K - 0.5)[:, None]
+    diff = W.bspline(x[:, 0], 4) - otr.forward(iset, x, fh)
+    want = math.sqrt(float(np.mean(np.abs(diff) ** 2)))
+    return abs(e - want) / want
+
+
 PINS = [
     ("printed_counts", pin_printed_counts, {}, 0.0),
     ("ordering", pin_ordering, {}, 0.0),
@@ -555,4 +610,10 @@ PINS = [
     ("gsi_invariants", pin_gsi_invariants, {}, 1e-13),
     ("active_set_rule", pin_active_set_rule, {}, 0.0),
     ("subset_transform", pin_subset_transform, {}, 1e-12),
+    ("bspline_closed_form_2", pin_bspline_closed_form, dict(j=2), 1e-12),
+    ("bspline_closed_form_4", pin_bspline_closed_form, dict(j=4), 1e-10),
+    ("bspline_closed_form_6", pin_bspline_closed_form, dict(j=6), 1e-12),
+    ("bspline_unit_norm", pin_bspline_unit_norm, {}, 1e-12),
+    ("testfun_anova", pin_testfun_anova, {}, 1e-15),
+    ("l2_error_quadrature", pin_l2_error_quadrature, {}, 1e-10),
 ]

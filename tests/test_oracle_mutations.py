@@ -42,6 +42,9 @@ MUTATIONS = [
      "out[..., i] = np.sum(np.abs(g), axis=-1) ** 2", "term norm as the squared l1 norm"),
     ("oracle.sensitivity", "osens", "mask[c] = 1 if rho[where[u]] > eps[len(u) - 1] else 0",
      "mask[c] = 1 if rho[where[u]] >= eps[len(u) - 1] else 0", "threshold not strict"),
+    ("oracle.sensitivity", "osens",
+     "e2 = norm2 + np.sum(np.abs(fhat - exact) ** 2, axis=-1) - np.sum(np.abs(exact) ** 2, axis=-1)",
+     "e2 = norm2 + np.sum(np.abs(fhat - exact) ** 2, axis=-1)", "error without the captured energy"),
     ("oracle.index_set", "oidx", "terms = [u for u, k in zip(terms, keep) if k or not u]",
      "terms = [u for u, k in zip(terms, keep) if k]", "subset drops the empty set"),
 ]

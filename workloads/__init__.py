@@ -65,6 +65,75 @@ def bspline2(x: np.ndarray) -> np.ndarray:
     return 2.0 * math.sqrt(3.0) * np.abs(x)
 
 
+# ---------------------------------------------------------------- the paper's test function
+# f(x) = B2(x_1) B4(x_3) B6(x_8) + B2(x_2) B4(x_5) B6(x_6) + B2(x_4) B4(x_7) B6(x_9) on T^9
+# (Sec. 4, eq. testfun; 0-based coordinates below), with B_j the periodised B-spline pieces
+# whose Fourier coefficients are c_j sinc^j(pi k / j) cos(pi k) and unit L2 norm.  This is
+# the target's definition (samples and exact coefficients for error reports), not a step of
+# the method.
+TESTFUN_GROUPS = ((0, 2, 7), (1, 4, 5), (3, 6, 8))     # coordinates of B2, B4, B6 in each product
+TESTFUN_ORDERS = (2, 4, 6)
+BSPLINE_NORM = {2: math.sqrt(3.0 / 4.0), 4: math.sqrt(315.0 / 604.0), 6: math.sqrt(277200.0 / 655177.0)}
+
+
+def bspline(x: np.ndarray, j: int) -> np.ndarray:
+    """B_j(x) in closed form: c_j times the cardinal B-spline of order j with knot spacing 1/j
+    and unit integral, centred at 1/2 and taken 1-periodic (x in [-1/2, 1/2))."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.where(x < 0.0, x + 0.5, x - 0.5)              # distance from the centre 1/2, periodised
+    s = j * t + j / 2.0                                  # argument of the order-j spline on [0, j]
+    acc = np.zeros_like(s)
+    for i in range(j + 1):
+        acc += (-1) ** i * math.comb(j, i) * np.maximum(s - i, 0.0) ** (j - 1)
+    return BSPLINE_NORM[j] * j * acc / math.factorial(j - 1)
+
+
+def bspline_coeff(k: np.ndarray, j: int) -> np.ndarray:
+    """Fourier coefficient c_j sinc^j(pi k / j) cos(pi k) of B_j (k integer)."""
+    k = np.asarray(k, dtype=np.float64)
+    a = np.pi * k / j
+    sinc = np.where(k == 0, 1.0, np.sin(a) / np.where(k == 0, 1.0, a))
+    return BSPLINE_NORM[j] * sinc ** j * np.cos(np.pi * k)
+
+
+def testfun(x: np.ndarray) -> np.ndarray:
+    """The test function at nodes x (M x 9)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = np.zeros(x.shape[0])
+    for g in TESTFUN_GROUPS:
+        p = np.ones(x.shape[0])
+        for c, j in zip(g, TESTFUN_ORDERS):
+            p *= bspline(x[:, c], j)
+        f += p
+    return f
+
+
+def testfun_coeffs(terms, freqs) -> np.ndarray:
+    """Exact Fourier coefficients of the test function on a grouped index set given as its
+    terms (coordinate tuples) and each term's frequencies (rows of k restricted to u): a
+    product touches term u when u lies in its coordinates, with the other factors at k = 0."""
+    out = []
+    for u, ell in zip(terms, freqs):
+        ell = np.asarray(ell).reshape(-1, len(u)) if u else np.zeros((1, 0))
+        v = np.zeros(ell.shape[0])
+        for g in TESTFUN_GROUPS:
+            if not set(u) <= set(g):
+                continue
+            p = np.ones(ell.shape[0])
+            for c, j in zip(g, TESTFUN_ORDERS):
+                p = p * (bspline_coeff(ell[:, u.index(c)], j) if c in u else BSPLINE_NORM[j])
+            v += p
+        out.append(v)
+    return np.concatenate(out).astype(np.complex128)
+
+
+def testfun_norm2() -> float:
+    """||f||^2: three products of unit norm, and six cross products of disjoint coordinates
+    equal to the product of their means (c2 c4 c6)^2."""
+    m = BSPLINE_NORM[2] * BSPLINE_NORM[4] * BSPLINE_NORM[6]
+    return 3.0 + 6.0 * m * m
+
+
 @dataclass
 class Workload:
     """One synthetic workload: sizes plus its generated inputs."""
