@@ -286,73 +286,93 @@ def run_active_set():
 
 
 def run_testfun():
-    """The paper's LSQR experiment on its test function (Sec. 4, eq. testfun; Sec. 4.1 first
-    experiment): d = 9, d_s = 3, N = 26/6/4 (3,394 coefficients), M = 10,000 uniform nodes,
-    exact samples, no smoothness weights; one batched FP32 LSQR call for the 11 values
-    lambda = e^0 .. e^10 (KT iterations each), the relative L2 error of eq. L2error for each
-    (Parseval with the exact coefficients), the sensitivity indices of the best solution, the
-    active set with thresholds 0.001 and the refit on it.  One node draw (the paper averages
-    100)."""
+    """The paper's LSQR experiments on its test function (Sec. 4, eq. testfun; Sec. 4.1 (i) to
+    (iv)): d = 9, d_s = 3, M = 10,000 uniform nodes; (i) N = 26/6/4 (3,394 coefficients),
+    exact samples, no weights; (ii) (i) with 10 % noise (standard deviation 0.1 x RMS of the
+    samples); (iii) N = 352/20/8 (44,968 coefficients, more than nodes), Sobolev weights
+    omega(k) = prod (1 + |k_j|)^1.5 (eq. sobolevweights), exact samples; (iv) (iii) with 10 %
+    noise.  Each: one batched FP32 LSQR call for lambda = e^0 .. e^10, the relative L2 error
+    of eq. L2error per lambda (Parseval with the exact coefficients), the sensitivity indices
+    of the best solution, the active set with thresholds 0.001 and the refit on it (same
+    bandwidths, weights and lambda).  One node draw (the paper averages 100)."""
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
-    d, ds, N, M, KT = 9, 3, (26, 6, 4), 10000, 50
+    d, ds, M = 9, 3, 10000
     lams = np.exp(np.arange(11.0))
     R = len(lams)
     x = W.uniform_nodes(W.rng(7, W.P_NODES), M, d, "f32")
-    y = W.testfun(x).astype(np.complex64)
-    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
-    coords, offs = lib.gt_term_table(d, ds, N)
-    terms = [tuple(int(c) for c in row if c >= 0) for row in coords]
+    y0 = W.testfun(x)
+    xd = torch.from_numpy(x).cuda()
     n2 = W.testfun_norm2()
-
-    def band(n):
-        return [k for k in range(-n // 2, n // 2) if k != 0]
-
-    def freqs(ts):
-        return [np.array(list(itertools.product(band(N[len(u) - 1]), repeat=len(u)))) if u else np.zeros((1, 0))
-                for u in ts]
-
-    def l2(fh, ex):   # eq. L2error by Parseval
-        return float(np.sqrt(max(n2 + np.sum(np.abs(fh - ex) ** 2) - np.sum(np.abs(ex) ** 2), 0.0) / n2))
-
-    exact = W.testfun_coeffs(terms, freqs(terms))
-    p, keep = lib.make_problem(d, ds, N, M=M, R=R, dtype=lib.GT_C64)
-    nc = int(offs[-1])
-    fh = torch.zeros(R * nc, dtype=torch.complex64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lib.lsqr_solve(p, xd, yd.repeat(R), lams, None, KT, 0.0, fh)
-    torch.cuda.synchronize()
-    t_fit = time.perf_counter() - t0
-    fhs = fh.cpu().numpy().reshape(R, nc).astype(np.complex128)
-    errs = [l2(fhs[r], exact) for r in range(R)]
-    best = int(np.argmin(errs))
-    p1, keep1 = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64)
-    rho = torch.empty(len(terms), dtype=torch.float64, device="cuda")
-    lib.sensitivity(p1, fh[best * nc:(best + 1) * nc], rho)
-    mask, na = lib.active_set(p1, rho.cpu().numpy(), (1e-3, 1e-3, 1e-3))
-    act = [u for u, k in zip(terms, mask) if k]
     want = set()
     for g in W.TESTFUN_GROUPS:
         for t in (1, 2, 3):
             want.update(itertools.combinations(g, t))
-    p2, keep2 = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64, term_mask=mask)
-    nt2, nc2 = lib.problem_size(p2)
-    f2 = torch.zeros(nc2, dtype=torch.complex64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lib.lsqr_solve(p2, xd, yd, [float(lams[best])], None, KT, 0.0, f2)
-    torch.cuda.synchronize()
-    t_refit = time.perf_counter() - t0
-    err_refit = l2(f2.cpu().numpy().astype(np.complex128), W.testfun_coeffs(act, freqs(act)))
-    del keep, keep1, keep2
-    return {"workload": f"test function, d={d}, d_s={ds}, N={N[0]}/{N[1]}/{N[2]}, {nc} coefficients, M={M} uniform "
-                        f"nodes, exact samples, FP32, LSQR {KT} iterations, lambda = e^0..e^10 in one call",
-            "l2_error": {f"e^{r}": errs[r] for r in range(R)}, "best_lambda": f"e^{best}",
-            "active_terms": len(act) - 1, "active_set_is_printed_U*": set(act) - {()} == want,
-            "refit_coeffs": nc2, "l2_error_refit": err_refit, "fit_s": t_fit, "refit_s": t_refit,
-            "paper": "minimal relative L2 error about 9.1e-2 with the active set (average over 100 node draws)"}
+
+    def experiment(N, noise, s_w, iters, printed):
+        y = (W.add_noise(W.rng(7, W.P_NOISE), y0, noise) if noise else y0).astype(np.complex64)
+        yd = torch.from_numpy(y).cuda()
+
+        def band(n):
+            return [k for k in range(-n // 2, n // 2) if k != 0]
+
+        def freqs(ts):
+            return [np.array(list(itertools.product(band(N[len(u) - 1]), repeat=len(u)))) if u
+                    else np.zeros((1, 0), dtype=np.int64) for u in ts]
+
+        def weights(ts):   # eq. sobolevweights, one per coefficient in coefficient order
+            return np.concatenate([np.prod((1.0 + np.abs(f)) ** s_w, axis=1) if u else np.ones(1)
+                                   for u, f in zip(ts, freqs(ts))]).astype(np.float32)
+
+        def l2(fh, ex):    # eq. L2error by Parseval
+            return float(np.sqrt(max(n2 + np.sum(np.abs(fh - ex) ** 2) - np.sum(np.abs(ex) ** 2), 0.0) / n2))
+
+        coords, offs = lib.gt_term_table(d, ds, N)
+        terms = [tuple(int(c) for c in row if c >= 0) for row in coords]
+        nc = int(offs[-1])
+        exact = W.testfun_coeffs(terms, freqs(terms))
+        om = torch.from_numpy(weights(terms)).cuda() if s_w else None
+        p, keep = lib.make_problem(d, ds, N, M=M, R=R, dtype=lib.GT_C64)
+        fh = torch.zeros(R * nc, dtype=torch.complex64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.lsqr_solve(p, xd, yd.repeat(R), lams, om, iters, 0.0, fh)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t0
+        fhs = fh.cpu().numpy().reshape(R, nc).astype(np.complex128)
+        errs = [l2(fhs[r], exact) for r in range(R)]
+        best = int(np.argmin(errs))
+        p1, keep1 = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64)
+        rho = torch.empty(len(terms), dtype=torch.float64, device="cuda")
+        lib.sensitivity(p1, fh[best * nc:(best + 1) * nc], rho)
+        mask, na = lib.active_set(p1, rho.cpu().numpy(), (1e-3, 1e-3, 1e-3))
+        act = [u for u, k in zip(terms, mask) if k]
+        p2, keep2 = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64, term_mask=mask)
+        nt2, nc2 = lib.problem_size(p2)
+        f2 = torch.zeros(nc2, dtype=torch.complex64, device="cuda")
+        om2 = torch.from_numpy(weights(act)).cuda() if s_w else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.lsqr_solve(p2, xd, yd, [float(lams[best])], om2, iters, 0.0, f2)
+        torch.cuda.synchronize()
+        t_refit = time.perf_counter() - t0
+        err_refit = l2(f2.cpu().numpy().astype(np.complex128), W.testfun_coeffs(act, freqs(act)))
+        del keep, keep1, keep2
+        print(f"[bench]   test function N={N} noise={noise} s={s_w}: best {min(errs):.4f}, refit {err_refit:.4f}",
+              file=sys.stderr, flush=True)
+        return {"N": list(N), "coefficients": nc, "noise": noise, "s": s_w, "lsqr_iterations": iters,
+                "l2_error": {f"e^{r}": errs[r] for r in range(R)}, "best_lambda": f"e^{best}",
+                "active_terms": len(act) - 1, "active_set_is_printed_U*": set(act) - {()} == want,
+                "refit_coeffs": nc2, "l2_error_refit": err_refit, "fit_s": t_fit, "refit_s": t_refit,
+                "paper": printed}
+
+    return {"workload": f"test function, d={d}, d_s={ds}, M={M} uniform nodes, FP32, lambda = e^0..e^10 in one "
+                        "LSQR call, one node draw (the paper averages 100)",
+            "i": experiment((26, 6, 4), 0.0, 0.0, 50, "about 9.1e-2 after the refit on U*"),
+            "ii": experiment((26, 6, 4), 0.1, 0.0, 50, "about 0.165 after the refit on U*"),
+            "iii": experiment((352, 20, 8), 0.0, 1.5, 100, "about 1.8e-2 after the refit on U*"),
+            "iv": experiment((352, 20, 8), 0.1, 1.5, 100, "about 0.189 after the refit on U*")}
 
 
 def cpu_baseline(sample_nodes: int):
