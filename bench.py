@@ -375,6 +375,83 @@ def run_testfun():
             "iv": experiment((352, 20, 8), 0.1, 1.5, 100, "about 0.189 after the refit on U*")}
 
 
+def run_testfun_fista():
+    """The paper's FISTA experiments on its test function (Sec. 4.2 (i) to (iv), Algorithm
+    algo:fista): the settings of run_testfun, group lasso over lambda = e^10, e^9, .., e^0,
+    the first from zero and each next one started from the previous solution (the paper's
+    warm-started path), KF constant steps each with L = 1.05 x a 50-step power-iteration
+    estimate; the relative L2 error on U_3 (no refit) per lambda and the active set of the
+    best solution (indices > 0.001).  FP32, one node draw."""
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    d, ds, M, KF = 9, 3, 10000, 200
+    lams = np.exp(np.arange(10.0, -1.0, -1.0))
+    x = W.uniform_nodes(W.rng(7, W.P_NODES), M, d, "f32")
+    y0 = W.testfun(x)
+    xd = torch.from_numpy(x).cuda()
+    n2 = W.testfun_norm2()
+    want = set()
+    for g in W.TESTFUN_GROUPS:
+        for t in (1, 2, 3):
+            want.update(itertools.combinations(g, t))
+
+    def experiment(N, noise, s_w, printed):
+        y = (W.add_noise(W.rng(7, W.P_NOISE), y0, noise) if noise else y0).astype(np.complex64)
+        yd = torch.from_numpy(y).cuda()
+
+        def band(n):
+            return [k for k in range(-n // 2, n // 2) if k != 0]
+
+        coords, offs = lib.gt_term_table(d, ds, N)
+        terms = [tuple(int(c) for c in row if c >= 0) for row in coords]
+        fr = [np.array(list(itertools.product(band(N[len(u) - 1]), repeat=len(u)))) if u
+              else np.zeros((1, 0), dtype=np.int64) for u in terms]
+        nc = int(offs[-1])
+        exact = W.testfun_coeffs(terms, fr)
+        om = None
+        if s_w:
+            w = np.concatenate([np.prod((1.0 + np.abs(f)) ** s_w, axis=1) if u else np.ones(1)
+                                for u, f in zip(terms, fr)]).astype(np.float32)
+            om = torch.from_numpy(w).cuda()
+        p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64)
+        plan = lib.Plan(p, xd, keepalive=keep)
+        L = 1.05 * plan.norm_estimate(50)
+        plan.close()
+        fh = torch.zeros(nc, dtype=torch.complex64, device="cuda")
+        errs, sols = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lam in lams:
+            lib.fista_group_lasso(p, xd, yd, [float(lam)], om, KF, L, 1.0, 0.0, fh)
+            sols.append(fh.clone())
+        torch.cuda.synchronize()
+        t_path = time.perf_counter() - t0
+        for f in sols:
+            fv = f.cpu().numpy().astype(np.complex128)
+            errs.append(float(np.sqrt(max(n2 + np.sum(np.abs(fv - exact) ** 2) - np.sum(np.abs(exact) ** 2), 0.0)
+                                      / n2)))
+        best = int(np.argmin(errs))
+        rho = torch.empty(len(terms), dtype=torch.float64, device="cuda")
+        lib.sensitivity(p, sols[best], rho)
+        mask, na = lib.active_set(p, rho.cpu().numpy(), (1e-3, 1e-3, 1e-3))
+        act = {u for u, k in zip(terms, mask) if k and u}
+        print(f"[bench]   fista test function N={N} noise={noise} s={s_w}: best {min(errs):.4f}",
+              file=sys.stderr, flush=True)
+        return {"N": list(N), "coefficients": nc, "noise": noise, "s": s_w, "steps_per_lambda": KF, "L": L,
+                "l2_error": {f"e^{int(round(np.log(l)))}": e for l, e in zip(lams, errs)},
+                "best_lambda": f"e^{int(round(np.log(lams[best])))}", "best_l2_error": errs[best],
+                "active_terms": len(act), "active_set_is_printed_U*": act == want, "path_s": t_path,
+                "paper": printed}
+
+    return {"workload": f"test function, d={d}, d_s={ds}, M={M} uniform nodes, FP32, group lasso (FISTA) on the "
+                        "warm-started path lambda = e^10 .. e^0, one node draw (the paper averages 100)",
+            "i": experiment((26, 6, 4), 0.0, 0.0, "about 9.2e-2 on U_3"),
+            "ii": experiment((26, 6, 4), 0.1, 0.0, "about 0.202 on U_3"),
+            "iii": experiment((352, 20, 8), 0.0, 1.5, "about 1.7e-2 on U_3"),
+            "iv": experiment((352, 20, 8), 0.1, 1.5, "about 0.203 on U_3")}
+
+
 def cpu_baseline(sample_nodes: int):
     """The FP64 oracle (direct sums) on the first `sample_nodes` nodes, forward + adjoint."""
     import workloads as W
@@ -487,6 +564,7 @@ def main():
         out["active_set"] = run_active_set()
         print("[bench] test function", file=sys.stderr, flush=True)
         out["testfun"] = run_testfun()
+        out["testfun_fista"] = run_testfun_fista()
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
