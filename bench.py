@@ -452,6 +452,64 @@ def run_testfun_fista():
             "iv": experiment((352, 20, 8), 0.1, 1.5, "about 0.203 on U_3")}
 
 
+def run_autograd(steps: int = 10):
+    """The differentiable transform on the ragged workload (64 datasets of 1,000 .. 20,000
+    nodes, d = 8, d_s = 2, N = 32/10, 37 terms, FP32): forward + backward of Re<v, f> with
+    respect to the coefficients and the nodes.  (a) Whole steps through the
+    torch.autograd.Function (a plan per forward: node sort included); (b) the three passes
+    (forward, adjoint, node gradient) on one plan.  Rates in node-terms/s of one pass."""
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    from paper_2010_10199_amd.autograd import grouped_trafo
+    d, ds, N, B = 8, 2, (32, 10), 64
+    sizes = W.ragged_sizes(5, B, 1000, 20000)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    Mt = int(offs[-1])
+    nterms, nc = lib.gt_num_terms(d, ds), lib.gt_num_coeffs(d, ds, N)
+    x = torch.from_numpy(W.uniform_nodes(W.rng(5, W.P_NODES), Mt, d, "f32")).cuda()
+    fh = torch.from_numpy(W.complex_normal(W.rng(5, W.P_COEFFS), (B, nc), "f32")).cuda()
+    v = torch.from_numpy(W.complex_normal(W.rng(5, W.P_GRAD), (Mt,), "f32")).cuda()
+    xt, ft = x.clone().requires_grad_(True), fh.clone().requires_grad_(True)
+
+    def step():
+        f = grouped_trafo(ft, xt, d, ds, N, offsets=offs)
+        (torch.conj(v) * f).real.sum().backward()
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    p, keep = lib.make_problem(d, ds, N, M=0, R=B, dtype=lib.GT_C64, offsets=offs)
+    plan = lib.Plan(p, x, keepalive=keep)
+    f = torch.empty(Mt, dtype=torch.complex64, device="cuda")
+    g = torch.empty(B * nc, dtype=torch.complex64, device="cuda")
+    gx = torch.empty((Mt, d), dtype=torch.float32, device="cuda")
+    times = {}
+    for name, fn in (("forward", lambda: plan.trafo(fh, f)), ("adjoint", lambda: plan.adjoint(v, g)),
+                     ("node_grad", lambda: plan.node_grad(fh, v, gx))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / steps
+    plan.close()
+    nt = Mt * nterms
+    return {"workload": f"ragged: {B} datasets, {Mt} nodes, d={d}, d_s={ds}, N={N[0]}/{N[1]}, {nterms} terms, "
+                        f"{nc} coefficients per dataset, FP32",
+            "autograd_step_ms": t_step * 1e3,
+            "autograd_node_terms_per_s": 3 * nt / t_step,
+            "plan_passes_ms": {k: t * 1e3 for k, t in times.items()},
+            "plan_passes_node_terms_per_s": {k: nt / t for k, t in times.items()},
+            "note": "autograd steps build a plan (node sort) per forward; rates count the three passes"}
+
+
 def cpu_baseline(sample_nodes: int):
     """The FP64 oracle (direct sums) on the first `sample_nodes` nodes, forward + adjoint."""
     import workloads as W
@@ -565,6 +623,8 @@ def main():
         print("[bench] test function", file=sys.stderr, flush=True)
         out["testfun"] = run_testfun()
         out["testfun_fista"] = run_testfun_fista()
+        print("[bench] autograd", file=sys.stderr, flush=True)
+        out["autograd"] = run_autograd()
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
