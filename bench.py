@@ -457,7 +457,8 @@ def run_autograd(steps: int = 10):
     nodes, d = 8, d_s = 2, N = 32/10, 37 terms, FP32): forward + backward of Re<v, f> with
     respect to the coefficients and the nodes.  (a) Whole steps through the
     torch.autograd.Function (a plan per forward: node sort included); (b) the three passes
-    (forward, adjoint, node gradient) on one plan.  Rates in node-terms/s of one pass."""
+    (forward, adjoint, node gradient) on one plan; (c) forward + coefficient gradient with
+    GroupedTrafoFixedNodes (one plan for all steps).  Rates in node-terms/s of the passes."""
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
@@ -484,6 +485,23 @@ def run_autograd(steps: int = 10):
         step()
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
+    from paper_2010_10199_amd.autograd import GroupedTrafoFixedNodes
+    fixed = GroupedTrafoFixedNodes(x, d, ds, N, offsets=offs)
+    fc = fh.clone().requires_grad_(True)
+
+    def step_fixed():
+        f = fixed(fc)
+        (torch.conj(v) * f).real.sum().backward()
+
+    for _ in range(2):
+        step_fixed()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_fixed()
+    torch.cuda.synchronize()
+    t_fixed = (time.perf_counter() - t0) / steps
+    fixed.close()
     p, keep = lib.make_problem(d, ds, N, M=0, R=B, dtype=lib.GT_C64, offsets=offs)
     plan = lib.Plan(p, x, keepalive=keep)
     f = torch.empty(Mt, dtype=torch.complex64, device="cuda")
@@ -505,9 +523,12 @@ def run_autograd(steps: int = 10):
                         f"{nc} coefficients per dataset, FP32",
             "autograd_step_ms": t_step * 1e3,
             "autograd_node_terms_per_s": 3 * nt / t_step,
+            "fixed_nodes_step_ms": t_fixed * 1e3,
+            "fixed_nodes_node_terms_per_s": 2 * nt / t_fixed,
             "plan_passes_ms": {k: t * 1e3 for k, t in times.items()},
             "plan_passes_node_terms_per_s": {k: nt / t for k, t in times.items()},
-            "note": "autograd steps build a plan (node sort) per forward; rates count the three passes"}
+            "note": "autograd steps build a plan (node sort) per forward and count three passes (forward, "
+                    "adjoint, node gradient); fixed-nodes steps reuse one plan and count two (forward, adjoint)"}
 
 
 def cpu_baseline(sample_nodes: int):

@@ -4,7 +4,8 @@ forward:   f = F(X) fhat                              (gt_plan_trafo)
 backward:  grad_fhat = F(X)^H grad_f                  (gt_plan_adjoint; F is C-linear)
            grad_x[v, j] = Re(conj(d f_v / d x_{v,j}) grad_f_v)   (gt_plan_node_grad)
 with grad_f the conjugate-Wirtinger gradient torch passes to backward.  Batched over R
-right-hand sides on shared nodes or over ragged datasets (offsets), one plan per call.
+right-hand sides on shared nodes or over ragged datasets (offsets), one plan per call;
+GroupedTrafoFixedNodes keeps one plan for nodes that do not change (coefficient gradients).
 """
 from __future__ import annotations
 
@@ -69,3 +70,60 @@ def grouped_trafo(fhat: torch.Tensor, x: torch.Tensor, d: int, ds: int, N: Seque
     """Differentiable f = F(X) fhat.  fhat: (R, |I|) or (|I|,) complex; x: (Mtot, d) real."""
     return GroupedTrafo.apply(fhat, x, int(d), int(ds), tuple(int(v) for v in N),
                               None if offsets is None else tuple(int(v) for v in offsets), int(m), float(sigma))
+
+
+class _TrafoOnPlan(torch.autograd.Function):
+    """f = F fhat on a prepared plan; backward gives the coefficients' gradient only."""
+
+    @staticmethod
+    def forward(ctx, fhat, owner):
+        fhat_c = fhat.detach().contiguous()
+        f = torch.empty(owner.nout, dtype=fhat.dtype, device=fhat.device)
+        owner.plan.trafo(fhat_c, f)
+        ctx.owner = owner
+        ctx.shape_fhat = fhat.shape
+        return f.view(owner.R, -1) if (owner.offsets is None and fhat.dim() == 2) else f
+
+    @staticmethod
+    def backward(ctx, gf):
+        grad_fhat = None
+        if ctx.needs_input_grad[0]:
+            owner = ctx.owner
+            grad_fhat = torch.empty(ctx.shape_fhat, dtype=gf.dtype, device=gf.device)
+            owner.plan.adjoint(gf.contiguous(), grad_fhat)
+        return grad_fhat, None
+
+
+class GroupedTrafoFixedNodes:
+    """Differentiable f = F(X) fhat for nodes fixed at construction: the plan (node copy and
+    sort, the costly part of a call) is built once and reused by every call, which suits
+    fitting coefficients to fixed data.  Gradients flow to fhat only; the nodes are copied
+    when the object is built, so later changes to x are not seen (build a new object).
+
+    x: (Mtot, d) real CUDA tensor; calls take fhat (R, |I|) or (|I|,) complex of the matching
+    precision and return f as grouped_trafo does."""
+
+    def __init__(self, x: torch.Tensor, d: int, ds: int, N: Sequence[int], R: int = 1,
+                 offsets: Optional[Sequence[int]] = None, m: int = 0, sigma: float = 0.0):
+        if not x.is_cuda:
+            raise RuntimeError("grouped transform runs on the GPU only")
+        code = lib.GT_C64 if x.dtype == torch.float32 else lib.GT_C128 if x.dtype == torch.float64 else None
+        if code is None:
+            raise TypeError("x must be float32 or float64")
+        self.offsets = None if offsets is None else tuple(int(v) for v in offsets)
+        self.R = int(R) if offsets is None else len(self.offsets) - 1
+        x_c = x.detach().contiguous()
+        Mx = x_c.shape[0]
+        prob, keep = lib.make_problem(d, ds, N, M=Mx if offsets is None else 0, R=self.R, dtype=code, m=m,
+                                      sigma=sigma, offsets=self.offsets)
+        self.plan = lib.Plan(prob, x_c, keepalive=keep)
+        self.nout = self.R * Mx if offsets is None else Mx
+        self.cdtype = torch.complex64 if code == lib.GT_C64 else torch.complex128
+
+    def __call__(self, fhat: torch.Tensor) -> torch.Tensor:
+        if fhat.dtype != self.cdtype:
+            raise TypeError("fhat precision does not match the nodes")
+        return _TrafoOnPlan.apply(fhat, self)
+
+    def close(self):
+        self.plan.close()
