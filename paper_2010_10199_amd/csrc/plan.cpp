@@ -311,6 +311,18 @@ void free_plan(gt_plan *pl) {
 }
 
 
+// The binning's cell starts of order t on the host (nt x B x nkey + 1 positions), copied
+// once per plan for both setups below.
+static int fetch_cell_starts(gt_plan *pl, int t, hipStream_t s, std::vector<int64_t> &cs) {
+  const OrderHost &o = pl->ord[t];
+  const int B = pl->ragged ? pl->R : 1;
+  const int64_t nkeys = (int64_t)(o.term_end - o.term_begin) * B * o.nkey + 1;
+  cs.resize(nkeys);
+  hipError_t e = hipMemcpyAsync(cs.data(), o.d_cstart, nkeys * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? GT_OK : hip_fail(e, "cell boundaries");
+}
+
 // Work list of the order-2 tile spread (needs the binning's tile boundaries on the host).
 // The wavefronts of all right-hand sides make one resident round of tile_wg_cu workgroups
 // per compute unit (as many as the staging LDS allows, at most kTileWavesPerCU / kTileWaves);
@@ -321,18 +333,13 @@ void free_plan(gt_plan *pl) {
 // tile order, so its segments are numbered consecutively from its first segment; the
 // segments of one tile are consecutive too (waves follow the sorted order), which gives the
 // fold its per-tile segment ranges.
-static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
+static int setup_tile_spread(gt_plan *pl, const std::vector<int64_t> &cs) {
   OrderHost &o = pl->ord[2];
   const int nt = o.term_end - o.term_begin;
   if (nt == 0) return GT_OK;
   const int B = pl->ragged ? pl->R : 1;
   const int TS = o.ts, TT = TS * TS;
   const int64_t ntiles = (int64_t)o.ntile * o.ntile;
-  const int64_t nkeys = (int64_t)nt * B * o.nkey + 1;
-  std::vector<int64_t> cs(nkeys);
-  hipError_t e = hipMemcpyAsync(cs.data(), o.d_cstart, nkeys * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "tile boundaries");
   const int64_t total = (int64_t)nt * pl->Mtot;
   const int reff = pl->ragged ? 1 : pl->R;
   // (the LDS of a compute unit equals the per-workgroup limit on this GPU)
@@ -379,8 +386,8 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
   int rc;
   if ((rc = upload_raw(waves, &o.d_waves2)) || (rc = upload_raw(tileseg, &o.d_tileseg))) return rc;
   const size_t csz = 2 * pl->rsize;
-  if ((rc = dev_alloc(&o.d_patch, (size_t)reff * std::max<int64_t>(1, nseg) * 256 * csz, s))) return rc;
-  if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * o.ntile * 16 * o.n * csz, s))) return rc;
+  if ((rc = dev_alloc(&o.d_patch, (size_t)reff * std::max<int64_t>(1, nseg) * 256 * csz, nullptr))) return rc;
+  if ((rc = dev_alloc(&o.d_tsum, (size_t)pl->R * nt * o.ntile * 16 * o.n * csz, nullptr))) return rc;
   return GT_OK;
 }
 
@@ -388,7 +395,7 @@ static int setup_tile_spread(gt_plan *pl, hipStream_t s) {
 // cell of one term and dataset.  Kept only when the runs fill at least kCellGatherFill of the
 // lanes they occupy (otherwise the order keeps k_gather_sorted, whose workgroups take any 1024
 // consecutive positions).
-static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
+static int setup_cell_gather(gt_plan *pl, const std::vector<int64_t> (&cstarts)[kMaxOrder + 1], hipStream_t s) {
   for (int t = 1; t <= pl->ds; ++t) {
     OrderHost &o = pl->ord[t];
     o.citems.clear();
@@ -396,12 +403,14 @@ static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
     const int nt = o.term_end - o.term_begin;
     if (nt == 0 || (int64_t)nt * pl->Mtot >= (int64_t(1) << 31)) continue;
     const int B = pl->ragged ? pl->R : 1;
-    const int64_t nkeys = (int64_t)nt * B * o.nkey + 1;
-    std::vector<int64_t> cs(nkeys);
-    hipError_t e = hipMemcpyAsync(cs.data(), o.d_cstart, nkeys * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "cell boundaries");
+    const std::vector<int64_t> &cs = cstarts[t];
+    // lane fill of the items (runs of <= 64 nodes of one cell), decided before building them
+    int64_t nitems = 0;
+    for (size_t k = 0; k + 1 < cs.size(); ++k) nitems += (cs[k + 1] - cs[k] + 63) / 64;
+    const double fill = nitems == 0 ? 0.0 : (double)((int64_t)nt * pl->Mtot) / (64.0 * (double)nitems);
+    if (fill < kCellGatherFill || nitems >= (int64_t(1) << 31)) continue;
     std::vector<CellItem> items;
+    items.reserve((size_t)nitems);
     std::vector<int32_t> begin(nt + 1, 0);
     for (int tl = 0; tl < nt; ++tl) {
       begin[tl] = (int32_t)items.size();
@@ -438,8 +447,6 @@ static int setup_cell_gather(gt_plan *pl, hipStream_t s) {
       }
     }
     begin[nt] = (int32_t)items.size();
-    const double fill = items.empty() ? 0.0 : (double)((int64_t)nt * pl->Mtot) / (64.0 * (double)items.size());
-    if (fill < kCellGatherFill || items.size() >= (size_t(1) << 31)) continue;
     o.citems.swap(items);
     o.citem_begin.swap(begin);
     if (int rc = upload_raw(o.citems, &o.d_citems)) return rc;
@@ -749,8 +756,11 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     hipError_t e2 = hipStreamSynchronize(s);
     if (e2 != hipSuccess) rc = hip_fail(e2, "node binning");
   }
-  if (rc == GT_OK && p->ds >= 2) rc = setup_tile_spread(pl, s);
-  if (rc == GT_OK && p->ds >= 1) rc = setup_cell_gather(pl, s);
+  std::vector<int64_t> cstarts[kMaxOrder + 1];
+  for (int t = 1; rc == GT_OK && t <= p->ds; ++t)
+    if (pl->ord[t].term_end > pl->ord[t].term_begin) rc = fetch_cell_starts(pl, t, s, cstarts[t]);
+  if (rc == GT_OK && p->ds >= 2 && pl->ord[2].term_end > pl->ord[2].term_begin) rc = setup_tile_spread(pl, cstarts[2]);
+  if (rc == GT_OK && p->ds >= 1) rc = setup_cell_gather(pl, cstarts, s);
   if (rc) {
     free_plan(pl);
     return rc;
