@@ -18,9 +18,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -462,6 +464,32 @@ static int setup_cell_gather(gt_plan *pl, const std::vector<int64_t> (&cstarts)[
   return GT_OK;
 }
 
+// Deconvolution factors, roots of unity and window polynomials of an order depend only on
+// (N, n, m, polynomial degree) (the shape b follows from N and n); their long-double
+// evaluation costs about a millisecond, so plans share them through this process-wide
+// cache (bounded; cleared when full).
+struct OrderTables {
+  std::vector<double> deconv, roots, poly;
+};
+static std::mutex g_tab_mu;
+static std::map<std::array<int, 4>, OrderTables> g_tab;
+
+static bool cached_tables(int N, int n, int m, int D, OrderHost &o) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto it = g_tab.find({N, n, m, D});
+  if (it == g_tab.end()) return false;
+  o.deconv = it->second.deconv;
+  o.roots = it->second.roots;
+  o.poly = it->second.poly;
+  return true;
+}
+
+static void cache_tables(int N, int n, int m, int D, const OrderHost &o) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  if (g_tab.size() >= 64) g_tab.clear();
+  g_tab[{N, n, m, D}] = OrderTables{o.deconv, o.roots, o.poly};
+}
+
 int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out) {
   *out = nullptr;
   int rc = validate_problem(p);
@@ -579,20 +607,23 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
       return fail(GT_EUNSUPPORTED, "grid of order " + std::to_string(t) + " needs " + std::to_string(need) +
                                        " bytes of LDS (limit " + std::to_string(pl->lds_limit) + ")");
     }
-    o.deconv.resize(K);
-    for (int a = 0; a < K; ++a) {
-      int k = a - o.N / 2 + (a >= o.N / 2 ? 1 : 0);
-      long double ph = kb_phihat(k, o.m, (long double)o.b, o.n);
-      o.deconv[a] = (double)(((k & 1) ? -1.0L : 1.0L) / ph);
+    const int D = p->dtype == GT_C64 ? Deg<float>::value : Deg<double>::value;
+    if (!cached_tables(o.N, o.n, o.m, D, o)) {
+      o.deconv.resize(K);
+      for (int a = 0; a < K; ++a) {
+        int k = a - o.N / 2 + (a >= o.N / 2 ? 1 : 0);
+        long double ph = kb_phihat(k, o.m, (long double)o.b, o.n);
+        o.deconv[a] = (double)(((k & 1) ? -1.0L : 1.0L) / ph);
+      }
+      o.roots.resize(2 * o.n);
+      for (int j = 0; j < o.n; ++j) {
+        long double a = 2.0L * M_PIl * j / o.n;
+        o.roots[2 * j] = (double)std::cos(a);
+        o.roots[2 * j + 1] = (double)std::sin(a);
+      }
+      window_poly(o.m, (long double)o.b, D, o.poly);
+      cache_tables(o.N, o.n, o.m, D, o);
     }
-    o.roots.resize(2 * o.n);
-    for (int j = 0; j < o.n; ++j) {
-      long double a = 2.0L * M_PIl * j / o.n;
-      o.roots[2 * j] = (double)std::cos(a);
-      o.roots[2 * j + 1] = (double)std::sin(a);
-    }
-    int D = p->dtype == GT_C64 ? Deg<float>::value : Deg<double>::value;
-    window_poly(o.m, (long double)o.b, D, o.poly);
     int r1 = p->dtype == GT_C64 ? upload<float>(o.deconv, &o.d_deconv) : upload<double>(o.deconv, &o.d_deconv);
     int r2 = p->dtype == GT_C64 ? upload<float>(o.roots, &o.d_roots) : upload<double>(o.roots, &o.d_roots);
     int r3 = p->dtype == GT_C64 ? upload<float>(o.poly, &o.d_poly) : upload<double>(o.poly, &o.d_poly);
