@@ -150,3 +150,34 @@ def test_testfun_error_and_active_set_fp64():
             want.update(itertools.combinations(g, t))
     say(f"  U*: {len(got)} terms; printed U*: {len(want)}")
     assert got == want and na == 22
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mask_keeping_only_the_empty_set(prec):
+    """Degenerate index set: a mask dropping every term leaves the empty set alone, on
+    ragged datasets (one of them empty): the forward gives each dataset its constant, the
+    adjoint each dataset's sum of samples, the indices are all zero."""
+    import torch
+    d, ds, N = 4, 2, (8, 6)
+    sizes = [300, 0, 512]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    mask = np.zeros(oidx.anova_terms(d, ds).__len__(), dtype=np.uint8)
+    iset = oidx.grouped_index_set(d, ds, N, keep=mask)
+    assert iset.terms == [()]
+    R, Mt = len(sizes), int(offs[-1])
+    x = W.uniform_nodes(W.rng(64, W.P_NODES), Mt, d, prec)
+    fh = W.complex_normal(W.rng(64, W.P_COEFFS), (R, 1), prec)
+    y = W.complex_normal(W.rng(64, W.P_SAMPLES), (Mt,), prec)
+    p, keep = lib.make_problem(d, ds, N, M=0, R=R, dtype=dtype_code(prec), offsets=offs, term_mask=mask)
+    assert lib.problem_size(p) == (1, 1)
+    f = torch.empty(Mt, dtype=cdtype(prec), device="cuda")
+    a = torch.empty(R, dtype=cdtype(prec), device="cuda")
+    lib.grouped_trafo(p, to_dev(x), to_dev(fh.reshape(-1)), f)
+    lib.grouped_adjoint(p, to_dev(x), to_dev(y), a)
+    rho = _rho_gpu(p, a, R, 1)
+    torch.cuda.synchronize()
+    want_f = np.concatenate([np.full(sizes[b], fh[b, 0]) for b in range(R)])
+    want_a = np.array([y[offs[b]:offs[b + 1]].astype(np.complex128).sum() for b in range(R)])
+    e1, e2 = rel(f.cpu().numpy(), want_f), rel(a.cpu().numpy(), want_a)
+    say(f"[empty set only] {prec} forward {e1:.3e} adjoint {e2:.3e}")
+    assert e1 <= TOL[prec] and e2 <= TOL[prec] and np.all(rho == 0.0)
