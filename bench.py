@@ -285,7 +285,7 @@ def run_active_set():
     return out
 
 
-def run_testfun():
+def run_testfun(draw: int = 0):
     """The paper's LSQR experiments on its test function (Sec. 4, eq. testfun; Sec. 4.1 (i) to
     (iv)): d = 9, d_s = 3, M = 10,000 uniform nodes; (i) N = 26/6/4 (3,394 coefficients),
     exact samples, no weights; (ii) (i) with 10 % noise (standard deviation 0.1 x RMS of the
@@ -301,7 +301,7 @@ def run_testfun():
     d, ds, M = 9, 3, 10000
     lams = np.exp(np.arange(11.0))
     R = len(lams)
-    x = W.uniform_nodes(W.rng(7, W.P_NODES), M, d, "f32")
+    x = W.uniform_nodes(W.rng(7, W.P_NODES, draw), M, d, "f32")
     y0 = W.testfun(x)
     xd = torch.from_numpy(x).cuda()
     n2 = W.testfun_norm2()
@@ -311,7 +311,7 @@ def run_testfun():
             want.update(itertools.combinations(g, t))
 
     def experiment(N, noise, s_w, iters, printed):
-        y = (W.add_noise(W.rng(7, W.P_NOISE), y0, noise) if noise else y0).astype(np.complex64)
+        y = (W.add_noise(W.rng(7, W.P_NOISE, draw), y0, noise) if noise else y0).astype(np.complex64)
         yd = torch.from_numpy(y).cuda()
 
         def band(n):
@@ -375,7 +375,7 @@ def run_testfun():
             "iv": experiment((352, 20, 8), 0.1, 1.5, 100, "about 0.189 after the refit on U*")}
 
 
-def run_testfun_fista():
+def run_testfun_fista(draw: int = 0):
     """The paper's FISTA experiments on its test function (Sec. 4.2 (i) to (iv), Algorithm
     algo:fista): the settings of run_testfun, group lasso over lambda = e^10, e^9, .., e^0,
     the first from zero and each next one started from the previous solution (the paper's
@@ -387,7 +387,7 @@ def run_testfun_fista():
     from paper_2010_10199_amd import lib
     d, ds, M, KF = 9, 3, 10000, 200
     lams = np.exp(np.arange(10.0, -1.0, -1.0))
-    x = W.uniform_nodes(W.rng(7, W.P_NODES), M, d, "f32")
+    x = W.uniform_nodes(W.rng(7, W.P_NODES, draw), M, d, "f32")
     y0 = W.testfun(x)
     xd = torch.from_numpy(x).cuda()
     n2 = W.testfun_norm2()
@@ -397,7 +397,7 @@ def run_testfun_fista():
             want.update(itertools.combinations(g, t))
 
     def experiment(N, noise, s_w, printed):
-        y = (W.add_noise(W.rng(7, W.P_NOISE), y0, noise) if noise else y0).astype(np.complex64)
+        y = (W.add_noise(W.rng(7, W.P_NOISE, draw), y0, noise) if noise else y0).astype(np.complex64)
         yd = torch.from_numpy(y).cuda()
 
         def band(n):
@@ -562,6 +562,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20000, help="nodes for the oracle baseline (0 = skip)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-solvers", action="store_true", help="skip the FP32-batched vs FP64 solver timing")
+    ap.add_argument("--draws", type=int, default=1,
+                    help="node draws of the test-function experiments (the paper averages 100); means are reported")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -642,8 +644,18 @@ def main():
         print("[bench] active set", file=sys.stderr, flush=True)
         out["active_set"] = run_active_set()
         print("[bench] test function", file=sys.stderr, flush=True)
-        out["testfun"] = run_testfun()
-        out["testfun_fista"] = run_testfun_fista()
+        runs = [run_testfun(k) for k in range(max(1, args.draws))]
+        fruns = [run_testfun_fista(k) for k in range(max(1, args.draws))]
+        out["testfun"], out["testfun_fista"] = runs[0], fruns[0]
+        if args.draws > 1:
+            exps = ("i", "ii", "iii", "iv")
+            out["testfun"]["mean_over_draws"] = {
+                e: {"draws": len(runs), "best_l2_error": float(np.mean([min(r[e]["l2_error"].values()) for r in runs])),
+                    "l2_error_refit": float(np.mean([r[e]["l2_error_refit"] for r in runs])),
+                    "active_set_is_printed_U*": sum(r[e]["active_set_is_printed_U*"] for r in runs)} for e in exps}
+            out["testfun_fista"]["mean_over_draws"] = {
+                e: {"draws": len(fruns), "best_l2_error": float(np.mean([r[e]["best_l2_error"] for r in fruns])),
+                    "active_set_is_printed_U*": sum(r[e]["active_set_is_printed_U*"] for r in fruns)} for e in exps}
         print("[bench] autograd", file=sys.stderr, flush=True)
         out["autograd"] = run_autograd()
     if args.cpu_sample > 0:
