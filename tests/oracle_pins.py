@@ -574,6 +574,24 @@ def pin_l2_error_quadrature(seed=44, N=8, K=20000) -> float:
     return abs(e - want) / want
 
 
+def pin_testfun_gsi_closed_form() -> float:
+    """Sensitivity indices of the test function's exact coefficients (on a wide index set,
+    N = 512/64/24) against the variances of its ANOVA terms in closed form (printed terms
+    eq. onedimterm, eq. twodimterm, eq. threedimterm): with P = c2 c4 c6 and c_k the
+    constant of the B-spline on coordinate k, term u inside a product has variance
+    (P / prod_{k in u} c_k)^2 prod_{k in u} (1 - c_k^2), and the function 3 (1 - P^2)."""
+    import workloads as W
+    iset = oidx.grouped_index_set(9, 3, (512, 64, 24))
+    rho = osens.sensitivity_indices(iset, W.testfun_coeffs(iset.terms, iset.freqs))
+    P = W.BSPLINE_NORM[2] * W.BSPLINE_NORM[4] * W.BSPLINE_NORM[6]
+    ck = {k: W.BSPLINE_NORM[j] for g in W.TESTFUN_GROUPS for k, j in zip(g, W.TESTFUN_ORDERS)}
+    want = np.zeros(iset.n_terms)
+    for i, u in enumerate(iset.terms):
+        if u and any(set(u) <= set(g) for g in W.TESTFUN_GROUPS):
+            want[i] = (P / np.prod([ck[k] for k in u])) ** 2 * np.prod([1.0 - ck[k] ** 2 for k in u])
+    return float(np.max(np.abs(rho - want / (3.0 * (1.0 - P * P)))))
+
+
 PINS = [
     ("printed_counts", pin_printed_counts, {}, 0.0),
     ("ordering", pin_ordering, {}, 0.0),
@@ -616,4 +634,5 @@ PINS = [
     ("bspline_unit_norm", pin_bspline_unit_norm, {}, 1e-12),
     ("testfun_anova", pin_testfun_anova, {}, 1e-15),
     ("l2_error_quadrature", pin_l2_error_quadrature, {}, 1e-10),
+    ("testfun_gsi_closed_form", pin_testfun_gsi_closed_form, {}, 1e-5),
 ]
