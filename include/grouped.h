@@ -109,8 +109,10 @@ int64_t gt_num_coeffs(int32_t d, int32_t ds, const int32_t *N);
  * With a term mask, only the kept terms (|U| = gt_problem_size's nterms). */
 int gt_term_table(const gt_problem *p, int32_t *coords, int64_t *offsets);
 
-/* Terms |U| and coefficients |I_N(U)| of the problem's index set (its term mask applied).
- * Either output may be NULL. */
+/* Terms |U| and coefficients |I_N(U)| = 1 + sum over u != empty set of (N_{|u|} - 1)^{|u|}
+ * (Remark rem:cardinality, eq. groupedset) of the problem's index set, its term mask
+ * applied.  nterms, ncoeffs: host, either may be NULL.  Returns GT_EINVAL for invalid d, ds
+ * or bandwidths. */
 int gt_problem_size(const gt_problem *p, int64_t *nterms, int64_t *ncoeffs);
 
 /* ------------------------------------------------------------------ one-shot transforms
