@@ -63,10 +63,11 @@ typedef struct gt_problem {
   int32_t d;                   /* spatial dimension, >= 1 */
   int32_t ds;                  /* superposition threshold, 0 <= ds <= min(d, 3) */
   int32_t N[GT_MAX_ORDER];     /* N[k-1]: even bandwidth >= 2 of every term with |u| = k; unused entries ignored */
-  int64_t M;                   /* nodes (shared by all R right-hand sides); ignored when offsets != NULL */
+  int64_t M;                   /* nodes (shared by all R right-hand sides), >= 1; ignored when offsets != NULL */
   int32_t R;                   /* batch: right-hand sides (lambda values) or ragged datasets, >= 1 */
   const int64_t *offsets;      /* host, NULL or R+1 non-decreasing prefix offsets starting at 0: dataset b owns
-                                  nodes offsets[b]..offsets[b+1]-1 of the node array and has its own coefficients */
+                                  nodes offsets[b]..offsets[b+1]-1 of the node array and has its own coefficients;
+                                  a dataset may be empty, the total may not */
   int32_t dtype;               /* GT_C64 or GT_C128 */
   int32_t m;                   /* window half-width (Kaiser-Bessel support 2m grid points), 0 = chosen per order
                                   from the precision; otherwise 2..8 */

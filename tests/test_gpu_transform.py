@@ -210,6 +210,12 @@ def test_invalid_arguments_are_rejected():
         with pytest.raises(lib.GroupedError) as e:
             lib.grouped_trafo(p, x, fh, f)
         assert e.value.code in (lib.GT_EINVAL, lib.GT_EUNSUPPORTED)
+    # no nodes at all: shared (M = 0) or ragged with every dataset empty
+    for kw in [dict(M=0), dict(M=0, R=2, offsets=[0, 0, 0])]:
+        p, keep = lib.make_problem(3, 2, [4, 4], dtype=lib.GT_C128, **kw)
+        with pytest.raises(lib.GroupedError) as e:
+            lib.grouped_trafo(p, x, fh, f)
+        assert e.value.code == lib.GT_EINVAL and keep is not None
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
