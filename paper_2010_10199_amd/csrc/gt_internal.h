@@ -170,7 +170,6 @@ struct gt_plan {
   int32_t nslots = 0;                 // gather output slots (terms per forward block)
   void *d_fpart = nullptr;            // nslots x Vtot
   double *d_ysum = nullptr;           // per gather item: partial sums (re, im) for the empty set
-  int32_t *d_ycount = nullptr;        // per right-hand side: finished items of the empty-set sum
   int32_t *d_flag = nullptr;          // node validation flag
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
   hipStream_t stream = nullptr;

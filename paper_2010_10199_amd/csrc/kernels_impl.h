@@ -150,11 +150,6 @@ __global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T 
 
 static __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
-static __global__ void k_zero_n(int32_t *p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 // ------------------------------------------------------------------ K1 + K2 forward
 
 // One workgroup per (term, right-hand side).  Pruned separable inverse DFT from the
@@ -432,17 +427,15 @@ __global__ __launch_bounds__(256) void k_reduce_f(const cx_t<T> *__restrict__ fh
 #include "spread.h"   // K4 spread (binned, MFMA)
 namespace gt {
 
-// Empty-set coefficient fhat_empty(r) = sum_v y_v.  Each workgroup sums one gather item
-// (FP64) into ysum; the last workgroup of right-hand side r to finish (counter per r)
-// adds that side's partials in item order, writes the coefficient and resets the counter.
+// Empty-set coefficient fhat_empty(r) = sum_v y_v, in two launches: k_empty_part sums one
+// gather item per workgroup (FP64) into ysum; k_empty_adj, one workgroup per right-hand side,
+// adds that side's partials in item order and writes the coefficient.  (One launch whose last
+// workgroup adds the partials needs a device-scope fence per workgroup, an L2 write-back that
+// slowed the adjoint kernels running beside it.)
 template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const WorkItem *__restrict__ items,
-                                                         const int32_t *__restrict__ item_begin,
-                                                         const cx_t<T> *__restrict__ y, double *__restrict__ ysum,
-                                                         int32_t *__restrict__ counters, int64_t ncoef,
-                                                         cx_t<T> *__restrict__ fhat) {
+__global__ __launch_bounds__(kGatherBS) void k_empty_part(const WorkItem *__restrict__ items,
+                                                          const cx_t<T> *__restrict__ y, double *__restrict__ ysum) {
   __shared__ double sh[2 * (kGatherBS / 64)];
-  __shared__ int last;
   const WorkItem it = items[blockIdx.x];
   double a = 0, b = 0;
   if ((int)threadIdx.x < it.count) {
@@ -454,24 +447,22 @@ __global__ __launch_bounds__(kGatherBS) void k_empty_adj(const WorkItem *__restr
   if (threadIdx.x == 0) {
     ysum[2 * blockIdx.x] = a;
     ysum[2 * blockIdx.x + 1] = b;
-    __threadfence();
-    const int nitems = item_begin[it.r + 1] - item_begin[it.r];
-    last = atomicAdd(&counters[it.r], 1) == nitems - 1;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  a = 0;
-  b = 0;
-  for (int i = item_begin[it.r] + threadIdx.x; i < item_begin[it.r + 1]; i += kGatherBS) {
-    a += __hip_atomic_load(&ysum[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b += __hip_atomic_load(&ysum[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restrict__ item_begin,
+                                                         const double *__restrict__ ysum, int64_t ncoef,
+                                                         cx_t<T> *__restrict__ fhat) {
+  __shared__ double sh[2 * (kGatherBS / 64)];
+  const int r = blockIdx.x;
+  double a = 0, b = 0;
+  for (int i = item_begin[r] + threadIdx.x; i < item_begin[r + 1]; i += kGatherBS) {
+    a += ysum[2 * i];
+    b += ysum[2 * i + 1];
   }
   block_sum2(a, b, sh);
-  if (threadIdx.x == 0) {
-    fhat[(int64_t)it.r * ncoef] = cmake<T>((T)a, (T)b);
-    counters[it.r] = 0;
-  }
+  if (threadIdx.x == 0) fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
 }
 
 // ------------------------------------------------------------------ fold of the spread partials
@@ -1269,8 +1260,10 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
   if (ngi > 0) {
     const hipStream_t st = fk ? pl->side : s;
     prof_begin(st, "empty_adj");
-    hipLaunchKernelGGL((k_empty_adj<T>), dim3(ngi), dim3(kGatherBS), 0, st, pl->d_gitems, pl->d_gitem_begin,
-                       (const C *)y, pl->d_ysum, pl->d_ycount, pl->ncoef, (C *)fhat);
+    hipLaunchKernelGGL((k_empty_part<T>), dim3(ngi), dim3(kGatherBS), 0, st, pl->d_gitems, (const C *)y,
+                       pl->d_ysum);
+    hipLaunchKernelGGL((k_empty_adj<T>), dim3(pl->R), dim3(kGatherBS), 0, st, pl->d_gitem_begin,
+                       (const double *)pl->d_ysum, pl->ncoef, (C *)fhat);
     prof_end(st);
     if (int rc = check_launch("k_empty_adj")) return rc;
   }
@@ -1350,7 +1343,6 @@ template <typename T>
 int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s) {
   const int64_t total = pl->Mtot * pl->d;
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pl->d_flag);
-  hipLaunchKernelGGL((k_zero_n), dim3((pl->R + 255) / 256), dim3(256), 0, s, pl->d_ycount, pl->R);
   if (total > 0)
     hipLaunchKernelGGL((k_prepare_nodes<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)x,
                        pl->Mtot, pl->d, (T *)pl->d_x, pl->d_flag);

@@ -288,7 +288,6 @@ void free_plan(gt_plan *pl) {
   dev_free(pl->d_fpart, nullptr);
   dev_free(pl->d_ysum, nullptr);
   dev_free(pl->d_flag, nullptr);
-  dev_free(pl->d_ycount, nullptr);
   dev_free(pl->d_gxp, nullptr);
   for (auto &o : pl->ord) {
     dev_free(o.d_deconv, nullptr);
@@ -747,8 +746,7 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
       (rc = upload_raw(pl->gitems, &pl->d_gitems)) || (rc = upload_raw(pl->gitem_begin, &pl->d_gitem_begin)) ||
       (rc = dev_alloc(&pl->d_fpart, (size_t)std::max(1, pl->nslots) * pl->Vtot * csz, s)) ||
       (rc = dev_alloc((void **)&pl->d_ysum, (size_t)ngi * 2 * sizeof(double), s)) ||
-      (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s)) ||
-      (rc = dev_alloc((void **)&pl->d_ycount, (size_t)pl->R * sizeof(int32_t), s))) {
+      (rc = dev_alloc((void **)&pl->d_flag, sizeof(int32_t), s))) {
     free_plan(pl);
     return rc;
   }
