@@ -89,6 +89,32 @@ def pin_dense_matrix(seed=1, d=4, ds=3, N=(6, 4, 4), M=37) -> float:
     return max(rel(otr.forward(iset, x, fh), A @ fh), rel(otr.adjoint(iset, x, y), A.conj().T @ y))
 
 
+def pin_adjoint_at(seed=5, d=5, ds=3, N=(6, 4, 4), M=43, picks=60) -> float:
+    """Selected adjoint entries equal rows of the conjugate transpose of the d-dimensional
+    matrix of eq. FM (k in Z^d), built independently from the ordering rule: (A^H y)[idx]
+    for a sample of coefficients that includes the empty set and terms of orders 1, 2, 3,
+    taken out of order and with a repeated index."""
+    g = np.random.default_rng(seed)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = g.random((M, d)) - 0.5
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    K = []
+    for t in range(ds + 1):
+        for u in itertools.combinations(range(d), t):
+            band = [k for k in range(-N[t - 1] // 2, N[t - 1] // 2) if k != 0] if t else []
+            for ell in itertools.product(band, repeat=t):
+                k = np.zeros(d)
+                k[list(u)] = ell
+                K.append(k)
+    K = np.array(K)
+    order = (K != 0).sum(axis=1)
+    idx = [0] + [int(g.choice(np.flatnonzero(order == t))) for t in range(1, ds + 1)]
+    idx += list(g.choice(len(K), picks, replace=False)) + [idx[2]]
+    idx = np.array(idx)[g.permutation(len(idx))]
+    A = np.cos(2 * np.pi * x @ K.T) + 1j * np.sin(2 * np.pi * x @ K.T)
+    return rel(otr.adjoint_at(iset, x, y, idx), (A.conj().T @ y)[idx])
+
+
 def pin_hypercube_fft(d=3, N=6) -> float:
     """U = P(D), N_u = N, nodes on the grid l/N: the grouped transform is a d-dim inverse FFT.
 
@@ -596,6 +622,7 @@ PINS = [
     ("printed_counts", pin_printed_counts, {}, 0.0),
     ("ordering", pin_ordering, {}, 0.0),
     ("dense_matrix", pin_dense_matrix, {}, 1e-12),
+    ("adjoint_at", pin_adjoint_at, {}, 1e-12),
     ("hypercube_fft_1d", pin_hypercube_fft, dict(d=1, N=8), 1e-12),
     ("hypercube_fft_2d", pin_hypercube_fft, dict(d=2, N=6), 1e-12),
     ("hypercube_fft_3d", pin_hypercube_fft, dict(d=3, N=4), 1e-12),

@@ -13,7 +13,8 @@ import workloads as W
 from oracle import index_set as oidx
 from oracle import transform as otr
 from paper_2010_10199_amd import lib
-from tests.gpu_util import TOL, dtype_code, gpu_adjoint, gpu_trafo, nfft_model_error, rel, say, to_dev
+from tests.gpu_util import (TOL, check, dtype_code, gpu_adjoint, gpu_trafo, max_err, max_tol, nfft_model_error, rel,
+                            say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -77,15 +78,17 @@ def test_forward_and_adjoint_parity(case, prec):
     tol = _tol(prec, m, sigma, ds)
     # forward
     f = gpu_trafo(d, ds, N, x, fhat, prec, R=R, offsets=offsets, m=m, sigma=sigma)
+    mtol = max_tol(prec, ds, m, sigma)
     if offsets is None:
         ref = otr.forward(iset, x, fhat)
-        err = rel(f, ref)
+        check("forward", f, ref, fhat, tol, mtol)
     else:
         ref = np.concatenate([otr.forward(iset, x[offsets[b]:offsets[b + 1]], fhat[b]) if offsets[b + 1] > offsets[b]
                               else np.zeros(0, complex) for b in range(R)])
         err = rel(f, ref)
-    say(f"  forward rel err {err:.3e} (tol {tol:.1e})")
-    assert err <= tol
+        em = max(max_err(f[offsets[b]:offsets[b + 1]], ref[offsets[b]:offsets[b + 1]], fhat[b]) for b in range(R))
+        say(f"  forward rel l2 {err:.3e} (tol {tol:.1e}), max/l1 {em:.3e} (tol {mtol:.1e})")
+        assert err <= tol and em <= mtol
     # adjoint
     yy = y.reshape(R, Mx) if offsets is None else y
     a = gpu_adjoint(d, ds, N, x, yy, prec, iset.n_coeffs, R=R, offsets=offsets, m=m, sigma=sigma)
@@ -94,9 +97,16 @@ def test_forward_and_adjoint_parity(case, prec):
     else:
         refa = np.stack([otr.adjoint(iset, x[offsets[b]:offsets[b + 1]], y[offsets[b]:offsets[b + 1]])
                          for b in range(R)])
-    erra = rel(a, refa)
-    say(f"  adjoint rel err {erra:.3e} (tol {tol:.1e})")
-    assert erra <= tol
+    if offsets is None:
+        check("adjoint", a, refa, yy, tol, mtol)
+    else:
+        erra = rel(a, refa)
+        em = max(max_err(a[b], refa[b], y[offsets[b]:offsets[b + 1]]) for b in range(R) if offsets[b + 1] > offsets[b])
+        say(f"  adjoint rel l2 {erra:.3e} (tol {tol:.1e}), max/l1 {em:.3e} (tol {mtol:.1e})")
+        assert erra <= tol and em <= mtol
+        for b in range(R):          # an empty dataset's coefficients are exactly zero
+            if offsets[b + 1] == offsets[b]:
+                assert not np.any(a[b])
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -129,11 +139,9 @@ def test_config1_fp64_full():
     x, fhat, y = W.trafo_inputs(1, d, ds, M, iset.n_coeffs, 1, "f64")
     say("[config1] full fp64")
     f = gpu_trafo(d, ds, N, x, fhat, "f64")
-    e1 = rel(f, otr.forward(iset, x, fhat))
+    check("forward", f, otr.forward(iset, x, fhat), fhat, TOL["f64"], max_tol("f64", ds))
     a = gpu_adjoint(d, ds, N, x, y.reshape(1, M), "f64", iset.n_coeffs)
-    e2 = rel(a, otr.adjoint(iset, x, y.reshape(1, M)))
-    say(f"  forward {e1:.3e} adjoint {e2:.3e}")
-    assert e1 <= TOL["f64"] and e2 <= TOL["f64"]
+    check("adjoint", a, otr.adjoint(iset, x, y.reshape(1, M)), y.reshape(1, M), TOL["f64"], max_tol("f64", ds))
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -150,13 +158,12 @@ def test_config2_full_size_sampled(prec):
     f = gpu_trafo(d, ds, N, x, fhat, prec, m=6, sigma=2.0)[0]
     g = np.random.default_rng(0)
     S = np.sort(g.choice(M, 3000, replace=False))
-    e1 = rel(f[S], otr.forward(iset, x[S], fhat[0]))
+    tol = TOL[prec] if prec == "f32" else 20 * ds * nfft_model_error(6, 2.0)
+    mtol = max_tol(prec, ds, 6, 2.0)
+    check("forward (3,000 nodes)", f[S], otr.forward(iset, x[S], fhat[0]), fhat, tol, mtol)
     a = gpu_adjoint(d, ds, N, x, y.reshape(1, M), prec, iset.n_coeffs, m=6, sigma=2.0)[0]
     K = np.sort(g.choice(iset.n_coeffs, 400, replace=False))
-    e2 = rel(a[K], otr.adjoint_at(iset, x, y.reshape(-1), K))
-    tol = TOL[prec] if prec == "f32" else 20 * ds * nfft_model_error(6, 2.0)
-    say(f"  forward {e1:.3e} adjoint {e2:.3e} tol {tol:.1e}")
-    assert e1 <= tol and e2 <= tol
+    check("adjoint (400 coefficients)", a[K], otr.adjoint_at(iset, x, y.reshape(-1), K), y, tol, mtol)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])

@@ -22,6 +22,14 @@ MUTATIONS = [
      "E = _phase_matrix(x[a:b][:, list(u)[::-1]], ell)", "coordinates of a term swapped"),
     ("oracle.transform", "otr", "2j * np.pi * ell[:, pos] * c", "2j * np.pi * ell[:, pos - 1] * c",
      "gradient uses the wrong frequency component"),
+    ("oracle.transform", "otr", "out += y[a:b] @ np.exp(-2j * np.pi * theta)",
+     "out += y[a:b] @ np.exp(2j * np.pi * theta)", "selected adjoint entries without conjugate"),
+    ("oracle.transform", "otr", "K = iset.full_frequencies()[np.asarray(idx)].astype(np.float64)",
+     "K = iset.full_frequencies()[np.sort(np.asarray(idx))].astype(np.float64)",
+     "selected adjoint entries returned in sorted instead of requested order"),
+    ("oracle.transform", "otr", "for a in range(0, x.shape[0], _CHUNK):\n        b = min(x.shape[0], a + _CHUNK)\n        theta",
+     "for a in range(0, x.shape[0] - 1, _CHUNK):\n        b = min(x.shape[0] - 1, a + _CHUNK)\n        theta",
+     "selected adjoint entries drop the last node"),
     ("oracle.index_set", "oidx", "[k for k in range(-N // 2, N // 2) if k != 0]",
      "[k for k in range(-N // 2 + 1, N // 2 + 1) if k != 0]", "band shifted by one"),
     ("oracle.index_set", "oidx", "out.extend(itertools.combinations(range(d), t))",
