@@ -329,7 +329,7 @@ def run_testfun(draw: int = 0):
 
         def weights(ts):   # eq. sobolevweights, one per coefficient in coefficient order
             return np.concatenate([np.prod((1.0 + np.abs(f)) ** s_w, axis=1) if u else np.ones(1)
-                                   for u, f in zip(ts, freqs(ts))]).astype(np.float32)
+                                   for u, f in zip(ts, freqs(ts))])
 
         def l2(fh, ex):    # eq. L2error by Parseval
             return float(np.sqrt(max(n2 + np.sum(np.abs(fh - ex) ** 2) - np.sum(np.abs(ex) ** 2), 0.0) / n2))
@@ -383,15 +383,16 @@ def run_testfun(draw: int = 0):
 
 def run_testfun_fista(draw: int = 0):
     """The paper's FISTA experiments on its test function (Sec. 4.2 (i) to (iv), Algorithm
-    algo:fista): the settings of run_testfun, group lasso over lambda = e^10, e^9, .., e^0,
-    the first from zero and each next one started from the previous solution (the paper's
-    warm-started path), KF constant steps each with L = 1.05 x a 50-step power-iteration
-    estimate; the relative L2 error on U_3 (no refit) per lambda and the active set of the
-    best solution (indices > 0.001).  FP32, one node draw."""
+    algo:fista as printed): the settings of run_testfun, group lasso over lambda = e^10, e^9,
+    .., e^0 in one library call (fista_group_lasso_path: one plan, the first lambda from zero
+    and each next one started from the previous solution), KF iterations per lambda with
+    backtracking from L_0 = M (every column of F has squared norm M, so ||F||^2 >= M) and
+    eta = 2; the relative L2 error on U_3 (no refit) per lambda and the active set of the best
+    solution (indices > 0.001).  FP32, one node draw."""
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
-    d, ds, M, KF = 9, 3, 10000, 200
+    d, ds, M, KF, ETA = 9, 3, 10000, 200, 2.0
     lams = np.exp(np.arange(10.0, -1.0, -1.0))
     x = W.uniform_nodes(W.rng(7, W.P_NODES, draw), M, d, "f32")
     y0 = W.testfun(x)
@@ -418,40 +419,39 @@ def run_testfun_fista(draw: int = 0):
         om = None
         if s_w:
             w = np.concatenate([np.prod((1.0 + np.abs(f)) ** s_w, axis=1) if u else np.ones(1)
-                                for u, f in zip(terms, fr)]).astype(np.float32)
+                                for u, f in zip(terms, fr)])
             om = torch.from_numpy(w).cuda()
         p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64)
-        plan = lib.Plan(p, xd, keepalive=keep)
-        L = 1.05 * plan.norm_estimate(50)
-        plan.close()
-        fh = torch.zeros(nc, dtype=torch.complex64, device="cuda")
-        errs, sols = [], []
+        path = torch.zeros(len(lams) * nc, dtype=torch.complex64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for lam in lams:
-            lib.fista_group_lasso(p, xd, yd, [float(lam)], om, KF, L, 1.0, 0.0, fh)
-            sols.append(fh.clone())
+        infos = lib.fista_group_lasso_path(p, xd, yd, lams, om, KF, float(M), ETA, 0.0, None, path)
         torch.cuda.synchronize()
         t_path = time.perf_counter() - t0
-        for f in sols:
-            fv = f.cpu().numpy().astype(np.complex128)
+        sols = path.reshape(len(lams), nc)
+        errs = []
+        for j in range(len(lams)):
+            fv = sols[j].cpu().numpy().astype(np.complex128)
             errs.append(float(np.sqrt(max(n2 + np.sum(np.abs(fv - exact) ** 2) - np.sum(np.abs(exact) ** 2), 0.0)
                                       / n2)))
         best = int(np.argmin(errs))
         rho = torch.empty(len(terms), dtype=torch.float64, device="cuda")
-        lib.sensitivity(p, sols[best], rho)
+        lib.sensitivity(p, sols[best].contiguous(), rho)
         mask, na = lib.active_set(p, rho.cpu().numpy(), (1e-3, 1e-3, 1e-3))
         act = {u for u, k in zip(terms, mask) if k and u}
         print(f"[bench]   fista test function N={N} noise={noise} s={s_w}: best {min(errs):.4f}",
               file=sys.stderr, flush=True)
-        return {"N": list(N), "coefficients": nc, "noise": noise, "s": s_w, "steps_per_lambda": KF, "L": L,
+        return {"N": list(N), "coefficients": nc, "noise": noise, "s": s_w, "iterations_per_lambda": KF,
+                "L0": float(M), "eta": ETA, "L_final": [inf[0].L for inf in infos],
+                "capped": any(inf[0].flags & lib.GT_SOLVE_BACKTRACK_CAP for inf in infos),
                 "l2_error": {f"e^{int(round(np.log(l)))}": e for l, e in zip(lams, errs)},
                 "best_lambda": f"e^{int(round(np.log(lams[best])))}", "best_l2_error": errs[best],
                 "active_terms": len(act), "active_set_is_printed_U*": act == want, "path_s": t_path,
                 "paper": printed}
 
-    return {"workload": f"test function, d={d}, d_s={ds}, M={M} uniform nodes, FP32, group lasso (FISTA) on the "
-                        "warm-started path lambda = e^10 .. e^0, one node draw (the paper averages 100)",
+    return {"workload": f"test function, d={d}, d_s={ds}, M={M} uniform nodes, FP32, group lasso (FISTA with "
+                        "backtracking) on the warm-started path lambda = e^10 .. e^0 in one call, one node draw "
+                        "(the paper averages 100)",
             "i": experiment((26, 6, 4), 0.0, 0.0, "about 9.2e-2 on U_3"),
             "ii": experiment((26, 6, 4), 0.1, 0.0, "about 0.202 on U_3"),
             "iii": experiment((352, 20, 8), 0.0, 1.5, "about 1.7e-2 on U_3"),

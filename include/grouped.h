@@ -134,7 +134,8 @@ int grouped_adjoint(const gt_problem *p, const void *x, const void *y, void *fha
  * Creation synchronises `stream` once (to validate the nodes).  A plan may be used from one
  * stream at a time; calls on the same plan must not overlap. */
 int gt_plan_create(const gt_problem *p, const void *x, void *stream, gt_plan **out);
-int gt_plan_destroy(gt_plan *plan);            /* synchronises the plan's last stream */
+int gt_plan_destroy(gt_plan *plan);            /* synchronises the plan's last stream; NULL is a no-op;
+                                                  a handle that is not a live plan gives GT_EINVAL */
 int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream);
 int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream);
 
@@ -164,30 +165,62 @@ int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path);
  * LSQR (Paige & Saunders) on A = F W^{-1/2} with damping sqrt(2 lambda); fhat = W^{-1/2} x.
  *   y      device, complex, R x M (or ragged)
  *   lambda host, R doubles >= 0
- *   omega  device, real (dtype's), |I| weights > 0 shared by all r, or NULL (omega = 1)
+ *   omega  device, double, |I| weights > 0 (W = diag(omega), Sec. 4.1) shared by all r, or
+ *          NULL (omega = 1); FP64 on both precision paths
  *   max_iter >= 1; tol > 0: stop when every r has resid <= tol * resid_0 (checked every
  *   8 iterations with one stream synchronisation), tol <= 0: run exactly max_iter.
  *   fhat   device, complex, R x |I| (output)
  *   info   host, R entries (output); the call synchronises `stream` before returning.
- * Bulk vectors are in the dtype's precision; alpha, beta, norms and rotations are FP64. */
+ * Bulk vectors are in the dtype's precision; alpha, beta, norms and rotations are FP64.
+ * A breakdown (alpha or beta exactly 0: the solution lies in the Krylov space) freezes that
+ * right-hand side and sets GT_SOLVE_BREAKDOWN; it is not an error. */
 int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *lambda,
-               const void *omega, int32_t max_iter, double tol, void *fhat,
+               const double *omega, int32_t max_iter, double tol, void *fhat,
                gt_solve_info *info, void *stream);
 
 /* fista_group_lasso: R group-lasso problems (eq. alligatoah), lambda[r] > 0, every ANOVA
  * term (the empty set included) one group, Algorithm algo:fista from fhat (in: start
  * f_0, out: f_K).
- *   L > 0: step constant; L <= 0: 1.05 x a 50-step power-iteration estimate of ||F||_2^2.
+ *   omega  device, double, |I| weights > 0 or NULL, as for lsqr_solve.
+ *   L > 0: step constant (backtracking: L_0); L <= 0: 1.05 x a 50-step power-iteration
+ *   estimate of ||F||_2^2.
  *   eta <= 1: constant step (the variant in the remark after the algorithm);
- *   eta > 1: backtracking with factor eta (one host synchronisation per trial step).
- *   tol > 0: stop when every r has relative step ||f_k - f_{k-1}|| / ||f_k|| <= tol (checked
- *   every 8 iterations); tol <= 0: exactly max_iter iterations.
+ *   eta > 1: backtracking with factor eta: a trial step is accepted when
+ *   ||F(f - h)||^2 <= L ||f - h||^2 (the algorithm's test in an equivalent form), else L
+ *   grows by eta and the step is retried; after 30 increases within one iteration the
+ *   trial is taken and GT_SOLVE_BACKTRACK_CAP is set for that right-hand side.  The
+ *   iteration state lives on the device; the host reads it once per batch of steps (not
+ *   per trial).
+ *   tol > 0: a right-hand side stops when its relative step ||f_k - f_{k-1}|| / ||f_k|| <=
+ *   tol; tol <= 0: exactly max_iter accepted iterations.
  * Group norms, the proximal scale (closed form for omega = NULL, otherwise bisection +
- * Newton for xi as in the remark after Theorem theorem:projection), t_k and the momentum
- * are FP64. */
+ * Newton for xi as in the remark after Theorem theorem:projection), t_k, the momentum and
+ * the test are FP64.  Synchronises `stream`. */
 int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda,
-                      const void *omega, int32_t max_iter, double L, double eta, double tol,
+                      const double *omega, int32_t max_iter, double L, double eta, double tol,
                       void *fhat, gt_solve_info *info, void *stream);
+
+/* fista_group_lasso_path: the warm-started path of the paper's experiments (Sec. 4.2):
+ * stage j = 0..nlambda-1 solves eq. alligatoah with lambda[j] for every right-hand side, as
+ * fista_group_lasso does, starting from the previous stage's solution (stage 0 from fhat0,
+ * device R x |I|, or zero when fhat0 is NULL); every stage restarts t_1 = 1 and L_0.  One
+ * plan (node sort) serves the whole path.
+ *   fhat_path device, complex, nlambda x R x |I| (output: every stage's solution)
+ *   info      host, nlambda x R entries (output)
+ * Other arguments as for fista_group_lasso.  Synchronises `stream`. */
+int fista_group_lasso_path(const gt_problem *p, const void *x, const void *y, int32_t nlambda,
+                           const double *lambda, const double *omega, int32_t max_iter, double L,
+                           double eta, double tol, const void *fhat0, void *fhat_path,
+                           gt_solve_info *info, void *stream);
+
+/* The solvers on an existing plan (the plan's R right-hand sides; nodes sorted once and reused
+ * by every call, so repeated solves on fixed nodes pay no plan creation).  Arguments and
+ * results as for lsqr_solve and fista_group_lasso.  Work buffers are allocated per call. */
+int gt_plan_lsqr(gt_plan *plan, const void *y, const double *lambda, const double *omega,
+                 int32_t max_iter, double tol, void *fhat, gt_solve_info *info, void *stream);
+int gt_plan_fista(gt_plan *plan, const void *y, const double *lambda, const double *omega,
+                  int32_t max_iter, double L, double eta, double tol, void *fhat,
+                  gt_solve_info *info, void *stream);
 
 /* ------------------------------------------------------------------ sensitivity analysis
  * gt_sensitivity: global sensitivity indices (eq. gsi) of the approximation with
@@ -210,6 +243,13 @@ int gt_active_set(const gt_problem *p, const double *rho, const double *eps, uin
  * synchronises `stream`.  Uses right-hand side 0 of the plan. */
 int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *stream);
 
+/* ------------------------------------------------------------------ lifetime
+ * gt_release_all: destroys every live plan (as gt_plan_destroy would) and clears the
+ * process-wide window-table cache.  Handles of released plans become invalid: later calls
+ * with them return GT_EINVAL (they are recognised, not dereferenced), as do calls with a
+ * destroyed plan.  Synchronises the released plans' streams. */
+int gt_release_all(void);
+
 /* ------------------------------------------------------------------ diagnostics
  * gt_last_error: thread-local message of the last failing call ("" if none).
  * gt_prof_enable(1): record HIP events around every kernel launch (same stream);
@@ -219,6 +259,12 @@ const char *gt_last_error(void);
 int gt_prof_enable(int32_t on);
 int64_t gt_prof_report(char *buf, int64_t len);
 const char *gt_version(void);
+
+/* Allocation-failure hook for testing the error paths: gt_debug_fail_alloc(k), k >= 1, makes
+ * the k-th device allocation from now on fail with GT_ENOMEM (k = 0 turns the hook off); it
+ * also resets the count that gt_debug_alloc_count returns (device allocations since). */
+int gt_debug_fail_alloc(int64_t k);
+int64_t gt_debug_alloc_count(void);
 
 #ifdef __cplusplus
 }

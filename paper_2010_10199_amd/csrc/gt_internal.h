@@ -211,15 +211,23 @@ template <typename T> int launch_binning(gt_plan *pl, hipStream_t s);   // binni
 // Sensitivity indices (eq. gsi) from term offsets goff (device, nterms + 1): rho[r][u].
 template <typename T> int run_sensitivity(const int64_t *goff, int nterms, int64_t ncoef, int R, const void *fhat,
                                           double *rho, hipStream_t s);
-template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega,
+template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *omega,
                                    int max_iter, double tol, void *fhat, gt_solve_info *info, hipStream_t s);
-template <typename T> int run_fista(gt_plan *pl, const void *y, const double *lambda, const void *omega,
+template <typename T> int run_fista(gt_plan *pl, const void *y, const double *lambda, const double *omega,
                                     int max_iter, double L, double eta, double tol, void *fhat,
                                     gt_solve_info *info, hipStream_t s);
+template <typename T> int run_fista_path(gt_plan *pl, const void *y, int nlam, const double *lambda,
+                                         const double *omega, int max_iter, double L, double eta, double tol,
+                                         const void *f0, void *path, gt_solve_info *info, hipStream_t s);
 template <typename T> int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s);
+template <typename T> int run_norm_estimate_region(gt_plan *pl, int iters, void *region, size_t cap, size_t *need,
+                                                   double *out, hipStream_t s);
 
-// stream-ordered scratch allocation
+// device allocation (fails with GT_ENOMEM when the allocation-failure hook says so)
 int dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+
+// live plans (gt_release_all, and the check that a handle is one)
+bool plan_is_live(const gt_plan *pl);
 
 }  // namespace gt

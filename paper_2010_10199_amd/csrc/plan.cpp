@@ -75,10 +75,22 @@ void prof_end(hipStream_t s) {
   g_prof_open = -1;
 }
 
-// ------------------------------------------------------------------ scratch
+// ------------------------------------------------------------------ device allocation
+// Allocation-failure hook (gt_debug_fail_alloc): when armed with k >= 1, the k-th device
+// allocation from then on fails with GT_ENOMEM as if the device were out of memory.
+static std::mutex g_alloc_mu;
+static int64_t g_alloc_count = 0;    // device allocations since the last gt_debug_fail_alloc
+static int64_t g_alloc_fail_at = 0;  // 0: hook off
+
 int dev_alloc(void **p, size_t bytes, hipStream_t) {
   *p = nullptr;
   if (bytes == 0) return GT_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    ++g_alloc_count;
+    if (g_alloc_fail_at > 0 && g_alloc_count == g_alloc_fail_at)
+      return fail(GT_ENOMEM, "device allocation failed (allocation-failure hook)");
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -89,6 +101,29 @@ int dev_alloc(void **p, size_t bytes, hipStream_t) {
 
 void dev_free(void *p, hipStream_t) {
   if (p) (void)hipFree(p);
+}
+
+// ------------------------------------------------------------------ live plans
+static std::mutex g_plans_mu;
+static std::vector<gt_plan *> g_plans;
+
+static void plan_register(gt_plan *pl) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  g_plans.push_back(pl);
+}
+
+// Removes pl from the live set; false when it is not a live plan.
+static bool plan_unregister(gt_plan *pl) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  auto it = std::find(g_plans.begin(), g_plans.end(), pl);
+  if (it == g_plans.end()) return false;
+  g_plans.erase(it);
+  return true;
+}
+
+bool plan_is_live(const gt_plan *pl) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  return pl && std::find(g_plans.begin(), g_plans.end(), pl) != g_plans.end();
 }
 
 // ------------------------------------------------------------------ index set
@@ -623,12 +658,13 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
       window_poly(o.m, (long double)o.b, D, o.poly);
       cache_tables(o.N, o.n, o.m, D, o);
     }
-    int r1 = p->dtype == GT_C64 ? upload<float>(o.deconv, &o.d_deconv) : upload<double>(o.deconv, &o.d_deconv);
-    int r2 = p->dtype == GT_C64 ? upload<float>(o.roots, &o.d_roots) : upload<double>(o.roots, &o.d_roots);
-    int r3 = p->dtype == GT_C64 ? upload<float>(o.poly, &o.d_poly) : upload<double>(o.poly, &o.d_poly);
-    if (r1 || r2 || r3) {
+    // one table at a time, stopping at the first failure (so the status and message agree)
+    int rt = p->dtype == GT_C64 ? upload<float>(o.deconv, &o.d_deconv) : upload<double>(o.deconv, &o.d_deconv);
+    if (!rt) rt = p->dtype == GT_C64 ? upload<float>(o.roots, &o.d_roots) : upload<double>(o.roots, &o.d_roots);
+    if (!rt) rt = p->dtype == GT_C64 ? upload<float>(o.poly, &o.d_poly) : upload<double>(o.poly, &o.d_poly);
+    if (rt) {
       free_plan(pl);
-      return r1 ? r1 : (r2 ? r2 : r3);
+      return rt;
     }
   }
 
@@ -794,8 +830,14 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     free_plan(pl);
     return rc;
   }
+  plan_register(pl);
   *out = pl;
   return GT_OK;
+}
+
+// Plans made and released inside one call (the one-shot entry points) are never exposed.
+static void release_plan(gt_plan *pl) {
+  if (pl && plan_unregister(pl)) free_plan(pl);
 }
 
 }  // namespace
@@ -937,16 +979,15 @@ int gt_sensitivity(const gt_problem *p, const void *fhat, double *rho, void *str
   if (int rc = gt_term_table(p, nullptr, offs.data())) return rc;
   const hipStream_t s = (hipStream_t)stream;
   int64_t *d_offs = nullptr;
-  hipError_t e = hipMalloc(&d_offs, offs.size() * sizeof(int64_t));
-  if (e != hipSuccess) return hip_fail(e, "term offsets");
-  e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  if (int rc = dev_alloc((void **)&d_offs, offs.size() * sizeof(int64_t), s)) return rc;
+  hipError_t e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
   int rc = e == hipSuccess ? GT_OK : hip_fail(e, "term offsets");
   if (rc == GT_OK)
     rc = p->dtype == GT_C64 ? run_sensitivity<float>(d_offs, (int)nu, offs[nu], p->R, fhat, rho, s)
                             : run_sensitivity<double>(d_offs, (int)nu, offs[nu], p->R, fhat, rho, s);
   e = hipStreamSynchronize(s);
   if (rc == GT_OK && e != hipSuccess) rc = hip_fail(e, "sensitivity indices");
-  (void)hipFree(d_offs);
+  dev_free(d_offs, s);
   return rc;
 }
 
@@ -956,47 +997,87 @@ int gt_plan_create(const gt_problem *p, const void *x, void *stream, gt_plan **o
 }
 
 int gt_plan_destroy(gt_plan *plan) {
+  if (!plan) return GT_OK;
+  if (!plan_unregister(plan)) return fail(GT_EINVAL, "not a live plan (destroyed or released)");
   free_plan(plan);
   return GT_OK;
 }
 
+int gt_release_all(void) {
+  std::vector<gt_plan *> all;
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    all.swap(g_plans);
+  }
+  for (gt_plan *pl : all) free_plan(pl);
+  {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    g_tab.clear();
+  }
+  return GT_OK;
+}
+
+int gt_debug_fail_alloc(int64_t k) {
+  if (k < 0) return fail(GT_EINVAL, "k must be >= 0");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc_fail_at = k;
+  g_alloc_count = 0;
+  return GT_OK;
+}
+
+int64_t gt_debug_alloc_count(void) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc_count;
+}
+
+#define GT_LIVE(plan)                                                                 \
+  do {                                                                                \
+    if (!plan_is_live(plan)) return fail(GT_EINVAL, "not a live plan (destroyed or released)"); \
+  } while (0)
+
 int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n) {
-  if (!plan || t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  GT_LIVE(plan);
+  if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
   if (m) *m = plan->ord[t].m;
   if (n) *n = plan->ord[t].n;
   return GT_OK;
 }
 
 int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path) {
-  if (!plan || t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  GT_LIVE(plan);
+  if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
   const OrderHost &o = plan->ord[t];
   if (path) *path = o.d_kpoly ? GT_GATHER_POLY : (!o.citems.empty() ? GT_GATHER_CELL : GT_GATHER_SORTED);
   return GT_OK;
 }
 
 int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream) {
-  if (!plan || !fhat || !f) return fail(GT_EINVAL, "NULL argument");
+  GT_LIVE(plan);
+  if (!fhat || !f) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
   return plan->dtype == GT_C64 ? launch_forward<float>(plan, fhat, nullptr, f, (hipStream_t)stream)
                                : launch_forward<double>(plan, fhat, nullptr, f, (hipStream_t)stream);
 }
 
 int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream) {
-  if (!plan || !fhat || !y) return fail(GT_EINVAL, "NULL argument");
+  GT_LIVE(plan);
+  if (!fhat || !y) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
   return plan->dtype == GT_C64 ? launch_adjoint<float>(plan, y, nullptr, fhat, (hipStream_t)stream)
                                : launch_adjoint<double>(plan, y, nullptr, fhat, (hipStream_t)stream);
 }
 
 int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, void *stream) {
-  if (!plan || !fhat || !g || !gx) return fail(GT_EINVAL, "NULL argument");
+  GT_LIVE(plan);
+  if (!fhat || !g || !gx) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
   return plan->dtype == GT_C64 ? launch_node_grad<float>(plan, fhat, g, gx, (hipStream_t)stream)
                                : launch_node_grad<double>(plan, fhat, g, gx, (hipStream_t)stream);
 }
 
 int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *stream) {
-  if (!plan || !out || iters < 1) return fail(GT_EINVAL, "invalid argument");
+  GT_LIVE(plan);
+  if (!out || iters < 1) return fail(GT_EINVAL, "invalid argument");
   plan->stream = (hipStream_t)stream;
   return plan->dtype == GT_C64 ? run_norm_estimate<float>(plan, iters, out, (hipStream_t)stream)
                                : run_norm_estimate<double>(plan, iters, out, (hipStream_t)stream);
@@ -1007,7 +1088,7 @@ int grouped_trafo(const gt_problem *p, const void *x, const void *fhat, void *f,
   int rc = build_plan(p, x, (hipStream_t)stream, &pl);
   if (rc) return rc;
   rc = gt_plan_trafo(pl, fhat, f, stream);
-  free_plan(pl);
+  release_plan(pl);
   return rc;
 }
 
@@ -1016,42 +1097,92 @@ int grouped_adjoint(const gt_problem *p, const void *x, const void *y, void *fha
   int rc = build_plan(p, x, (hipStream_t)stream, &pl);
   if (rc) return rc;
   rc = gt_plan_adjoint(pl, y, fhat, stream);
-  free_plan(pl);
+  release_plan(pl);
   return rc;
 }
 
-int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *lambda, const void *omega,
+static int check_lambda(int R, const double *lambda, bool positive) {
+  for (int r = 0; r < R; ++r) {
+    const double l = lambda[r];
+    if (!std::isfinite(l) || (positive ? !(l > 0.0) : !(l >= 0.0)))
+      return fail(GT_EINVAL, positive ? "lambda must be finite and > 0" : "lambda must be finite and >= 0");
+  }
+  return GT_OK;
+}
+
+int gt_plan_lsqr(gt_plan *plan, const void *y, const double *lambda, const double *omega, int32_t max_iter,
+                 double tol, void *fhat, gt_solve_info *info, void *stream) {
+  GT_LIVE(plan);
+  if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (int rc = check_lambda(plan->R, lambda, false)) return rc;
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64
+             ? run_lsqr<float>(plan, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream)
+             : run_lsqr<double>(plan, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream);
+}
+
+int gt_plan_fista(gt_plan *plan, const void *y, const double *lambda, const double *omega, int32_t max_iter,
+                  double L, double eta, double tol, void *fhat, gt_solve_info *info, void *stream) {
+  GT_LIVE(plan);
+  if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (!std::isfinite(L) || !std::isfinite(eta)) return fail(GT_EINVAL, "L and eta must be finite");
+  if (int rc = check_lambda(plan->R, lambda, true)) return rc;
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64
+             ? run_fista<float>(plan, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream)
+             : run_fista<double>(plan, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream);
+}
+
+int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *lambda, const double *omega,
                int32_t max_iter, double tol, void *fhat, gt_solve_info *info, void *stream) {
   if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
   if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
-  if (p)
-    for (int r = 0; r < p->R; ++r)
-      if (!(lambda[r] >= 0.0) || !std::isfinite(lambda[r])) return fail(GT_EINVAL, "lambda must be finite and >= 0");
+  if (p && p->R >= 1)
+    if (int rc = check_lambda(p->R, lambda, false)) return rc;
   gt_plan *pl = nullptr;
   int rc = build_plan(p, x, (hipStream_t)stream, &pl);
   if (rc) return rc;
-  rc = pl->dtype == GT_C64 ? run_lsqr<float>(pl, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream)
-                           : run_lsqr<double>(pl, y, lambda, omega, max_iter, tol, fhat, info, (hipStream_t)stream);
-  free_plan(pl);
+  rc = gt_plan_lsqr(pl, y, lambda, omega, max_iter, tol, fhat, info, stream);
+  release_plan(pl);
   return rc;
 }
 
-int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda, const void *omega,
+int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const double *lambda, const double *omega,
                       int32_t max_iter, double L, double eta, double tol, void *fhat, gt_solve_info *info,
                       void *stream) {
   if (!y || !lambda || !fhat || !info) return fail(GT_EINVAL, "NULL argument");
   if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
   if (!std::isfinite(L) || !std::isfinite(eta)) return fail(GT_EINVAL, "L and eta must be finite");
-  if (p)
-    for (int r = 0; r < p->R; ++r)
-      if (!(lambda[r] > 0.0) || !std::isfinite(lambda[r])) return fail(GT_EINVAL, "lambda must be finite and > 0");
+  if (p && p->R >= 1)
+    if (int rc = check_lambda(p->R, lambda, true)) return rc;
   gt_plan *pl = nullptr;
   int rc = build_plan(p, x, (hipStream_t)stream, &pl);
   if (rc) return rc;
+  rc = gt_plan_fista(pl, y, lambda, omega, max_iter, L, eta, tol, fhat, info, stream);
+  release_plan(pl);
+  return rc;
+}
+
+int fista_group_lasso_path(const gt_problem *p, const void *x, const void *y, int32_t nlambda, const double *lambda,
+                           const double *omega, int32_t max_iter, double L, double eta, double tol,
+                           const void *fhat0, void *fhat_path, gt_solve_info *info, void *stream) {
+  if (!y || !lambda || !fhat_path || !info) return fail(GT_EINVAL, "NULL argument");
+  if (nlambda < 1) return fail(GT_EINVAL, "nlambda must be >= 1");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (!std::isfinite(L) || !std::isfinite(eta)) return fail(GT_EINVAL, "L and eta must be finite");
+  if (int rc = check_lambda(nlambda, lambda, true)) return rc;
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  pl->stream = (hipStream_t)stream;
   rc = pl->dtype == GT_C64
-           ? run_fista<float>(pl, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream)
-           : run_fista<double>(pl, y, lambda, omega, max_iter, L, eta, tol, fhat, info, (hipStream_t)stream);
-  free_plan(pl);
+           ? run_fista_path<float>(pl, y, nlambda, lambda, omega, max_iter, L, eta, tol, fhat0, fhat_path, info,
+                                   (hipStream_t)stream)
+           : run_fista_path<double>(pl, y, nlambda, lambda, omega, max_iter, L, eta, tol, fhat0, fhat_path, info,
+                                    (hipStream_t)stream);
+  release_plan(pl);
   return rc;
 }
 

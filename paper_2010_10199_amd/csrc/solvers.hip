@@ -263,16 +263,16 @@ __global__ __launch_bounds__(kVecBS) void k_lsqr_xw(int64_t n, const LsqrState *
 }
 
 template <typename T>
-__global__ __launch_bounds__(kVecBS) void k_colscale(int64_t ncoef, const T *__restrict__ omega, T *__restrict__ cs,
+__global__ __launch_bounds__(kVecBS) void k_colscale(int64_t ncoef, const double *__restrict__ omega, T *__restrict__ cs,
                                                      int32_t *__restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * kVecBS + threadIdx.x;
   if (i >= ncoef) return;
-  const T w = omega[i];
-  if (!(w > (T)0) || !isfinite(w)) {
+  const double w = omega[i];
+  if (!(w > 0.0) || !isfinite(w)) {
     atomicOr(bad, 1);
-    cs[i] = (T)1;
-  } else {
-    cs[i] = (T)(1.0 / sqrt((double)w));
+    if (cs) cs[i] = (T)1;
+  } else if (cs) {
+    cs[i] = (T)(1.0 / sqrt(w));
   }
 }
 
@@ -290,21 +290,51 @@ __global__ __launch_bounds__(kVecBS) void k_c_mul_colscale(int64_t n, const T *_
 }
 
 // ---------------------------------------------------------------- FISTA kernels
-// res = (1 + beta) Fcur - beta Fold - y   (beta = 0: res = Fcur - y)
+// Per right-hand side state of the device-resident FISTA iteration (all FP64).  A host
+// step enqueues one trial of Algorithm algo:fista for every right-hand side; k_fista_decide
+// then accepts the trial (the iteration advances) or, when the backtracking test fails,
+// multiplies L by eta so that the next step retries the same h.
+struct FistaState {
+  double L;          // step constant of the current trial
+  double t;          // t_k
+  double beta;       // (t_{k-1} - 1) / t_k: h = f_k + beta (f_k - f_{k-1}), so F h from F f_k, F f_{k-1}
+  double rel;        // relative step ||f_k - f_{k-1}|| / ||f_k|| of the last accepted iteration
+  int32_t k;         // accepted iterations
+  int32_t ninc;      // increases of L within the current iteration
+  int32_t frozen;    // finished: max_iter reached or converged; no further updates
+  int32_t accept;    // the current step's trial was accepted
+  int32_t capped;    // an iteration reached the backtracking cap
+  int32_t converged;
+};
+
+__global__ void k_fista_init(int R, const double *__restrict__ L0, FistaState *__restrict__ st) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  FistaState s{};
+  s.L = L0[r];
+  s.t = 1.0;
+  st[r] = s;
+}
+
+// res = F h - y with F h = (1 + beta_r) F f_k - beta_r F f_{k-1} (F f_{k-1} unread when beta_r = 0).
 template <typename T>
-__global__ __launch_bounds__(kVecBS) void k_fista_resid(int64_t V, double beta, const cx_t<T> *__restrict__ Fcur,
-                                                        const cx_t<T> *__restrict__ Fold, const cx_t<T> *__restrict__ y,
-                                                        cx_t<T> *__restrict__ res) {
-  const int64_t i = (int64_t)blockIdx.x * kVecBS + threadIdx.x;
-  if (i >= V) return;
-  const cx_t<T> a = Fcur[i], c = y[i];
-  double re = (1.0 + beta) * (double)a.x - (double)c.x, im = (1.0 + beta) * (double)a.y - (double)c.y;
-  if (beta != 0.0) {
-    const cx_t<T> b = Fold[i];
-    re -= beta * (double)b.x;
-    im -= beta * (double)b.y;
+__global__ __launch_bounds__(kVecBS) void k_fista_resid(const WorkItem *__restrict__ items,
+                                                        const FistaState *__restrict__ st,
+                                                        const cx_t<T> *__restrict__ Fcur, const cx_t<T> *__restrict__ Fold,
+                                                        const cx_t<T> *__restrict__ y, cx_t<T> *__restrict__ res) {
+  const WorkItem it = items[blockIdx.x];
+  const double beta = st[it.r].beta;
+  for (int i = threadIdx.x; i < it.count; i += kVecBS) {
+    const int64_t v = it.v0 + i;
+    const cx_t<T> a = Fcur[v], c = y[v];
+    double re = (1.0 + beta) * (double)a.x - (double)c.x, im = (1.0 + beta) * (double)a.y - (double)c.y;
+    if (beta != 0.0) {
+      const cx_t<T> b = Fold[v];
+      re -= beta * (double)b.x;
+      im -= beta * (double)b.y;
+    }
+    res[v] = mk<T>((T)re, (T)im);
   }
-  res[i] = mk<T>((T)re, (T)im);
 }
 
 // t(xi) = sum_k w_k a_k xi^2 / (1 + xi w_k)^2 and its derivative (a_k = |z_k|^2).
@@ -316,15 +346,17 @@ struct GroupView {
 // stats[(r * ngroups + group) * 2 + {0,1}] = ||f_new - f_cur||^2, ||f_new||^2 over the group.
 template <typename T>
 __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int64_t *__restrict__ goff, int ngroups,
-                                                       const double *__restrict__ lambda, const double *__restrict__ Lr,
-                                                       const T *__restrict__ omega, const cx_t<T> *__restrict__ h,
+                                                       const double *__restrict__ lambda,
+                                                       const FistaState *__restrict__ st,
+                                                       const double *__restrict__ omega, const cx_t<T> *__restrict__ h,
                                                        const cx_t<T> *__restrict__ g, const cx_t<T> *__restrict__ fcur,
                                                        cx_t<T> *__restrict__ fnew, double *__restrict__ stats) {
   __shared__ double sh[kVecBS / 64 + 1];
   const int grp = blockIdx.x, r = blockIdx.y;
+  if (st[r].frozen) return;   // uniform per workgroup
   const int64_t lo = goff[grp], hi = goff[grp + 1];
   const int64_t base = (int64_t)r * ncoef;
-  const double L = Lr[r];
+  const double L = st[r].L;
   const double tau = lambda[r] / L;
   const double invL = 1.0 / L;
   auto zval = [&](int64_t k, double &zr, double &zi) {
@@ -337,7 +369,7 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
   for (int64_t k = lo + threadIdx.x; k < hi; k += kVecBS) {
     double zr, zi;
     zval(k, zr, zi);
-    const double w = omega ? (double)omega[k] : 1.0;
+    const double w = omega ? omega[k] : 1.0;
     s += (zr * zr + zi * zi) / w;
   }
   const double zero_level = sqrt(block_sum_all(s, sh));
@@ -352,7 +384,7 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
       for (int64_t k = lo + threadIdx.x; k < hi; k += kVecBS) {
         double zr, zi;
         zval(k, zr, zi);
-        const double w = (double)omega[k], a = zr * zr + zi * zi;
+        const double w = omega[k], a = zr * zr + zi * zi;
         const double den = 1.0 + xv * w;
         acc += w * a * xv * xv / (den * den);
       }
@@ -363,7 +395,7 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
       for (int64_t k = lo + threadIdx.x; k < hi; k += kVecBS) {
         double zr, zi;
         zval(k, zr, zi);
-        const double w = (double)omega[k], a = zr * zr + zi * zi;
+        const double w = omega[k], a = zr * zr + zi * zi;
         const double den = zeta + w;
         acc += w * a / (den * den);
       }
@@ -389,7 +421,7 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
       for (int64_t k = lo + threadIdx.x; k < hi; k += kVecBS) {
         double zr, zi;
         zval(k, zr, zi);
-        const double w = (double)omega[k], a = zr * zr + zi * zi;
+        const double w = omega[k], a = zr * zr + zi * zi;
         const double den = 1.0 + xi * w;
         v += w * a * xi * xi / (den * den);
         dv += w * a * 2.0 * xi / (den * den * den);
@@ -407,7 +439,7 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
     zval(k, zr, zi);
     double fr = 0, fi = 0;
     if (!zero) {
-      const double sc = omega ? 1.0 / (1.0 + xi * (double)omega[k]) : scale;
+      const double sc = omega ? 1.0 / (1.0 + xi * omega[k]) : scale;
       fr = sc * zr;
       fi = sc * zi;
     }
@@ -426,14 +458,84 @@ __global__ __launch_bounds__(kVecBS) void k_fista_prox(int64_t ncoef, const int6
   }
 }
 
-// h = f_new + beta (f_new - f_cur)
+// One workgroup per right-hand side: the relative step from the prox statistics (sums over
+// the groups in a fixed order), then the trial's verdict.  With backtracking the trial is
+// accepted when ||F(f - h)||^2 <= L ||f - h||^2 (the algorithm's test in an equivalent
+// form); otherwise L grows by eta and the next step retries, except after `cap` increases
+// within one iteration, when the trial is taken as it is and the cap is flagged.
+__global__ __launch_bounds__(kVecBS) void k_fista_decide(int ngroups, const double *__restrict__ stats,
+                                                         const double *__restrict__ nd, const double *__restrict__ nFd,
+                                                         int backtrack, double eta, int cap, int max_iter, double tol,
+                                                         FistaState *__restrict__ st) {
+  __shared__ double sh[kVecBS / 64 + 1];
+  const int r = blockIdx.x;
+  if (st[r].frozen) {   // uniform per workgroup
+    if (threadIdx.x == 0) st[r].accept = 0;
+    return;
+  }
+  double dd = 0, nn = 0;
+  for (int gi = threadIdx.x; gi < ngroups; gi += kVecBS) {
+    dd += stats[((int64_t)r * ngroups + gi) * 2];
+    nn += stats[((int64_t)r * ngroups + gi) * 2 + 1];
+  }
+  dd = block_sum_all(dd, sh);
+  nn = block_sum_all(nn, sh);
+  if (threadIdx.x != 0) return;
+  FistaState s = st[r];
+  const bool pass = !backtrack || !(nFd[r] > s.L * nd[r]);
+  if (!pass && s.ninc < cap) {
+    s.L *= eta;
+    s.ninc += 1;
+    s.accept = 0;
+    st[r] = s;
+    return;
+  }
+  if (!pass) s.capped = 1;
+  s.accept = 1;
+  s.ninc = 0;
+  s.k += 1;
+  const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * s.t * s.t));
+  s.beta = (s.t - 1.0) / t_next;
+  s.t = t_next;
+  s.rel = nn > 0 ? sqrt(dd / nn) : sqrt(dd);
+  if (tol > 0 && s.rel <= tol) {
+    s.converged = 1;
+    s.frozen = 1;
+  }
+  if (s.k >= max_iter) s.frozen = 1;
+  st[r] = s;
+}
+
+// Accepted trial, coefficient space: h = f_new + beta (f_new - f_cur), f_cur = f_new.
 template <typename T>
-__global__ __launch_bounds__(kVecBS) void k_fista_momentum(int64_t total, double beta, const cx_t<T> *__restrict__ fnew,
-                                                           const cx_t<T> *__restrict__ fcur, cx_t<T> *__restrict__ h) {
-  const int64_t i = (int64_t)blockIdx.x * kVecBS + threadIdx.x;
-  if (i >= total) return;
-  const cx_t<T> a = fnew[i], b = fcur[i];
-  h[i] = mk<T>((T)((double)a.x + beta * ((double)a.x - b.x)), (T)((double)a.y + beta * ((double)a.y - b.y)));
+__global__ __launch_bounds__(kVecBS) void k_fista_apply_c(int64_t n, const FistaState *__restrict__ st,
+                                                          const cx_t<T> *__restrict__ fnew, cx_t<T> *__restrict__ fcur,
+                                                          cx_t<T> *__restrict__ h) {
+  const int r = blockIdx.y;
+  if (!st[r].accept) return;
+  const double beta = st[r].beta;
+  const int64_t lo = (int64_t)blockIdx.x * kCoefChunk, hi = min(n, lo + kCoefChunk);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kVecBS) {
+    const int64_t k = (int64_t)r * n + i;
+    const cx_t<T> a = fnew[k], b = fcur[k];
+    h[k] = mk<T>((T)((double)a.x + beta * ((double)a.x - b.x)), (T)((double)a.y + beta * ((double)a.y - b.y)));
+    fcur[k] = a;
+  }
+}
+
+// Accepted trial, sample space: F f_{k-1} = F f_k, F f_k = F f_new.
+template <typename T>
+__global__ __launch_bounds__(kVecBS) void k_fista_apply_v(const WorkItem *__restrict__ items,
+                                                          const FistaState *__restrict__ st,
+                                                          const cx_t<T> *__restrict__ Fnew, cx_t<T> *__restrict__ Fcur,
+                                                          cx_t<T> *__restrict__ Fold) {
+  const WorkItem it = items[blockIdx.x];
+  if (!st[it.r].accept) return;
+  for (int i = threadIdx.x; i < it.count; i += kVecBS) {
+    const int64_t v = it.v0 + i;
+    Fold[v] = Fcur[v];
+    Fcur[v] = Fnew[v];
+  }
 }
 
 // d = a - b
@@ -445,6 +547,8 @@ __global__ __launch_bounds__(kVecBS) void k_sub(int64_t total, const cx_t<T> *__
   const cx_t<T> x = a[i], z = b[i];
   d[i] = mk<T>(x.x - z.x, x.y - z.y);
 }
+
+__global__ void k_zero_flag(int32_t *f) { *f = 0; }
 
 __global__ void k_neg(int R, const double *__restrict__ a, double *__restrict__ na) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,16 +562,40 @@ int check(const char *what) {
   return e == hipSuccess ? GT_OK : hip_fail(e, what);
 }
 
-// Scratch owned by one solver call.
+// Device scratch of one solver call.  By default every buffer is its own allocation, freed
+// when the call ends.  In carve mode the buffers are consecutive 256-byte aligned pieces of
+// one caller-provided region (nothing is allocated; a request past its end fails), and in
+// measure mode nothing is handed out and `used` totals the bytes the buffers would take.
 struct Scratch {
+  enum Mode { Alloc, Carve, Measure };
+  Mode mode = Alloc;
+  unsigned char *base = nullptr;
+  size_t cap = 0, used = 0;
   std::vector<void *> ptrs;
+  Scratch() = default;
+  Scratch(Mode m, void *b, size_t c) : mode(m), base((unsigned char *)b), cap(c) {}
+  Scratch(const Scratch &) = delete;
+  Scratch &operator=(const Scratch &) = delete;
   ~Scratch() {
     for (void *p : ptrs) dev_free(p, nullptr);
   }
   template <typename P>
   int get(P **p, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 16);
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (mode == Measure) {
+      used += need;
+      *p = nullptr;
+      return GT_OK;
+    }
+    if (mode == Carve) {
+      if (used + need > cap) return fail(GT_EINVAL, "work buffers exceed the fixed scratch region");
+      *p = (P *)(base + used);
+      used += need;
+      return GT_OK;
+    }
     void *q = nullptr;
-    int rc = dev_alloc(&q, std::max<size_t>(bytes, 16), nullptr);
+    int rc = dev_alloc(&q, bytes, nullptr);
     if (rc) return rc;
     ptrs.push_back(q);
     *p = (P *)q;
@@ -507,8 +635,24 @@ struct Norms {
 }  // namespace
 
 // ================================================================== LSQR
+// Column scaling 1 / sqrt(omega) (device, T) from the FP64 weights, with the weights checked.
 template <typename T>
-int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega, int max_iter, double tol, void *fhat,
+static int weight_scale(const double *omega, int64_t n, Scratch &sc, T **cs, hipStream_t s) {
+  int32_t *bad = nullptr;
+  int rc;
+  if ((rc = sc.get(&bad, sizeof(int32_t)))) return rc;
+  if (cs && (rc = sc.get(cs, n * sizeof(T)))) return rc;
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, s, bad);
+  hipLaunchKernelGGL((k_colscale<T>), dim3(nblk(n)), dim3(kVecBS), 0, s, n, omega, cs ? *cs : (T *)nullptr, bad);
+  int32_t hbad = 0;
+  GT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
+  GT_HIP(hipStreamSynchronize(s));
+  if (hbad) return fail(GT_EINVAL, "weights must be finite and > 0");
+  return GT_OK;
+}
+
+template <typename T>
+int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *omega, int max_iter, double tol, void *fhat,
              gt_solve_info *info, hipStream_t s) {
   using C = cx_t<T>;
   const int R = pl->R;
@@ -518,28 +662,18 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega
   double *alpha, *beta, *ialpha, *ibeta, *dlam;
   LsqrState *st;
   T *cs = nullptr;
-  int32_t *bad;
   int rc;
   if ((rc = sc.get(&u, V * sizeof(C))) || (rc = sc.get(&tV, V * sizeof(C))) || (rc = sc.get(&v, n * R * sizeof(C))) ||
       (rc = sc.get(&w, n * R * sizeof(C))) || (rc = sc.get(&x, n * R * sizeof(C))) ||
       (rc = sc.get(&tI, n * R * sizeof(C))) || (rc = sc.get(&alpha, R * sizeof(double))) ||
       (rc = sc.get(&beta, R * sizeof(double))) || (rc = sc.get(&ialpha, R * sizeof(double))) ||
       (rc = sc.get(&ibeta, R * sizeof(double))) || (rc = sc.get(&dlam, R * sizeof(double))) ||
-      (rc = sc.get(&st, R * sizeof(LsqrState))) || (rc = sc.get(&bad, sizeof(int32_t))))
+      (rc = sc.get(&st, R * sizeof(LsqrState))))
     return rc;
   Norms<T> nm{pl};
   if ((rc = nm.init(sc))) return rc;
   GT_HIP(hipMemcpyAsync(dlam, lambda, R * sizeof(double), hipMemcpyHostToDevice, s));
-  if (omega) {
-    if ((rc = sc.get(&cs, n * sizeof(T)))) return rc;
-    int32_t zero = 0;
-    GT_HIP(hipMemcpyAsync(bad, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL((k_colscale<T>), dim3(nblk(n)), dim3(kVecBS), 0, s, n, (const T *)omega, cs, bad);
-    int32_t hbad = 0;
-    GT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
-    GT_HIP(hipStreamSynchronize(s));
-    if (hbad) return fail(GT_EINVAL, "weights must be finite and > 0");
-  }
+  if (omega && (rc = weight_scale<T>(omega, n, sc, &cs, s))) return rc;
   const unsigned nchunk = (unsigned)nm.nchunk;
   // beta_1 u_1 = y
   if ((rc = nm.v_axpby((const C *)y, nullptr, nullptr, nullptr, u, beta, ibeta, s))) return rc;
@@ -605,208 +739,291 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const void *omega
 }
 
 // ================================================================== power iteration
+// Rayleigh-quotient estimate of ||F||_2^2 per right-hand side from the all-ones start.
 template <typename T>
-static int power_iter(gt_plan *pl, int iters, Scratch &sc, double *est_host, hipStream_t s) {
-  using C = cx_t<T>;
+struct PowerBuf {
+  cx_t<T> *v = nullptr, *wv = nullptr, *tV = nullptr;
+  double *nrm = nullptr, *inv = nullptr, *dot = nullptr, *partV = nullptr, *partC = nullptr;
+  int get(const gt_plan *pl, Scratch &sc) {
+    const int R = pl->R;
+    const int64_t V = pl->Vtot, n = pl->ncoef;
+    const int64_t nchunk = (n + kCoefChunk - 1) / kCoefChunk;
+    using C = cx_t<T>;
+    int rc;
+    if ((rc = sc.get(&v, n * R * sizeof(C))) || (rc = sc.get(&wv, n * R * sizeof(C))) ||
+        (rc = sc.get(&tV, V * sizeof(C))) || (rc = sc.get(&nrm, R * sizeof(double))) ||
+        (rc = sc.get(&inv, R * sizeof(double))) || (rc = sc.get(&dot, R * sizeof(double))) ||
+        (rc = sc.get(&partV, sizeof(double) * std::max<size_t>(1, pl->gitems.size()))) ||
+        (rc = sc.get(&partC, sizeof(double) * (size_t)nchunk * R)))
+      return rc;
+    return GT_OK;
+  }
+};
+
+template <typename T>
+static int power_run(gt_plan *pl, int iters, PowerBuf<T> &b, double *est_host, hipStream_t s) {
   const int R = pl->R;
-  const int64_t V = pl->Vtot, n = pl->ncoef;
-  C *v, *wv, *tV;
-  double *nrm, *inv, *dot, *partC;
-  int rc;
-  if ((rc = sc.get(&v, n * R * sizeof(C))) || (rc = sc.get(&wv, n * R * sizeof(C))) ||
-      (rc = sc.get(&tV, V * sizeof(C))) || (rc = sc.get(&nrm, R * sizeof(double))) ||
-      (rc = sc.get(&inv, R * sizeof(double))) || (rc = sc.get(&dot, R * sizeof(double))))
-    return rc;
+  const int64_t n = pl->ncoef;
   Norms<T> nm{pl};
-  if ((rc = nm.init(sc))) return rc;
-  partC = nm.partC;
+  nm.partV = b.partV;
+  nm.partC = b.partC;
+  nm.nchunk = (int)((n + kCoefChunk - 1) / kCoefChunk);
   const unsigned nchunk = (unsigned)nm.nchunk;
+  cx_t<T> *v = b.v, *wv = b.wv;
+  int rc;
   // v = ones / sqrt(n)
   hipLaunchKernelGGL((k_c_fill_value<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (T)(1.0 / std::sqrt((double)n)),
                      v);
   for (int k = 0; k < iters; ++k) {
-    if ((rc = launch_forward<T>(pl, v, nullptr, tV, s))) return rc;
-    if ((rc = launch_adjoint<T>(pl, tV, nullptr, wv, s))) return rc;
-    hipLaunchKernelGGL((k_c_dot<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, v, wv, partC);
-    hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kVecBS), 0, s, partC, nullptr, (int)nchunk, R, dot, nullptr, nullptr);
-    if ((rc = nm.c_axpby(wv, nullptr, nullptr, nullptr, wv, nrm, inv, s))) return rc;
-    hipLaunchKernelGGL((k_c_scale<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, inv, wv);
+    if ((rc = launch_forward<T>(pl, v, nullptr, b.tV, s))) return rc;
+    if ((rc = launch_adjoint<T>(pl, b.tV, nullptr, wv, s))) return rc;
+    hipLaunchKernelGGL((k_c_dot<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, v, wv, b.partC);
+    hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kVecBS), 0, s, b.partC, nullptr, (int)nchunk, R, b.dot, nullptr,
+                       nullptr);
+    if ((rc = nm.c_axpby(wv, nullptr, nullptr, nullptr, wv, b.nrm, b.inv, s))) return rc;
+    hipLaunchKernelGGL((k_c_scale<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, b.inv, wv);
     std::swap(v, wv);
     if ((rc = check("power iteration"))) return rc;
   }
-  GT_HIP(hipMemcpyAsync(est_host, dot, R * sizeof(double), hipMemcpyDeviceToHost, s));
+  GT_HIP(hipMemcpyAsync(est_host, b.dot, R * sizeof(double), hipMemcpyDeviceToHost, s));
   GT_HIP(hipStreamSynchronize(s));
   return GT_OK;
 }
 
 template <typename T>
-int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s) {
+static int power_iter(gt_plan *pl, int iters, double *est_host, hipStream_t s) {
   Scratch sc;
+  PowerBuf<T> b;
+  if (int rc = b.get(pl, sc)) return rc;
+  return power_run<T>(pl, iters, b, est_host, s);
+}
+
+template <typename T>
+int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s) {
   std::vector<double> est(pl->R);
-  int rc = power_iter<T>(pl, iters, sc, est.data(), s);
+  int rc = power_iter<T>(pl, iters, est.data(), s);
   if (rc) return rc;
   *out = est[0];
   return GT_OK;
 }
 
-// ================================================================== FISTA
+// The same estimate with every work buffer carved from a fixed device region (the caller's
+// memory is not touched beyond the plan); region NULL measures: *need = bytes required.
 template <typename T>
-int run_fista(gt_plan *pl, const void *y, const double *lambda, const void *omega, int max_iter, double L, double eta,
-              double tol, void *fhat, gt_solve_info *info, hipStream_t s) {
-  using C = cx_t<T>;
-  const int R = pl->R;
-  const int64_t V = pl->Vtot, n = pl->ncoef;
-  const int ngroups = pl->nterms;
-  Scratch sc;
-  C *fa, *fb, *h, *g, *Fcur, *Fold, *res;
-  double *dlam, *dL, *stats;
-  int64_t *goff;
-  int32_t *bad;
-  int rc;
-  if ((rc = sc.get(&fa, n * R * sizeof(C))) || (rc = sc.get(&fb, n * R * sizeof(C))) ||
-      (rc = sc.get(&h, n * R * sizeof(C))) || (rc = sc.get(&g, n * R * sizeof(C))) ||
-      (rc = sc.get(&Fcur, V * sizeof(C))) || (rc = sc.get(&Fold, V * sizeof(C))) || (rc = sc.get(&res, V * sizeof(C))) ||
-      (rc = sc.get(&dlam, R * sizeof(double))) || (rc = sc.get(&dL, R * sizeof(double))) ||
-      (rc = sc.get(&stats, (size_t)R * ngroups * 2 * sizeof(double))) ||
-      (rc = sc.get(&goff, (size_t)(ngroups + 1) * sizeof(int64_t))) || (rc = sc.get(&bad, sizeof(int32_t))))
-    return rc;
-  if (omega) {
-    T *tmp = nullptr;
-    if ((rc = sc.get(&tmp, n * sizeof(T)))) return rc;
-    int32_t zero = 0;
-    GT_HIP(hipMemcpyAsync(bad, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL((k_colscale<T>), dim3(nblk(n)), dim3(kVecBS), 0, s, n, (const T *)omega, tmp, bad);
-    int32_t hbad = 0;
-    GT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
-    GT_HIP(hipStreamSynchronize(s));
-    if (hbad) return fail(GT_EINVAL, "weights must be finite and > 0");
+int run_norm_estimate_region(gt_plan *pl, int iters, void *region, size_t cap, size_t *need, double *out,
+                             hipStream_t s) {
+  {
+    Scratch m(Scratch::Measure, nullptr, 0);
+    PowerBuf<T> b;
+    (void)b.get(pl, m);
+    *need = m.used;
   }
-  std::vector<int64_t> hoff(ngroups + 1);
-  for (int i = 0; i < ngroups; ++i) hoff[i] = pl->terms[i].coef_off;
-  hoff[ngroups] = n;
-  GT_HIP(hipMemcpyAsync(goff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  GT_HIP(hipMemcpyAsync(dlam, lambda, R * sizeof(double), hipMemcpyHostToDevice, s));
-  std::vector<double> hL(R, L);
-  if (!(L > 0)) {
-    std::vector<double> est(R);
-    if ((rc = power_iter<T>(pl, 50, sc, est.data(), s))) return rc;
-    for (int r = 0; r < R; ++r) hL[r] = 1.05 * est[r];
-  }
-  for (int r = 0; r < R; ++r)
-    if (!(hL[r] > 0) || !std::isfinite(hL[r])) return fail(GT_EINVAL, "step constant L must be > 0");
-  GT_HIP(hipMemcpyAsync(dL, hL.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
-  const bool backtrack = eta > 1.0;
-  C *delta = nullptr, *Fd = nullptr;
-  double *partC = nullptr, *partV = nullptr, *nd = nullptr, *nFd = nullptr;
-  Norms<T> nm{pl};
-  if ((rc = nm.init(sc))) return rc;
-  if (backtrack) {
-    if ((rc = sc.get(&delta, n * R * sizeof(C))) || (rc = sc.get(&Fd, V * sizeof(C))) ||
-        (rc = sc.get(&nd, R * sizeof(double))) || (rc = sc.get(&nFd, R * sizeof(double))))
+  if (!region) return GT_OK;
+  if (*need > cap) return fail(GT_EINVAL, "problem too large for the fixed scratch region");
+  Scratch sc(Scratch::Carve, region, cap);
+  PowerBuf<T> b;
+  if (int rc = b.get(pl, sc)) return rc;
+  std::vector<double> est(pl->R);
+  if (int rc = power_run<T>(pl, iters, b, est.data(), s)) return rc;
+  *out = est[0];
+  return GT_OK;
+}
+
+// ================================================================== FISTA
+// Algorithm algo:fista for R right-hand sides, state on the device (FistaState).  Each host
+// step enqueues one trial for every right-hand side:
+//   res = F h - y  (F h by linearity from F f_k and F f_{k-1});  g = F^H res;
+//   f_new = p_L(h - g / L) (k_fista_prox);  with backtracking: d = f_new - h, ||d||^2 and
+//   ||F d||^2;  F f_new;  verdict (k_fista_decide);  accepted: h, f_k, F f_k, F f_{k-1} advance.
+// A rejected trial only raises L, so the next step redoes the same h.  The host reads the
+// state once per enqueued batch: exactly max_iter steps for the constant step without a
+// tolerance; otherwise batches of (max_iter - the fewest accepted iterations) steps, or of at
+// most 8 steps when a tolerance is set, until every right-hand side is frozen.  With backtracking
+// a step costs one adjoint and two forward transforms, without it one of each.
+template <typename T>
+struct FistaWork {
+  cx_t<T> *fa = nullptr, *fb = nullptr, *h = nullptr, *g = nullptr, *delta = nullptr;
+  cx_t<T> *Fcur = nullptr, *Fold = nullptr, *Fnew = nullptr, *res = nullptr, *Fd = nullptr;
+  double *dlam = nullptr, *dL = nullptr, *stats = nullptr, *nd = nullptr, *nFd = nullptr;
+  int64_t *goff = nullptr;
+  FistaState *st = nullptr;
+  Norms<T> nm{nullptr};
+  int get(gt_plan *pl, Scratch &sc, bool backtrack) {
+    using C = cx_t<T>;
+    const int R = pl->R, ngroups = pl->nterms;
+    const int64_t V = pl->Vtot, n = pl->ncoef;
+    int rc;
+    if ((rc = sc.get(&fa, n * R * sizeof(C))) || (rc = sc.get(&fb, n * R * sizeof(C))) ||
+        (rc = sc.get(&h, n * R * sizeof(C))) || (rc = sc.get(&g, n * R * sizeof(C))) ||
+        (rc = sc.get(&Fcur, V * sizeof(C))) || (rc = sc.get(&Fold, V * sizeof(C))) ||
+        (rc = sc.get(&Fnew, V * sizeof(C))) || (rc = sc.get(&res, V * sizeof(C))) ||
+        (rc = sc.get(&dlam, R * sizeof(double))) || (rc = sc.get(&dL, R * sizeof(double))) ||
+        (rc = sc.get(&stats, (size_t)R * ngroups * 2 * sizeof(double))) ||
+        (rc = sc.get(&goff, (size_t)(ngroups + 1) * sizeof(int64_t))) ||
+        (rc = sc.get(&st, R * sizeof(FistaState))))
       return rc;
-    partC = nm.partC;
-    partV = nm.partV;
+    if (backtrack && ((rc = sc.get(&delta, n * R * sizeof(C))) || (rc = sc.get(&Fd, V * sizeof(C))) ||
+                      (rc = sc.get(&nd, R * sizeof(double))) || (rc = sc.get(&nFd, R * sizeof(double)))))
+      return rc;
+    nm.pl = pl;
+    return nm.init(sc);
   }
-  const unsigned nchunk = (unsigned)nm.nchunk;
-  // f_0 from fhat, h_1 = f_0, t_1 = 1, Fcur = F f_0
-  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)fhat, fa);
-  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)fhat, h);
-  if ((rc = launch_forward<T>(pl, fa, nullptr, Fcur, s))) return rc;
-  double t = 1.0, beta_prev = 0.0;
-  std::vector<double> hstats((size_t)R * ngroups * 2);
-  std::vector<double> rel(R, 0.0);
-  std::vector<int32_t> capped(R, 0);
-  int it = 0;
-  bool converged = false;
-  for (it = 1; it <= max_iter; ++it) {
-    // gradient at h: F^H (F h - y)
-    hipLaunchKernelGGL((k_fista_resid<T>), dim3(nblk(V)), dim3(kVecBS), 0, s, V, beta_prev, Fcur, Fold, (const C *)y,
-                       res);
-    if ((rc = launch_adjoint<T>(pl, res, nullptr, g, s))) return rc;
-    hipLaunchKernelGGL((k_fista_prox<T>), dim3(ngroups, R), dim3(kVecBS), 0, s, n, goff, ngroups, dlam, dL,
-                       (const T *)omega, h, g, fa, fb, stats);
-    if ((rc = check("fista prox"))) return rc;
+};
+
+static constexpr int kBacktrackCap = 30;
+
+// One FISTA solve from f0 (device, R x |I|) into out (may equal f0): lambda and L0 host, R each.
+template <typename T>
+static int fista_solve(gt_plan *pl, FistaWork<T> &w, const void *y, const double *lambda, const double *omega,
+                       int max_iter, const double *L0, double eta, double tol, const void *f0, void *out,
+                       gt_solve_info *info, hipStream_t s) {
+  using C = cx_t<T>;
+  const int R = pl->R, ngroups = pl->nterms;
+  const int64_t n = pl->ncoef;
+  const bool backtrack = eta > 1.0;
+  const unsigned ngi = (unsigned)pl->gitems.size();
+  const unsigned nchunk = (unsigned)w.nm.nchunk;
+  GT_HIP(hipMemcpyAsync(w.dlam, lambda, R * sizeof(double), hipMemcpyHostToDevice, s));
+  GT_HIP(hipMemcpyAsync(w.dL, L0, R * sizeof(double), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fista_init, dim3((R + 63) / 64), dim3(64), 0, s, R, (const double *)w.dL, w.st);
+  // f_0, h_1 = f_0, F f_0
+  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)f0, w.fa);
+  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)f0, w.h);
+  int rc;
+  if ((rc = launch_forward<T>(pl, w.fa, nullptr, w.Fcur, s))) return rc;
+  auto step = [&]() -> int {
+    int e;
+    hipLaunchKernelGGL((k_fista_resid<T>), dim3(ngi), dim3(kVecBS), 0, s, pl->d_gitems, (const FistaState *)w.st,
+                       (const C *)w.Fcur, (const C *)w.Fold, (const C *)y, w.res);
+    if ((e = launch_adjoint<T>(pl, w.res, nullptr, w.g, s))) return e;
+    hipLaunchKernelGGL((k_fista_prox<T>), dim3(ngroups, R), dim3(kVecBS), 0, s, n, (const int64_t *)w.goff, ngroups,
+                       (const double *)w.dlam, (const FistaState *)w.st, omega, (const C *)w.h, (const C *)w.g,
+                       (const C *)w.fa, w.fb, w.stats);
     if (backtrack) {
-      // accept when ||F(f - h)||^2 <= L ||f - h||^2 (exact equivalent of the algorithm's test)
-      for (int trial = 0;; ++trial) {
-        hipLaunchKernelGGL((k_sub<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, fb, h, delta);
-        if ((rc = nm.c_axpby(delta, nullptr, nullptr, nullptr, delta, nullptr, nullptr, s, nd))) return rc;
-        if ((rc = launch_forward<T>(pl, delta, nullptr, Fd, s))) return rc;
-        if ((rc = nm.v_axpby(Fd, nullptr, nullptr, nullptr, Fd, nullptr, nullptr, s))) return rc;
-        hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kVecBS), 0, s, partV, pl->d_gitem_begin, 0, R, nFd, nullptr,
-                           nullptr);
-        std::vector<double> a(R), b(R);
-        GT_HIP(hipMemcpyAsync(a.data(), nFd, R * sizeof(double), hipMemcpyDeviceToHost, s));
-        GT_HIP(hipMemcpyAsync(b.data(), nd, R * sizeof(double), hipMemcpyDeviceToHost, s));
-        GT_HIP(hipStreamSynchronize(s));
-        bool all = true;
-        for (int r = 0; r < R; ++r)
-          if (a[r] > hL[r] * b[r]) {
-            all = false;
-            if (trial < 30) hL[r] *= eta;
-          }
-        if (all) break;
-        if (trial >= 30) {
-          for (int r = 0; r < R; ++r) capped[r] = 1;
-          break;
-        }
-        GT_HIP(hipMemcpyAsync(dL, hL.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL((k_fista_prox<T>), dim3(ngroups, R), dim3(kVecBS), 0, s, n, goff, ngroups, dlam, dL,
-                           (const T *)omega, h, g, fa, fb, stats);
-        if ((rc = check("fista prox"))) return rc;
-      }
+      hipLaunchKernelGGL((k_sub<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)w.fb, (const C *)w.h,
+                         w.delta);
+      if ((e = w.nm.c_axpby(w.delta, nullptr, nullptr, nullptr, w.delta, nullptr, nullptr, s, w.nd))) return e;
+      if ((e = launch_forward<T>(pl, w.delta, nullptr, w.Fd, s))) return e;
+      hipLaunchKernelGGL((k_v_axpby_norm<T>), dim3(ngi), dim3(kVecBS), 0, s, pl->d_gitems, (const C *)w.Fd,
+                         (const double *)nullptr, (const C *)nullptr, (const double *)nullptr, w.Fd, w.nm.partV);
+      hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kVecBS), 0, s, (const double *)w.nm.partV, pl->d_gitem_begin, 0, R,
+                         w.nFd, (double *)nullptr, (double *)nullptr);
     }
-    const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-    const double beta = (t - 1.0) / t_next;
-    hipLaunchKernelGGL((k_fista_momentum<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, beta, fb, fa, h);
-    // F f^k into Fold, then it becomes the current product
-    if ((rc = launch_forward<T>(pl, fb, nullptr, Fold, s))) return rc;
-    std::swap(Fcur, Fold);
-    std::swap(fa, fb);
-    t = t_next;
-    beta_prev = beta;
-    if ((rc = check("fista iteration"))) return rc;
-    if (tol > 0 && (it % 8 == 0 || it == max_iter)) {
-      GT_HIP(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      GT_HIP(hipStreamSynchronize(s));
-      bool all = true;
-      for (int r = 0; r < R; ++r) {
-        double dd = 0, nn = 0;
-        for (int gi = 0; gi < ngroups; ++gi) {
-          dd += hstats[((size_t)r * ngroups + gi) * 2];
-          nn += hstats[((size_t)r * ngroups + gi) * 2 + 1];
-        }
-        rel[r] = nn > 0 ? std::sqrt(dd / nn) : std::sqrt(dd);
-        if (rel[r] > tol) all = false;
+    if ((e = launch_forward<T>(pl, w.fb, nullptr, w.Fnew, s))) return e;
+    hipLaunchKernelGGL(k_fista_decide, dim3(R), dim3(kVecBS), 0, s, ngroups, (const double *)w.stats,
+                       (const double *)w.nd, (const double *)w.nFd, backtrack ? 1 : 0, eta, kBacktrackCap, max_iter,
+                       tol, w.st);
+    hipLaunchKernelGGL((k_fista_apply_c<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, (const FistaState *)w.st,
+                       (const C *)w.fb, w.fa, w.h);
+    hipLaunchKernelGGL((k_fista_apply_v<T>), dim3(ngi), dim3(kVecBS), 0, s, pl->d_gitems, (const FistaState *)w.st,
+                       (const C *)w.Fnew, w.Fcur, w.Fold);
+    return check("fista step");
+  };
+  std::vector<FistaState> hs(R);
+  auto read_state = [&]() -> int {
+    GT_HIP(hipMemcpyAsync(hs.data(), w.st, R * sizeof(FistaState), hipMemcpyDeviceToHost, s));
+    GT_HIP(hipStreamSynchronize(s));
+    return GT_OK;
+  };
+  int64_t steps = 0;
+  const int64_t step_cap = (int64_t)max_iter * (kBacktrackCap + 1);   // every step advances some state
+  int min_k = 0;
+  while (true) {
+    int batch = max_iter - min_k;
+    if (tol > 0) batch = std::min(batch, 8);
+    batch = (int)std::min<int64_t>(std::max(batch, 1), step_cap - steps);
+    for (int b = 0; b < batch; ++b)
+      if ((rc = step())) return rc;
+    steps += batch;
+    if ((rc = read_state())) return rc;
+    bool all = true;
+    min_k = max_iter;
+    for (int r = 0; r < R; ++r)
+      if (!hs[r].frozen) {
+        all = false;
+        min_k = std::min(min_k, hs[r].k);
       }
-      if (all) {
-        converged = true;
-        break;
-      }
-    }
+    if (all || steps >= step_cap) break;
   }
-  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, fa, (C *)fhat);
+  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, (const C *)w.fa, (C *)out);
   if ((rc = check("fista output"))) return rc;
-  GT_HIP(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   GT_HIP(hipStreamSynchronize(s));
   for (int r = 0; r < R; ++r) {
-    double dd = 0, nn = 0;
-    for (int gi = 0; gi < ngroups; ++gi) {
-      dd += hstats[((size_t)r * ngroups + gi) * 2];
-      nn += hstats[((size_t)r * ngroups + gi) * 2 + 1];
-    }
-    rel[r] = nn > 0 ? std::sqrt(dd / nn) : std::sqrt(dd);
-    info[r].iters = std::min(it, max_iter);
-    info[r].resid = rel[r];
-    info[r].t_k = t;
-    info[r].L = hL[r];
+    info[r].iters = hs[r].k;
+    info[r].resid = hs[r].rel;
+    info[r].t_k = hs[r].t;
+    info[r].L = hs[r].L;
     int32_t fl = 0;
-    if (tol > 0 && rel[r] <= tol) fl |= GT_SOLVE_CONVERGED;
-    if (!converged) fl |= GT_SOLVE_MAX_ITER;
-    if (capped[r]) fl |= GT_SOLVE_BACKTRACK_CAP;
+    if (hs[r].converged) fl |= GT_SOLVE_CONVERGED;
+    if (hs[r].k >= max_iter && !hs[r].converged) fl |= GT_SOLVE_MAX_ITER;
+    if (hs[r].capped) fl |= GT_SOLVE_BACKTRACK_CAP;
     info[r].flags = fl;
   }
-  (void)nchunk;
+  return GT_OK;
+}
+
+// Shared set-up of the FISTA entry points: weights checked, group offsets uploaded, the step
+// constants L0 (per right-hand side) chosen.
+template <typename T>
+static int fista_setup(gt_plan *pl, FistaWork<T> &w, Scratch &sc, const double *omega, double L, double eta,
+                       std::vector<double> &L0, hipStream_t s) {
+  const int ngroups = pl->nterms;
+  int rc;
+  if ((rc = w.get(pl, sc, eta > 1.0))) return rc;
+  if (omega && (rc = weight_scale<T>(omega, pl->ncoef, sc, (T **)nullptr, s))) return rc;
+  std::vector<int64_t> hoff(ngroups + 1);
+  for (int i = 0; i < ngroups; ++i) hoff[i] = pl->terms[i].coef_off;
+  hoff[ngroups] = pl->ncoef;
+  GT_HIP(hipMemcpyAsync(w.goff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  GT_HIP(hipStreamSynchronize(s));   // hoff is a host temporary
+  L0.assign(pl->R, L);
+  if (!(L > 0)) {
+    std::vector<double> est(pl->R);
+    if ((rc = power_iter<T>(pl, 50, est.data(), s))) return rc;
+    for (int r = 0; r < pl->R; ++r) L0[r] = 1.05 * est[r];
+  }
+  for (int r = 0; r < pl->R; ++r)
+    if (!(L0[r] > 0) || !std::isfinite(L0[r])) return fail(GT_EINVAL, "step constant L must be > 0");
+  return GT_OK;
+}
+
+template <typename T>
+int run_fista(gt_plan *pl, const void *y, const double *lambda, const double *omega, int max_iter, double L, double eta,
+              double tol, void *fhat, gt_solve_info *info, hipStream_t s) {
+  Scratch sc;
+  FistaWork<T> w;
+  std::vector<double> L0;
+  if (int rc = fista_setup<T>(pl, w, sc, omega, L, eta, L0, s)) return rc;
+  return fista_solve<T>(pl, w, y, lambda, omega, max_iter, L0.data(), eta, tol, fhat, fhat, info, s);
+}
+
+// The warm-started path over lambda[0..nlam-1] (every right-hand side takes lambda[j] at
+// stage j): stage 0 starts from f0 (NULL: zero), each later stage from the previous
+// solution; every stage restarts t_1 = 1 and the step constant at L0.
+template <typename T>
+int run_fista_path(gt_plan *pl, const void *y, int nlam, const double *lambda, const double *omega, int max_iter,
+                   double L, double eta, double tol, const void *f0, void *path, gt_solve_info *info, hipStream_t s) {
+  using C = cx_t<T>;
+  const int R = pl->R;
+  const int64_t nR = pl->ncoef * R;
+  Scratch sc;
+  FistaWork<T> w;
+  std::vector<double> L0;
+  int rc;
+  if ((rc = fista_setup<T>(pl, w, sc, omega, L, eta, L0, s))) return rc;
+  C *zero = nullptr;
+  if (!f0) {
+    if ((rc = sc.get(&zero, nR * sizeof(C)))) return rc;
+    hipLaunchKernelGGL((k_c_fill<T>), dim3(nblk(nR)), dim3(kVecBS), 0, s, nR, zero);
+  }
+  std::vector<double> lam(R);
+  for (int j = 0; j < nlam; ++j) {
+    std::fill(lam.begin(), lam.end(), lambda[j]);
+    const void *start = j == 0 ? (f0 ? f0 : (const void *)zero) : (const void *)((const C *)path + (j - 1) * nR);
+    if ((rc = fista_solve<T>(pl, w, y, lam.data(), omega, max_iter, L0.data(), eta, tol, start,
+                             (C *)path + j * nR, info + (size_t)j * R, s)))
+      return rc;
+  }
   return GT_OK;
 }
 
@@ -857,15 +1074,21 @@ int run_sensitivity(const int64_t *goff, int nterms, int64_t ncoef, int R, const
 
 template int run_sensitivity<float>(const int64_t *, int, int64_t, int, const void *, double *, hipStream_t);
 template int run_sensitivity<double>(const int64_t *, int, int64_t, int, const void *, double *, hipStream_t);
-template int run_lsqr<float>(gt_plan *, const void *, const double *, const void *, int, double, void *, gt_solve_info *,
-                             hipStream_t);
-template int run_lsqr<double>(gt_plan *, const void *, const double *, const void *, int, double, void *,
+template int run_lsqr<float>(gt_plan *, const void *, const double *, const double *, int, double, void *,
+                             gt_solve_info *, hipStream_t);
+template int run_lsqr<double>(gt_plan *, const void *, const double *, const double *, int, double, void *,
                               gt_solve_info *, hipStream_t);
-template int run_fista<float>(gt_plan *, const void *, const double *, const void *, int, double, double, double,
+template int run_fista<float>(gt_plan *, const void *, const double *, const double *, int, double, double, double,
                               void *, gt_solve_info *, hipStream_t);
-template int run_fista<double>(gt_plan *, const void *, const double *, const void *, int, double, double, double,
+template int run_fista<double>(gt_plan *, const void *, const double *, const double *, int, double, double, double,
                                void *, gt_solve_info *, hipStream_t);
+template int run_fista_path<float>(gt_plan *, const void *, int, const double *, const double *, int, double, double,
+                                   double, const void *, void *, gt_solve_info *, hipStream_t);
+template int run_fista_path<double>(gt_plan *, const void *, int, const double *, const double *, int, double, double,
+                                    double, const void *, void *, gt_solve_info *, hipStream_t);
 template int run_norm_estimate<float>(gt_plan *, int, double *, hipStream_t);
 template int run_norm_estimate<double>(gt_plan *, int, double *, hipStream_t);
+template int run_norm_estimate_region<float>(gt_plan *, int, void *, size_t, size_t *, double *, hipStream_t);
+template int run_norm_estimate_region<double>(gt_plan *, int, void *, size_t, size_t *, double *, hipStream_t);
 
 }  // namespace gt

@@ -28,6 +28,8 @@ EXPORTS = [
     "gt_plan_create", "gt_plan_destroy", "gt_plan_trafo", "gt_plan_adjoint", "gt_plan_node_grad",
     "gt_plan_order_info", "gt_plan_gather_path", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
     "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
+    "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
+    "gt_debug_alloc_count",
 ]
 
 
@@ -91,6 +93,13 @@ def load(path: str = LIB_PATH):
         "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
         "fista_group_lasso": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp,
                                         C.POINTER(GtSolveInfo), vp]),
+        "fista_group_lasso_path": (C.c_int, [P, vp, vp, i32, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp, vp,
+                                             C.POINTER(GtSolveInfo), vp]),
+        "gt_plan_lsqr": (C.c_int, [vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
+        "gt_plan_fista": (C.c_int, [vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp, C.POINTER(GtSolveInfo), vp]),
+        "gt_release_all": (C.c_int, []),
+        "gt_debug_fail_alloc": (C.c_int, [i64]),
+        "gt_debug_alloc_count": (i64, []),
         "gt_last_error": (C.c_char_p, []),
         "gt_prof_enable": (C.c_int, [i32]),
         "gt_prof_report": (i64, [C.c_char_p, i64]),
@@ -207,21 +216,60 @@ def grouped_adjoint(problem, x, y, fhat, stream=None):
     _check(load().grouped_adjoint(C.byref(problem), _ptr(x), _ptr(y), _ptr(fhat), _stream(stream)))
 
 
+def _omega(omega):
+    """Device pointer of the FP64 weights (None: omega = 1)."""
+    if omega is None:
+        return None
+    import torch
+    if omega.dtype != torch.float64:
+        raise TypeError("omega must be a float64 device tensor (the weights are FP64 on both paths)")
+    return _ptr(omega)
+
+
+def _lam(lambdas):
+    return np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+
+
 def lsqr_solve(problem, x, y, lambdas, omega, max_iter, tol, fhat, stream=None):
-    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    lam = _lam(lambdas)
     info = (GtSolveInfo * problem.R)()
     _check(load().lsqr_solve(C.byref(problem), _ptr(x), _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
-                             _ptr(omega), int(max_iter), float(tol), _ptr(fhat), info, _stream(stream)))
+                             _omega(omega), int(max_iter), float(tol), _ptr(fhat), info, _stream(stream)))
     return list(info)
 
 
 def fista_group_lasso(problem, x, y, lambdas, omega, max_iter, L, eta, tol, fhat, stream=None):
-    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    lam = _lam(lambdas)
     info = (GtSolveInfo * problem.R)()
     _check(load().fista_group_lasso(C.byref(problem), _ptr(x), _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
-                                    _ptr(omega), int(max_iter), float(L), float(eta), float(tol), _ptr(fhat),
+                                    _omega(omega), int(max_iter), float(L), float(eta), float(tol), _ptr(fhat),
                                     info, _stream(stream)))
     return list(info)
+
+
+def fista_group_lasso_path(problem, x, y, lambdas, omega, max_iter, L, eta, tol, fhat0, fhat_path, stream=None):
+    """Warm-started path: returns info as a list of len(lambdas) lists of R entries."""
+    lam = _lam(lambdas)
+    K, R = len(lam), problem.R
+    info = (GtSolveInfo * (K * R))()
+    _check(load().fista_group_lasso_path(C.byref(problem), _ptr(x), _ptr(y), int(K),
+                                         lam.ctypes.data_as(C.POINTER(C.c_double)), _omega(omega), int(max_iter),
+                                         float(L), float(eta), float(tol), _ptr(fhat0), _ptr(fhat_path), info,
+                                         _stream(stream)))
+    return [list(info[j * R:(j + 1) * R]) for j in range(K)]
+
+
+def release_all():
+    _check(load().gt_release_all())
+
+
+def debug_fail_alloc(k: int):
+    """Arm the allocation-failure hook: the k-th device allocation from now fails (0: off)."""
+    _check(load().gt_debug_fail_alloc(int(k)))
+
+
+def debug_alloc_count() -> int:
+    return int(load().gt_debug_alloc_count())
 
 
 # ---------------------------------------------------------------- plans
@@ -249,6 +297,21 @@ class Plan:
         m, n = C.c_int32(), C.c_int32()
         _check(self._lib.gt_plan_order_info(self.handle, int(t), C.byref(m), C.byref(n)))
         return int(m.value), int(n.value)
+
+    def lsqr(self, y, lambdas, omega, max_iter, tol, fhat, stream=None):
+        lam = _lam(lambdas)
+        info = (GtSolveInfo * self.problem.R)()
+        _check(self._lib.gt_plan_lsqr(self.handle, _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                      _omega(omega), int(max_iter), float(tol), _ptr(fhat), info, _stream(stream)))
+        return list(info)
+
+    def fista(self, y, lambdas, omega, max_iter, L, eta, tol, fhat, stream=None):
+        lam = _lam(lambdas)
+        info = (GtSolveInfo * self.problem.R)()
+        _check(self._lib.gt_plan_fista(self.handle, _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                       _omega(omega), int(max_iter), float(L), float(eta), float(tol), _ptr(fhat),
+                                       info, _stream(stream)))
+        return list(info)
 
     def norm_estimate(self, iters=50, stream=None) -> float:
         out = C.c_double()

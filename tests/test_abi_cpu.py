@@ -87,3 +87,32 @@ def test_active_set_matches_oracle(masked):
     want = osens.active_set(sub, rho, eps)
     assert np.array_equal(got, want)
     assert na == int(want.sum())
+
+
+def test_allocation_failure_hook_and_plan_handles_on_cpu():
+    """Error paths that need no GPU: an armed allocation-failure hook turns the first device
+    allocation of a plan into GT_ENOMEM before anything reaches the device; a handle that is
+    not a live plan is rejected without being dereferenced; releasing everything with no live
+    plans is a no-op."""
+    import ctypes as C
+    import numpy as np
+    L = lib.load()
+    x = np.zeros((4, 3))
+    p, keep = lib.make_problem(3, 2, [4, 4], M=4, dtype=lib.GT_C128)
+    h = C.c_void_p()
+    lib.debug_fail_alloc(1)
+    try:
+        rc = L.gt_plan_create(C.byref(p), x.ctypes.data, None, C.byref(h))
+        assert rc == lib.GT_ENOMEM and h.value is None
+        assert "allocation" in L.gt_last_error().decode()
+        assert lib.debug_alloc_count() == 1
+    finally:
+        lib.debug_fail_alloc(0)
+    with pytest.raises(lib.GroupedError) as e:
+        lib.debug_fail_alloc(-1)
+    assert e.value.code == lib.GT_EINVAL
+    bogus = C.c_void_p(0x1000)       # never a plan; must not be dereferenced
+    assert L.gt_plan_destroy(bogus) == lib.GT_EINVAL
+    assert L.gt_plan_trafo(bogus, None, None, None) == lib.GT_EINVAL
+    assert L.gt_plan_destroy(None) == lib.GT_OK
+    assert L.gt_release_all() == lib.GT_OK

@@ -22,7 +22,7 @@ def _lsqr_gpu(d, ds, N, x, y, lambdas, prec, iters, omega=None, tol=0.0):
     iset = oidx.grouped_index_set(d, ds, N)
     p, keep = lib.make_problem(d, ds, N, M=x.shape[0], R=R, dtype=dtype_code(prec))
     out = torch.empty(R * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
-    om = None if omega is None else to_dev(omega.astype(np.float32 if prec == "f32" else np.float64))
+    om = None if omega is None else to_dev(omega.astype(np.float64))
     info = lib.lsqr_solve(p, to_dev(x), to_dev(y), lambdas, om, iters, tol, out)
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(complex).reshape(R, -1), info
@@ -37,7 +37,7 @@ def _fista_gpu(d, ds, N, x, y, lambdas, prec, iters, L, eta=0.0, omega=None, f0=
         out = torch.zeros(R * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
     else:
         out = to_dev(f0.astype(np.complex64 if prec == "f32" else np.complex128).reshape(-1))
-    om = None if omega is None else to_dev(omega.astype(np.float32 if prec == "f32" else np.float64))
+    om = None if omega is None else to_dev(omega.astype(np.float64))
     info = lib.fista_group_lasso(p, to_dev(x), to_dev(y), lambdas, om, iters, L, eta, tol, out)
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(complex).reshape(R, -1), info
@@ -249,3 +249,148 @@ def test_fp32_solvers_on_cell_and_polynomial_gathers():
         e = rel(fgf[r], ref.fhat)
         say(f"  fista lambda={lam} rel {e:.3e}")
         assert e <= 1e-5
+
+
+def test_fista_path_with_backtracking_matches_oracle_fp64():
+    """The warm-started path in one call (one plan), Algorithm algo:fista with backtracking
+    from a small L_0 (eta = 2) and Sobolev weights (s = 1.5, the prox's bisection + Newton
+    root for xi): every stage against the oracle's path, each stage from the previous
+    solution with t_1 = 1 and L_0 restarted."""
+    import torch
+    d, ds, N, M, iset, x, y = _fista_case("f64", seed=38)
+    omega = _sobolev(iset, 1.5)
+    lams = [400.0, 120.0, 40.0]
+    L0, K = 50.0, 25
+    p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C128)
+    path = torch.zeros(len(lams) * iset.n_coeffs, dtype=torch.complex128, device="cuda")
+    infos = lib.fista_group_lasso_path(p, to_dev(x), to_dev(y), lams, to_dev(omega), K, L0, 2.0, 0.0, None, path)
+    got = path.cpu().numpy().reshape(len(lams), -1)
+    prev = None
+    for j, lam in enumerate(lams):
+        ref = ofista.fista(lambda v: otr.forward(iset, x, v), lambda q: otr.adjoint(iset, x, q), y, iset.offsets,
+                           lam, L0, K, f0=prev, omega=omega, eta=2.0)
+        e = rel(got[j], ref.fhat)
+        say(f"[fista path] stage {j} lambda={lam} rel {e:.3e} L gpu {infos[j][0].L} oracle {ref.L} "
+            f"backtracks {ref.backtracks} iters {infos[j][0].iters}")
+        assert ref.backtracks > 0
+        assert abs(infos[j][0].L - ref.L) <= 1e-12 * ref.L
+        assert infos[j][0].iters == K and not infos[j][0].flags & lib.GT_SOLVE_BACKTRACK_CAP
+        assert e <= 1e-10
+        prev = ref.fhat
+
+
+def test_fista_backtrack_cap_flags_only_the_capped_side():
+    """Two right-hand sides in one call: lambda above lambda_max keeps f = 0, so its test
+    ||F(f - h)||^2 <= L ||f - h||^2 holds at once (0 <= 0); the other starts from a tiny L_0
+    with eta = 1.01, so 30 increases cannot reach a passing L.  Only the second reports the
+    cap."""
+    d, ds, N, M, iset, x, y = _fista_case("f64", seed=39)
+    g = otr.adjoint(iset, x, y)
+    lmax = max(np.linalg.norm(g[iset.term_slice(i)]) for i in range(iset.n_terms))
+    fg, info = _fista_gpu(d, ds, N, x, np.tile(y, 2).reshape(2, M), [2.0 * lmax, 0.01 * lmax], "f64", 3, 1e-6,
+                          eta=1.01)
+    say(f"[fista cap] flags {info[0].flags} {info[1].flags} L {info[0].L} {info[1].L}")
+    assert not info[0].flags & lib.GT_SOLVE_BACKTRACK_CAP
+    assert info[0].L == 1e-6 and np.abs(fg[0]).max() == 0.0
+    assert info[1].flags & lib.GT_SOLVE_BACKTRACK_CAP
+    assert abs(info[1].L - 1e-6 * 1.01 ** 30) <= 1e-12 * info[1].L
+    assert info[0].iters == info[1].iters == 3
+
+
+def test_lsqr_breakdown_is_flagged_not_an_error():
+    """Only the empty-set term (d_s = 0), M = 4, values exact in binary: samples in the range
+    of F (all ones: beta_1 = 2, u_1 = 1/2, alpha_1 = 2, v_1 = 1) make u_2 = F v_1 - alpha_1 u_1
+    exactly zero (beta_2 = 0) after one step, and the solution is their mean 1; samples
+    orthogonal to the range (alternating signs) make alpha_1 = 0 at once, and the solution
+    stays zero.  Both report GT_SOLVE_BREAKDOWN."""
+    import torch
+    x = np.zeros((4, 2))
+    for y, want in ((np.ones(4, complex), 1.0), (np.array([1.0, -1.0, 1.0, -1.0], complex), 0.0)):
+        p, keep = lib.make_problem(2, 0, [], M=4, R=1, dtype=lib.GT_C128)
+        out = torch.empty(1, dtype=torch.complex128, device="cuda")
+        info = lib.lsqr_solve(p, to_dev(x), to_dev(y), [0.0], None, 10, 0.0, out)
+        got = out.cpu().numpy()[0]
+        say(f"[lsqr breakdown] fhat {got} iters {info[0].iters} flags {info[0].flags}")
+        assert info[0].flags & lib.GT_SOLVE_BREAKDOWN
+        assert abs(got - want) <= 1e-15 * max(1.0, abs(want))
+        assert info[0].iters <= 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_plan_solvers_match_one_shot_calls(prec):
+    """gt_plan_lsqr / gt_plan_fista on one plan give the one-shot calls' results, twice in a
+    row on the same plan (the plan's buffers carry no state between calls)."""
+    import torch
+    d, ds, N, M, iset, x, y = _fista_case(prec, seed=40)
+    lams = [0.5, 50.0]
+    R = len(lams)
+    yy = np.tile(y, R).reshape(R, M)
+    ref_l, _ = _lsqr_gpu(d, ds, N, x, yy, lams, prec, 15)
+    ref_f, _ = _fista_gpu(d, ds, N, x, yy, [300.0, 3000.0], prec, 20, 0.0)
+    p, keep = lib.make_problem(d, ds, N, M=M, R=R, dtype=dtype_code(prec))
+    plan = lib.Plan(p, to_dev(x), keepalive=keep)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for call in range(2):
+        out = torch.empty(R * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
+        plan.lsqr(to_dev(yy), lams, None, 15, 0.0, out)
+        e1 = rel(out.cpu().numpy().reshape(R, -1), ref_l)
+        outf = torch.zeros(R * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
+        plan.fista(to_dev(yy), [300.0, 3000.0], None, 20, 0.0, 1.0, 0.0, outf)
+        e2 = rel(outf.cpu().numpy().reshape(R, -1), ref_f)
+        say(f"[plan solvers] {prec} call {call}: lsqr {e1:.2e} fista {e2:.2e}")
+        assert e1 <= tol and e2 <= tol
+    plan.close()
+
+
+def test_released_and_destroyed_plans_are_rejected():
+    import torch
+    d, ds, N, M = 3, 2, (6, 4), 200
+    x = W.uniform_nodes(W.rng(41, W.P_NODES), M, d, "f64")
+    p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C128)
+    n = lib.gt_num_coeffs(d, ds, N)
+    fh = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    f = torch.zeros(M, dtype=torch.complex128, device="cuda")
+    a = lib.Plan(p, to_dev(x), keepalive=keep)
+    b = lib.Plan(p, to_dev(x), keepalive=keep)
+    a.trafo(fh, f)
+    lib.release_all()
+    for pl in (a, b):
+        with pytest.raises(lib.GroupedError) as e:
+            pl.trafo(fh, f)
+        assert e.value.code == lib.GT_EINVAL
+        assert lib.load().gt_plan_destroy(pl.handle) == lib.GT_EINVAL
+        pl.handle = None
+    c = lib.Plan(p, to_dev(x), keepalive=keep)     # the library still works afterwards
+    c.trafo(fh, f)
+    c.close()
+    torch.cuda.synchronize()
+
+
+def test_allocation_failures_are_reported_and_leave_the_library_usable():
+    """Every device allocation of a plan creation and of an LSQR call, failed in turn through
+    the allocation-failure hook, gives GT_ENOMEM; afterwards the same calls succeed and
+    match the result obtained before."""
+    import torch
+    d, ds, N, M = 3, 2, (6, 4), 500
+    iset = oidx.grouped_index_set(d, ds, N)
+    x, _, yy = W.trafo_inputs(42, d, ds, M, iset.n_coeffs, 1, "f64")
+    xd, yd = to_dev(x), to_dev(yy[0])
+    p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C128)
+    out = torch.empty(iset.n_coeffs, dtype=torch.complex128, device="cuda")
+    lib.debug_fail_alloc(0)
+    lib.lsqr_solve(p, xd, yd, [0.1], None, 5, 0.0, out)
+    ref = out.cpu().numpy()
+    nalloc = lib.debug_alloc_count()
+    say(f"[alloc hook] an LSQR call makes {nalloc} device allocations")
+    assert nalloc >= 10
+    try:
+        for k in range(1, nalloc + 1):
+            lib.debug_fail_alloc(k)
+            with pytest.raises(lib.GroupedError) as e:
+                lib.lsqr_solve(p, xd, yd, [0.1], None, 5, 0.0, out)
+            assert e.value.code == lib.GT_ENOMEM, (k, e.value)
+    finally:
+        lib.debug_fail_alloc(0)
+    torch.cuda.synchronize()
+    lib.lsqr_solve(p, xd, yd, [0.1], None, 5, 0.0, out)
+    assert rel(out.cpu().numpy(), ref) <= 1e-13
