@@ -250,6 +250,18 @@ int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *strea
  * destroyed plan.  Synchronises the released plans' streams. */
 int gt_release_all(void);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation): gt_plan_norm_estimate with every work buffer in a
+ * fixed 16 MiB device array that the library holds per device for the life of the process,
+ * instead of per-call allocations.  It allocates nothing, device or host.
+ *   plan, iters, out, stream: as for gt_plan_norm_estimate (synchronises `stream`).
+ *   The work buffers take 2 R |I| + R M complex values plus a few partial sums; a plan whose
+ *   buffers exceed 16 MiB gives GT_EINVAL (the message states both sizes) without running.
+ *   Every call on one device shares the array and leaves its contents behind (each call
+ *   initialises what it reads); calls that overlap on one device, from any stream or thread,
+ *   race and must not be made. */
+int gt_plan_norm_estimate_noalloc(gt_plan *plan, int32_t iters, double *out, void *stream);
+
 /* ------------------------------------------------------------------ diagnostics
  * gt_last_error: thread-local message of the last failing call ("" if none).
  * gt_prof_enable(1): record HIP events around every kernel launch (same stream);

@@ -220,6 +220,11 @@ template <typename T> int run_fista_path(gt_plan *pl, const void *y, int nlam, c
                                          const double *omega, int max_iter, double L, double eta, double tol,
                                          const void *f0, void *path, gt_solve_info *info, hipStream_t s);
 template <typename T> int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s);
+// gt_plan_norm_estimate_noalloc: the estimate with its work buffers in the fixed device array
+// (kNoAllocScratchBytes per device, looked up once per device).
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+int run_norm_estimate_noalloc(gt_plan *pl, int iters, double *out, hipStream_t s);
 template <typename T> int run_norm_estimate_region(gt_plan *pl, int iters, void *region, size_t cap, size_t *need,
                                                    double *out, hipStream_t s);
 

@@ -1083,6 +1083,13 @@ int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *strea
                                : run_norm_estimate<double>(plan, iters, out, (hipStream_t)stream);
 }
 
+int gt_plan_norm_estimate_noalloc(gt_plan *plan, int32_t iters, double *out, void *stream) {
+  GT_LIVE(plan);
+  if (!out || iters < 1) return fail(GT_EINVAL, "invalid argument");
+  plan->stream = (hipStream_t)stream;
+  return run_norm_estimate_noalloc(plan, iters, out, (hipStream_t)stream);
+}
+
 int grouped_trafo(const gt_problem *p, const void *x, const void *fhat, void *f, void *stream) {
   gt_plan *pl = nullptr;
   int rc = build_plan(p, x, (hipStream_t)stream, &pl);

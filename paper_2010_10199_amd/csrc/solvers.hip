@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "gt_internal.h"
@@ -760,8 +762,9 @@ struct PowerBuf {
   }
 };
 
+// est_host receives the first ncopy right-hand sides' estimates (ncopy <= R).
 template <typename T>
-static int power_run(gt_plan *pl, int iters, PowerBuf<T> &b, double *est_host, hipStream_t s) {
+static int power_run(gt_plan *pl, int iters, PowerBuf<T> &b, double *est_host, int ncopy, hipStream_t s) {
   const int R = pl->R;
   const int64_t n = pl->ncoef;
   Norms<T> nm{pl};
@@ -785,7 +788,7 @@ static int power_run(gt_plan *pl, int iters, PowerBuf<T> &b, double *est_host, h
     std::swap(v, wv);
     if ((rc = check("power iteration"))) return rc;
   }
-  GT_HIP(hipMemcpyAsync(est_host, b.dot, R * sizeof(double), hipMemcpyDeviceToHost, s));
+  GT_HIP(hipMemcpyAsync(est_host, b.dot, std::min(ncopy, R) * sizeof(double), hipMemcpyDeviceToHost, s));
   GT_HIP(hipStreamSynchronize(s));
   return GT_OK;
 }
@@ -795,7 +798,7 @@ static int power_iter(gt_plan *pl, int iters, double *est_host, hipStream_t s) {
   Scratch sc;
   PowerBuf<T> b;
   if (int rc = b.get(pl, sc)) return rc;
-  return power_run<T>(pl, iters, b, est_host, s);
+  return power_run<T>(pl, iters, b, est_host, pl->R, s);
 }
 
 template <typename T>
@@ -807,8 +810,8 @@ int run_norm_estimate(gt_plan *pl, int iters, double *out, hipStream_t s) {
   return GT_OK;
 }
 
-// The same estimate with every work buffer carved from a fixed device region (the caller's
-// memory is not touched beyond the plan); region NULL measures: *need = bytes required.
+// The same estimate with every work buffer carved from a fixed device region; region NULL
+// only measures (*need = bytes the buffers take).  Allocates nothing, device or host.
 template <typename T>
 int run_norm_estimate_region(gt_plan *pl, int iters, void *region, size_t cap, size_t *need, double *out,
                              hipStream_t s) {
@@ -819,14 +822,13 @@ int run_norm_estimate_region(gt_plan *pl, int iters, void *region, size_t cap, s
     *need = m.used;
   }
   if (!region) return GT_OK;
-  if (*need > cap) return fail(GT_EINVAL, "problem too large for the fixed scratch region");
+  if (*need > cap)
+    return fail(GT_EINVAL, "the work buffers of this plan (" + std::to_string(*need) +
+                               " bytes) exceed the fixed scratch region (" + std::to_string(cap) + " bytes)");
   Scratch sc(Scratch::Carve, region, cap);
   PowerBuf<T> b;
   if (int rc = b.get(pl, sc)) return rc;
-  std::vector<double> est(pl->R);
-  if (int rc = power_run<T>(pl, iters, b, est.data(), s)) return rc;
-  *out = est[0];
-  return GT_OK;
+  return power_run<T>(pl, iters, b, out, 1, s);
 }
 
 // ================================================================== FISTA
@@ -1070,6 +1072,37 @@ int run_sensitivity(const int64_t *goff, int nterms, int64_t ncoef, int R, const
   hipLaunchKernelGGL(k_term_gsi, dim3(R), dim3(kVecBS), 0, s, nterms, rho);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? GT_OK : hip_fail(e, "sensitivity kernels");
+}
+
+// ---------------------------------------------------------------- allocation-free work region
+// A fixed device array for callers that cannot allocate (gt_plan_norm_estimate_noalloc): every
+// device holds its own copy for the life of the process.  Host code never uses the array's
+// name as an address; the device address comes from hipGetSymbolAddress, once per device,
+// with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+int run_norm_estimate_noalloc(gt_plan *pl, int iters, double *out, hipStream_t s) {
+  int dev = 0;
+  GT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GT_EUNSUPPORTED, "device index beyond the scratch table");
+  void *region = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+      if (!p) return fail(GT_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+      g_scratch_ptr[dev] = p;
+    }
+    region = g_scratch_ptr[dev];
+  }
+  size_t need = 0;
+  return pl->dtype == GT_C64 ? run_norm_estimate_region<float>(pl, iters, region, kNoAllocScratchBytes, &need, out, s)
+                             : run_norm_estimate_region<double>(pl, iters, region, kNoAllocScratchBytes, &need, out, s);
 }
 
 template int run_sensitivity<float>(const int64_t *, int, int64_t, int, const void *, double *, hipStream_t);

@@ -29,7 +29,7 @@ EXPORTS = [
     "gt_plan_order_info", "gt_plan_gather_path", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
     "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
-    "gt_debug_alloc_count",
+    "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc",
 ]
 
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         "gt_plan_order_info": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "gt_plan_gather_path": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "gt_plan_norm_estimate": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
+        "gt_plan_norm_estimate_noalloc": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
         "fista_group_lasso": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp,
                                         C.POINTER(GtSolveInfo), vp]),
@@ -316,6 +317,12 @@ class Plan:
     def norm_estimate(self, iters=50, stream=None) -> float:
         out = C.c_double()
         _check(self._lib.gt_plan_norm_estimate(self.handle, int(iters), C.byref(out), _stream(stream)))
+        return float(out.value)
+
+    def norm_estimate_noalloc(self, iters=50, stream=None) -> float:
+        """gt_plan_norm_estimate with its work buffers in the library's fixed device array."""
+        out = C.c_double()
+        _check(self._lib.gt_plan_norm_estimate_noalloc(self.handle, int(iters), C.byref(out), _stream(stream)))
         return float(out.value)
 
     def gather_path(self, t: int) -> int:
