@@ -228,6 +228,203 @@ def run_solvers():
     return out
 
 
+# batched-LSQR workload: d = 20, d_s = 3, N = 32 / 12 / 6 (1,351 terms, 166,111 coefficients),
+# M = 500,000 uniform nodes, 16 lambda values
+CD, CDS, CN, CM, CR = 20, 3, (32, 12, 6), 500000, 16
+C3_FP64_TIMED = (0, 5, 10, 15)       # lambda indices whose FP64-plain solves are timed by default
+
+
+def run_c3(steps: int, all_lambdas: bool):
+    """The batched-LSQR workload (Sec. 4.1, eq. new_min_prob): d = 20, d_s = 3, N = 32/12/6,
+    M = 500,000 uniform nodes, FP32 bulk arithmetic.
+
+    1. Transform throughput with 16 right-hand sides in one launch (the batch the solver's
+       lambda values make when each carries its own samples): forward + adjoint on a plan
+       built once, node-terms/s = 2 M |U| R / t, per-kernel times from a pass with an event
+       pair per launch, and the roofline of the dominant kernel.
+    2. Time to accuracy TAU of LSQR for y = 8 random low-order trigonometric monomials + 1 %
+       noise and lambda = logspace(-4, 1, 16):
+       * reference: FP64, all 16 lambda in one lsqr_solve_path call (shared bidiagonalisation),
+         run to a normal-equation residual of 1e-12 relative to its start;
+       * FP32 batched: all 16 lambda in one FP32 lsqr_solve_path call at the smallest K with
+         every lambda within TAU (relative l2) of the reference;
+       * FP64 plain: one FP64 gt_plan_lsqr call per lambda at that lambda's smallest K (found
+         off the clock with FP64 path runs, whose iterates are the plain runs' iterates);
+         by default the lambda values C3_FP64_TIMED are timed (all 16 with all_lambdas).
+       Plans are built off the clock (their creation time is reported separately); each timed
+       call is the library call's wall time (launches + one synchronisation)."""
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    ncoef = lib.gt_num_coeffs(CD, CDS, CN)
+    nterms = lib.gt_num_terms(CD, CDS)
+    x32 = W.uniform_nodes(W.rng(3, W.P_NODES), CM, CD, "f32")
+    out = {"workload": f"batched-lsqr-d20: d={CD}, d_s={CDS}, N={'/'.join(map(str, CN))}, {nterms} terms, "
+                       f"{ncoef} coefficients, M={CM} uniform nodes"}
+    # ---- 1. transform, R = 16
+    x_d = torch.from_numpy(x32).cuda()
+    fh, y0 = W.complex_normal(W.rng(3, W.P_COEFFS), (CR, ncoef), "f32"), W.complex_normal(W.rng(3, W.P_SAMPLES),
+                                                                                          (CR, CM), "f32")
+    fd, yd = torch.from_numpy(fh.reshape(-1)).cuda(), torch.from_numpy(y0.reshape(-1)).cuda()
+    f_out = torch.empty(CR * CM, dtype=torch.complex64, device="cuda")
+    a_out = torch.empty(CR * ncoef, dtype=torch.complex64, device="cuda")
+    p, keep = lib.make_problem(CD, CDS, CN, M=CM, R=CR, dtype=lib.GT_C64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = lib.Plan(p, x_d, keepalive=keep)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    plan.trafo(fd, f_out)
+    plan.adjoint(yd, a_out)
+
+    def timed(fwd, adj):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            if fwd:
+                plan.trafo(fd, f_out)
+            if adj:
+                plan.adjoint(yd, a_out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    ms, ms_f, ms_a = timed(True, True), timed(True, False), timed(False, True)
+    lib.prof_enable(True)
+    plan.trafo(fd, f_out)
+    plan.adjoint(yd, a_out)
+    kern = lib.prof_report()
+    lib.prof_enable(False)
+    m3 = plan.order_info(3)[0]
+    plan.close()
+    del f_out, a_out, fd, yd
+    nt = CM * nterms * CR          # node-terms per transform
+    name, (cnt, tot) = max(kern.items(), key=lambda kv: kv[1][1])
+    order = 2 if "2d" in name else (1 if "1d" in name else 3)
+    from math import comb
+    fl = CM * comb(CD, order) * CR * flops_per_node_term(order, m3)
+    out["transform"] = {
+        "R": CR, "m": m3, "plan_s": plan_s, "steps": steps,
+        "fwd_adj": {"value": 2 * nt / (ms * 1e-3), "unit": "node-terms/s", "ms": ms},
+        "forward": {"value": nt / (ms_f * 1e-3), "unit": "node-terms/s", "ms": ms_f},
+        "adjoint": {"value": nt / (ms_a * 1e-3), "unit": "node-terms/s", "ms": ms_a},
+        "kernels_ms": {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in sorted(kern.items())},
+        "roofline": {"bound": "alu", "kernel": name, "achieved": fl / (tot / cnt * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl / (tot / cnt * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, "flops_per_launch": fl,
+                     "avg_launch_ms": tot / cnt}}
+    print(f"[bench]   c3 transform R={CR}: {ms:.1f} ms per fwd+adj ({2 * nt / (ms * 1e-3):.3e} node-terms/s)",
+          file=sys.stderr, flush=True)
+    # ---- 2. LSQR time to accuracy
+    target, _ = W.sparse_trig_target(3, x32, CN)
+    y = W.add_noise(W.rng(3, W.P_NOISE), target, 0.01).astype(np.complex64)
+    lams = np.logspace(-4, 1, CR)
+    y32, y64 = torch.from_numpy(y).cuda(), torch.from_numpy(y.astype(np.complex128)).cuda()
+    x64 = torch.from_numpy(x32.astype(np.float64)).cuda()
+    plans = {}
+    for prec, xd_ in (("f32", x_d), ("f64", x64)):
+        pp, kk = lib.make_problem(CD, CDS, CN, M=CM, R=1, dtype=lib.GT_C64 if prec == "f32" else lib.GT_C128)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans[prec] = (lib.Plan(pp, xd_, keepalive=kk), time.perf_counter() - t0)
+    cdt = {"f32": torch.complex64, "f64": torch.complex128}
+
+    def path_run(prec, K, tol=0.0):
+        buf = torch.empty(CR * ncoef, dtype=cdt[prec], device="cuda")
+        info = plans[prec][0].lsqr_path(y32 if prec == "f32" else y64, lams, None, K, tol, buf)
+        return buf.cpu().numpy().astype(np.complex128).reshape(CR, ncoef), info
+
+    t0 = time.perf_counter()
+    ref, rinfo = path_run("f64", 400, 1e-12)
+    ref_s = time.perf_counter() - t0
+    ref_norm = np.linalg.norm(ref, axis=1)
+
+    def errs(sol):
+        return np.linalg.norm(sol - ref, axis=1) / ref_norm
+
+    cache = {}
+
+    def errs_at(prec, K):
+        if (prec, K) not in cache:
+            cache[(prec, K)] = errs(path_run(prec, K)[0])
+            print(f"[bench]   c3 lsqr {prec} K={K}: max err {cache[(prec, K)].max():.2e}", file=sys.stderr,
+                  flush=True)
+        return cache[(prec, K)]
+
+    def smallest_k(prec, j=None, guess=None):
+        """Smallest K whose error is within TAU (for lambda j, or for all).  Without a guess:
+        doubling from 8, then bisection; with one: steps of one from the guess (the error
+        falls monotonically in K here)."""
+        sel = (lambda e: e.max()) if j is None else (lambda e: e[j])
+        if guess is not None:
+            K = guess
+            if sel(errs_at(prec, K)) <= TAU:
+                while K > 1 and sel(errs_at(prec, K - 1)) <= TAU:
+                    K -= 1
+                return K
+            while sel(errs_at(prec, K)) > TAU:
+                K += 1
+                if K > 256:
+                    return None
+            return K
+        lo, hi = 0, 8
+        while sel(errs_at(prec, hi)) > TAU:
+            lo, hi = hi, 2 * hi
+            if hi > 256:
+                return None
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if sel(errs_at(prec, mid)) <= TAU:
+                hi = mid
+            else:
+                lo = mid
+        return hi
+
+    k32 = smallest_k("f32")
+    timed_idx = list(range(CR)) if all_lambdas else list(C3_FP64_TIMED)
+    # FP64 plain: one search per lambda, started from the FP32 count (path runs give every
+    # lambda's error at once, so the searches share their runs)
+    k64 = {j: smallest_k("f64", j, guess=k32) for j in timed_idx}
+    # on the clock
+    buf32 = torch.empty(CR * ncoef, dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans["f32"][0].lsqr_path(y32, lams, None, k32, 0.0, buf32)
+    t32 = time.perf_counter() - t0
+    e32 = errs(buf32.cpu().numpy().astype(np.complex128).reshape(CR, ncoef))
+    buf64 = torch.empty(ncoef, dtype=torch.complex128, device="cuda")
+    t64, e64 = 0.0, []
+    for j in timed_idx:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans["f64"][0].lsqr(y64, [float(lams[j])], None, k64[j], 0.0, buf64)
+        t64 += time.perf_counter() - t0
+        sol = buf64.cpu().numpy().astype(np.complex128)
+        e64.append(float(np.linalg.norm(sol - ref[j]) / ref_norm[j]))
+    for pl_, _ in plans.values():
+        pl_.close()
+    out["lsqr"] = {
+        "lambdas": [float(v) for v in lams], "tau": TAU,
+        "reference": {"form": "FP64, all 16 lambda in one lsqr_solve_path call (m = 8)",
+                      "iters": int(max(i[0].iters for i in rinfo)), "tol": 1e-12, "s": ref_s,
+                      "converged": all(bool(i[0].flags & lib.GT_SOLVE_CONVERGED) for i in rinfo)},
+        "fp32_batched": {"form": "FP32, 16 lambda in one call, one shared bidiagonalisation", "iters": k32,
+                         "s": t32, "max_rel_err": float(e32.max()), "plan_s": plans["f32"][1]},
+        "fp64_plain": {"form": "FP64, one gt_plan_lsqr call per lambda", "lambdas_timed": timed_idx,
+                       "iters_per_lambda": [k64[j] for j in timed_idx], "s": t64, "max_rel_err": max(e64),
+                       "plan_s": plans["f64"][1]},
+        "speedup": (t64 / len(timed_idx) * CR) / t32,
+        "speedup_measured_only": t64 / t32,
+        "note": ("speedup: FP64-plain time per lambda (timed lambda values) x 16 over the FP32 batched call; "
+                 "speedup_measured_only: the timed FP64-plain calls (a subset unless all lambda are timed) "
+                 "over the FP32 call for all 16, a lower bound without extrapolation")}
+    print(f"[bench]   c3 lsqr: fp32 batched K={k32} {t32:.2f} s; fp64 plain {t64:.2f} s over {len(timed_idx)} lambda",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def run_active_set():
     """The pipeline of Sec. 4.1 on the solver workload (B-spline target with 3 one- and 2
     two-dimensional terms, 1 % noise), FP32: LSQR fit on U_2, global sensitivity indices
@@ -570,6 +767,10 @@ def main():
     ap.add_argument("--no-solvers", action="store_true", help="skip the FP32-batched vs FP64 solver timing")
     ap.add_argument("--draws", type=int, default=1,
                     help="node draws of the test-function experiments (the paper averages 100); means are reported")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched-LSQR workload (d=20, M=500,000)")
+    ap.add_argument("--c3-steps", type=int, default=3, help="timed forward + adjoint steps of the d=20 workload")
+    ap.add_argument("--c3-all-lambdas", action="store_true",
+                    help="time the FP64-plain solve of all 16 lambda values (default: 4 of them)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -664,6 +865,9 @@ def main():
                     "active_set_is_printed_U*": sum(r[e]["active_set_is_printed_U*"] for r in fruns)} for e in exps}
         print("[bench] autograd", file=sys.stderr, flush=True)
         out["autograd"] = run_autograd()
+    if not args.no_c3:
+        print("[bench] batched-lsqr workload (d=20)", file=sys.stderr, flush=True)
+        out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas)
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -178,6 +178,22 @@ int lsqr_solve(const gt_problem *p, const void *x, const void *y, const double *
                const double *omega, int32_t max_iter, double tol, void *fhat,
                gt_solve_info *info, void *stream);
 
+/* lsqr_solve_path: eq. new_min_prob for nlambda values of lambda on each of the R right-hand
+ * sides at once (the lambda sweep of the paper's experiments, Sec. 4.1).  The Golub-Kahan
+ * bidiagonalisation of A = F W^{-1/2} started from y does not depend on lambda, which enters
+ * LSQR only through one extra plane rotation per step, so all lambda values of a right-hand
+ * side share one forward and one adjoint transform per iteration: the result for each
+ * (lambda[j], r) is the iterate a separate lsqr_solve call with that lambda computes.
+ *   lambda    host, nlambda doubles >= 0
+ *   fhat_path device, complex, nlambda x R x |I| (output, lambda-major)
+ *   info      host, nlambda x R entries (output)
+ *   tol > 0: stop when every (lambda, r) has resid <= tol * resid_0 (checked every 8
+ *   iterations); tol <= 0: exactly max_iter iterations.
+ * Other arguments as for lsqr_solve.  Synchronises `stream`. */
+int lsqr_solve_path(const gt_problem *p, const void *x, const void *y, int32_t nlambda,
+                    const double *lambda, const double *omega, int32_t max_iter, double tol,
+                    void *fhat_path, gt_solve_info *info, void *stream);
+
 /* fista_group_lasso: R group-lasso problems (eq. alligatoah), lambda[r] > 0, every ANOVA
  * term (the empty set included) one group, Algorithm algo:fista from fhat (in: start
  * f_0, out: f_K).
@@ -221,6 +237,9 @@ int gt_plan_lsqr(gt_plan *plan, const void *y, const double *lambda, const doubl
 int gt_plan_fista(gt_plan *plan, const void *y, const double *lambda, const double *omega,
                   int32_t max_iter, double L, double eta, double tol, void *fhat,
                   gt_solve_info *info, void *stream);
+int gt_plan_lsqr_path(gt_plan *plan, const void *y, int32_t nlambda, const double *lambda,
+                      const double *omega, int32_t max_iter, double tol, void *fhat_path,
+                      gt_solve_info *info, void *stream);
 
 /* ------------------------------------------------------------------ sensitivity analysis
  * gt_sensitivity: global sensitivity indices (eq. gsi) of the approximation with

@@ -213,6 +213,9 @@ template <typename T> int run_sensitivity(const int64_t *goff, int nterms, int64
                                           double *rho, hipStream_t s);
 template <typename T> int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *omega,
                                    int max_iter, double tol, void *fhat, gt_solve_info *info, hipStream_t s);
+template <typename T> int run_lsqr_path(gt_plan *pl, const void *y, int nlam, const double *lambda,
+                                        const double *omega, int max_iter, double tol, void *path,
+                                        gt_solve_info *info, hipStream_t s);
 template <typename T> int run_fista(gt_plan *pl, const void *y, const double *lambda, const double *omega,
                                     int max_iter, double L, double eta, double tol, void *fhat,
                                     gt_solve_info *info, hipStream_t s);

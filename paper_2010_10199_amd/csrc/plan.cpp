@@ -1172,6 +1172,35 @@ int fista_group_lasso(const gt_problem *p, const void *x, const void *y, const d
   return rc;
 }
 
+int gt_plan_lsqr_path(gt_plan *plan, const void *y, int32_t nlambda, const double *lambda, const double *omega,
+                      int32_t max_iter, double tol, void *fhat_path, gt_solve_info *info, void *stream) {
+  GT_LIVE(plan);
+  if (!y || !lambda || !fhat_path || !info) return fail(GT_EINVAL, "NULL argument");
+  if (nlambda < 1) return fail(GT_EINVAL, "nlambda must be >= 1");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (int rc = check_lambda(nlambda, lambda, false)) return rc;
+  plan->stream = (hipStream_t)stream;
+  return plan->dtype == GT_C64
+             ? run_lsqr_path<float>(plan, y, nlambda, lambda, omega, max_iter, tol, fhat_path, info, (hipStream_t)stream)
+             : run_lsqr_path<double>(plan, y, nlambda, lambda, omega, max_iter, tol, fhat_path, info,
+                                     (hipStream_t)stream);
+}
+
+int lsqr_solve_path(const gt_problem *p, const void *x, const void *y, int32_t nlambda, const double *lambda,
+                    const double *omega, int32_t max_iter, double tol, void *fhat_path, gt_solve_info *info,
+                    void *stream) {
+  if (!y || !lambda || !fhat_path || !info) return fail(GT_EINVAL, "NULL argument");
+  if (nlambda < 1) return fail(GT_EINVAL, "nlambda must be >= 1");
+  if (max_iter < 1) return fail(GT_EINVAL, "max_iter must be >= 1");
+  if (int rc = check_lambda(nlambda, lambda, false)) return rc;
+  gt_plan *pl = nullptr;
+  int rc = build_plan(p, x, (hipStream_t)stream, &pl);
+  if (rc) return rc;
+  rc = gt_plan_lsqr_path(pl, y, nlambda, lambda, omega, max_iter, tol, fhat_path, info, stream);
+  release_plan(pl);
+  return rc;
+}
+
 int fista_group_lasso_path(const gt_problem *p, const void *x, const void *y, int32_t nlambda, const double *lambda,
                            const double *omega, int32_t max_iter, double L, double eta, double tol,
                            const void *fhat0, void *fhat_path, gt_solve_info *info, void *stream) {

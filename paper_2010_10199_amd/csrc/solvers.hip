@@ -200,10 +200,19 @@ struct LsqrState {
   int32_t iters;
 };
 
-__global__ void k_lsqr_init(int R, const double *__restrict__ alpha, const double *__restrict__ beta,
+// State s = j R + r: damping value j (one per right-hand side when each r has its own
+// lambda: J = 1, lambda index r) on right-hand side r, whose bidiagonalisation (alpha_r,
+// beta_r) every j shares: the Golub-Kahan recurrences of A do not involve the damping,
+// which enters only through the extra plane rotation of each step.
+__device__ __forceinline__ double lsqr_lambda(const double *lambda, int s, int R, int path) {
+  return path ? lambda[s / R] : lambda[s];
+}
+
+__global__ void k_lsqr_init(int S, int R, const double *__restrict__ alpha, const double *__restrict__ beta,
                             LsqrState *__restrict__ st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  const int r = i % R;
   LsqrState s{};
   s.alpha = alpha[r];
   s.beta = beta[r];
@@ -213,22 +222,24 @@ __global__ void k_lsqr_init(int R, const double *__restrict__ alpha, const doubl
   s.normal0 = s.normal;
   s.done = (s.alpha == 0.0 || s.beta == 0.0) ? 1 : 0;
   s.iters = 0;
-  st[r] = s;
+  st[i] = s;
 }
 
-__global__ void k_lsqr_step(int R, const double *__restrict__ lambda, const double *__restrict__ alpha,
-                            const double *__restrict__ beta, LsqrState *__restrict__ st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  LsqrState s = st[r];
+__global__ void k_lsqr_step(int S, int R, int path, const double *__restrict__ lambda,
+                            const double *__restrict__ alpha, const double *__restrict__ beta,
+                            LsqrState *__restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  const int r = i % R;
+  LsqrState s = st[i];
   if (s.done) {
     s.cx = 0;
     s.cw = 0;
-    st[r] = s;
+    st[i] = s;
     return;
   }
   const double a = alpha[r], b = beta[r];
-  const double damp = sqrt(2.0 * lambda[r]);
+  const double damp = sqrt(2.0 * lsqr_lambda(lambda, i, R, path));
   const double rhobar1 = hypot(s.rhobar, damp);
   const double c1 = s.rhobar / rhobar1;
   s.phibar = c1 * s.phibar;
@@ -245,23 +256,33 @@ __global__ void k_lsqr_step(int R, const double *__restrict__ lambda, const doub
   s.beta = b;
   s.iters += 1;
   if (a == 0.0 || b == 0.0) s.done = 1;
-  st[r] = s;
+  st[i] = s;
 }
 
+// x_s += cx_s w_s; w_s = v_r + cw_s w_s.  Grid (chunks, S).
 template <typename T>
-__global__ __launch_bounds__(kVecBS) void k_lsqr_xw(int64_t n, const LsqrState *__restrict__ st,
+__global__ __launch_bounds__(kVecBS) void k_lsqr_xw(int64_t n, int R, const LsqrState *__restrict__ st,
                                                     const cx_t<T> *__restrict__ v, cx_t<T> *__restrict__ w,
                                                     cx_t<T> *__restrict__ x) {
-  const int r = blockIdx.y;
-  const double cx = st[r].cx, cw = st[r].cw;
+  const int si = blockIdx.y, r = si % R;
+  const double cx = st[si].cx, cw = st[si].cw;
   if (cx == 0.0 && cw == 0.0) return;
   const int64_t lo = (int64_t)blockIdx.x * kCoefChunk, hi = min(n, lo + kCoefChunk);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kVecBS) {
-    const int64_t k = (int64_t)r * n + i;
-    const cx_t<T> wv = w[k], xv = x[k], vv = v[k];
+    const int64_t k = (int64_t)si * n + i;
+    const cx_t<T> wv = w[k], xv = x[k], vv = v[(int64_t)r * n + i];
     x[k] = mk<T>((T)(xv.x + cx * wv.x), (T)(xv.y + cx * wv.y));
     w[k] = mk<T>((T)(vv.x + cw * wv.x), (T)(vv.y + cw * wv.y));
   }
+}
+
+// w_s = v_r for every state (start of the recurrences).
+template <typename T>
+__global__ __launch_bounds__(kVecBS) void k_lsqr_wstart(int64_t n, int R, const cx_t<T> *__restrict__ v,
+                                                        cx_t<T> *__restrict__ w) {
+  const int si = blockIdx.y, r = si % R;
+  const int64_t lo = (int64_t)blockIdx.x * kCoefChunk, hi = min(n, lo + kCoefChunk);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kVecBS) w[(int64_t)si * n + i] = v[(int64_t)r * n + i];
 }
 
 template <typename T>
@@ -653,11 +674,13 @@ static int weight_scale(const double *omega, int64_t n, Scratch &sc, T **cs, hip
   return GT_OK;
 }
 
+// J damping values per right-hand side (path: lambda[j] for every r, J = nlam; otherwise
+// J = 1 and lambda[r]); x, w and the rotations per state s = j R + r, everything else per r.
 template <typename T>
-int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *omega, int max_iter, double tol, void *fhat,
-             gt_solve_info *info, hipStream_t s) {
+static int lsqr_core(gt_plan *pl, const void *y, int nlam, bool path, const double *lambda, const double *omega,
+                     int max_iter, double tol, void *fhat, gt_solve_info *info, hipStream_t s) {
   using C = cx_t<T>;
-  const int R = pl->R;
+  const int R = pl->R, J = path ? nlam : 1, S = J * R;
   const int64_t V = pl->Vtot, n = pl->ncoef;
   Scratch sc;
   C *u, *v, *w, *x, *tV, *tI;
@@ -666,15 +689,15 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *ome
   T *cs = nullptr;
   int rc;
   if ((rc = sc.get(&u, V * sizeof(C))) || (rc = sc.get(&tV, V * sizeof(C))) || (rc = sc.get(&v, n * R * sizeof(C))) ||
-      (rc = sc.get(&w, n * R * sizeof(C))) || (rc = sc.get(&x, n * R * sizeof(C))) ||
+      (rc = sc.get(&w, n * S * sizeof(C))) || (rc = sc.get(&x, n * S * sizeof(C))) ||
       (rc = sc.get(&tI, n * R * sizeof(C))) || (rc = sc.get(&alpha, R * sizeof(double))) ||
       (rc = sc.get(&beta, R * sizeof(double))) || (rc = sc.get(&ialpha, R * sizeof(double))) ||
-      (rc = sc.get(&ibeta, R * sizeof(double))) || (rc = sc.get(&dlam, R * sizeof(double))) ||
-      (rc = sc.get(&st, R * sizeof(LsqrState))))
+      (rc = sc.get(&ibeta, R * sizeof(double))) || (rc = sc.get(&dlam, (path ? J : R) * sizeof(double))) ||
+      (rc = sc.get(&st, S * sizeof(LsqrState))))
     return rc;
   Norms<T> nm{pl};
   if ((rc = nm.init(sc))) return rc;
-  GT_HIP(hipMemcpyAsync(dlam, lambda, R * sizeof(double), hipMemcpyHostToDevice, s));
+  GT_HIP(hipMemcpyAsync(dlam, lambda, (path ? J : R) * sizeof(double), hipMemcpyHostToDevice, s));
   if (omega && (rc = weight_scale<T>(omega, n, sc, &cs, s))) return rc;
   const unsigned nchunk = (unsigned)nm.nchunk;
   // beta_1 u_1 = y
@@ -684,14 +707,14 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *ome
   if ((rc = launch_adjoint<T>(pl, u, cs, v, s))) return rc;
   if ((rc = nm.c_axpby(v, nullptr, nullptr, nullptr, v, alpha, ialpha, s))) return rc;
   hipLaunchKernelGGL((k_c_scale<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, ialpha, v);
-  hipLaunchKernelGGL((k_copy<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, v, w);
-  hipLaunchKernelGGL((k_c_fill<T>), dim3(nblk(n * R)), dim3(kVecBS), 0, s, n * R, x);
-  hipLaunchKernelGGL(k_lsqr_init, dim3((R + 63) / 64), dim3(64), 0, s, R, alpha, beta, st);
+  hipLaunchKernelGGL((k_lsqr_wstart<T>), dim3(nchunk, S), dim3(kVecBS), 0, s, n, R, (const C *)v, w);
+  hipLaunchKernelGGL((k_c_fill<T>), dim3(nblk(n * S)), dim3(kVecBS), 0, s, n * S, x);
+  hipLaunchKernelGGL(k_lsqr_init, dim3((S + 63) / 64), dim3(64), 0, s, S, R, alpha, beta, st);
   if ((rc = check("lsqr init"))) return rc;
   // -alpha and -beta for the axpby kernels
   double *nalpha, *nbeta;
   if ((rc = sc.get(&nalpha, R * sizeof(double))) || (rc = sc.get(&nbeta, R * sizeof(double)))) return rc;
-  std::vector<LsqrState> hst(R);
+  std::vector<LsqrState> hst(S);
   int it = 0;
   bool converged = false;
   for (it = 1; it <= max_iter; ++it) {
@@ -705,16 +728,18 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *ome
     hipLaunchKernelGGL(k_neg, dim3((R + 63) / 64), dim3(64), 0, s, R, (const double *)beta, nbeta);
     if ((rc = nm.c_axpby(tI, nullptr, v, nbeta, v, alpha, ialpha, s))) return rc;
     hipLaunchKernelGGL((k_c_scale<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, ialpha, v);
-    // rotations, x and w
-    hipLaunchKernelGGL(k_lsqr_step, dim3((R + 63) / 64), dim3(64), 0, s, R, dlam, alpha, beta, st);
-    hipLaunchKernelGGL((k_lsqr_xw<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, st, v, w, x);
+    // rotations, x and w per state
+    hipLaunchKernelGGL(k_lsqr_step, dim3((S + 63) / 64), dim3(64), 0, s, S, R, path ? 1 : 0, (const double *)dlam,
+                       (const double *)alpha, (const double *)beta, st);
+    hipLaunchKernelGGL((k_lsqr_xw<T>), dim3(nchunk, S), dim3(kVecBS), 0, s, n, R, (const LsqrState *)st,
+                       (const C *)v, w, x);
     if ((rc = check("lsqr iteration"))) return rc;
     if (tol > 0 && (it % 8 == 0 || it == max_iter)) {
-      GT_HIP(hipMemcpyAsync(hst.data(), st, R * sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      GT_HIP(hipMemcpyAsync(hst.data(), st, S * sizeof(LsqrState), hipMemcpyDeviceToHost, s));
       GT_HIP(hipStreamSynchronize(s));
       bool all = true;
-      for (int r = 0; r < R; ++r)
-        if (!(hst[r].done || hst[r].normal <= tol * hst[r].normal0)) all = false;
+      for (int q = 0; q < S; ++q)
+        if (!(hst[q].done || hst[q].normal <= tol * hst[q].normal0)) all = false;
       if (all) {
         converged = true;
         break;
@@ -722,22 +747,34 @@ int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *ome
     }
   }
   // fhat = W^{-1/2} x
-  hipLaunchKernelGGL((k_c_mul_colscale<T>), dim3(nchunk, R), dim3(kVecBS), 0, s, n, (const T *)cs, x, (C *)fhat);
+  hipLaunchKernelGGL((k_c_mul_colscale<T>), dim3(nchunk, S), dim3(kVecBS), 0, s, n, (const T *)cs, x, (C *)fhat);
   if ((rc = check("lsqr output"))) return rc;
-  GT_HIP(hipMemcpyAsync(hst.data(), st, R * sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+  GT_HIP(hipMemcpyAsync(hst.data(), st, S * sizeof(LsqrState), hipMemcpyDeviceToHost, s));
   GT_HIP(hipStreamSynchronize(s));
-  for (int r = 0; r < R; ++r) {
-    info[r].iters = hst[r].iters;
-    info[r].resid = hst[r].normal;
-    info[r].t_k = hst[r].phibar;
-    info[r].L = 0;
+  for (int q = 0; q < S; ++q) {
+    info[q].iters = hst[q].iters;
+    info[q].resid = hst[q].normal;
+    info[q].t_k = hst[q].phibar;
+    info[q].L = 0;
     int32_t fl = 0;
-    if (hst[r].done) fl |= GT_SOLVE_BREAKDOWN;
-    if (tol > 0 && (hst[r].done || hst[r].normal <= tol * hst[r].normal0)) fl |= GT_SOLVE_CONVERGED;
+    if (hst[q].done) fl |= GT_SOLVE_BREAKDOWN;
+    if (tol > 0 && (hst[q].done || hst[q].normal <= tol * hst[q].normal0)) fl |= GT_SOLVE_CONVERGED;
     if (!converged && it > max_iter) fl |= GT_SOLVE_MAX_ITER;
-    info[r].flags = fl;
+    info[q].flags = fl;
   }
   return GT_OK;
+}
+
+template <typename T>
+int run_lsqr(gt_plan *pl, const void *y, const double *lambda, const double *omega, int max_iter, double tol, void *fhat,
+             gt_solve_info *info, hipStream_t s) {
+  return lsqr_core<T>(pl, y, 1, false, lambda, omega, max_iter, tol, fhat, info, s);
+}
+
+template <typename T>
+int run_lsqr_path(gt_plan *pl, const void *y, int nlam, const double *lambda, const double *omega, int max_iter,
+                  double tol, void *path, gt_solve_info *info, hipStream_t s) {
+  return lsqr_core<T>(pl, y, nlam, true, lambda, omega, max_iter, tol, path, info, s);
 }
 
 // ================================================================== power iteration
@@ -1111,6 +1148,10 @@ template int run_lsqr<float>(gt_plan *, const void *, const double *, const doub
                              gt_solve_info *, hipStream_t);
 template int run_lsqr<double>(gt_plan *, const void *, const double *, const double *, int, double, void *,
                               gt_solve_info *, hipStream_t);
+template int run_lsqr_path<float>(gt_plan *, const void *, int, const double *, const double *, int, double, void *,
+                                  gt_solve_info *, hipStream_t);
+template int run_lsqr_path<double>(gt_plan *, const void *, int, const double *, const double *, int, double, void *,
+                                   gt_solve_info *, hipStream_t);
 template int run_fista<float>(gt_plan *, const void *, const double *, const double *, int, double, double, double,
                               void *, gt_solve_info *, hipStream_t);
 template int run_fista<double>(gt_plan *, const void *, const double *, const double *, int, double, double, double,

@@ -29,7 +29,7 @@ EXPORTS = [
     "gt_plan_order_info", "gt_plan_gather_path", "lsqr_solve", "fista_group_lasso", "gt_plan_norm_estimate",
     "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
-    "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc",
+    "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc", "lsqr_solve_path", "gt_plan_lsqr_path",
 ]
 
 
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
                                              C.POINTER(GtSolveInfo), vp]),
         "gt_plan_lsqr": (C.c_int, [vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
         "gt_plan_fista": (C.c_int, [vp, vp, C.POINTER(dbl), vp, i32, dbl, dbl, dbl, vp, C.POINTER(GtSolveInfo), vp]),
+        "lsqr_solve_path": (C.c_int, [P, vp, vp, i32, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
+        "gt_plan_lsqr_path": (C.c_int, [vp, vp, i32, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
         "gt_release_all": (C.c_int, []),
         "gt_debug_fail_alloc": (C.c_int, [i64]),
         "gt_debug_alloc_count": (i64, []),
@@ -248,6 +250,18 @@ def fista_group_lasso(problem, x, y, lambdas, omega, max_iter, L, eta, tol, fhat
     return list(info)
 
 
+def lsqr_solve_path(problem, x, y, lambdas, omega, max_iter, tol, fhat_path, stream=None):
+    """All lambda values on each right-hand side with one shared bidiagonalisation; returns
+    info as a list of len(lambdas) lists of R entries."""
+    lam = _lam(lambdas)
+    K, R = len(lam), problem.R
+    info = (GtSolveInfo * (K * R))()
+    _check(load().lsqr_solve_path(C.byref(problem), _ptr(x), _ptr(y), int(K),
+                                  lam.ctypes.data_as(C.POINTER(C.c_double)), _omega(omega), int(max_iter), float(tol),
+                                  _ptr(fhat_path), info, _stream(stream)))
+    return [list(info[j * R:(j + 1) * R]) for j in range(K)]
+
+
 def fista_group_lasso_path(problem, x, y, lambdas, omega, max_iter, L, eta, tol, fhat0, fhat_path, stream=None):
     """Warm-started path: returns info as a list of len(lambdas) lists of R entries."""
     lam = _lam(lambdas)
@@ -305,6 +319,15 @@ class Plan:
         _check(self._lib.gt_plan_lsqr(self.handle, _ptr(y), lam.ctypes.data_as(C.POINTER(C.c_double)),
                                       _omega(omega), int(max_iter), float(tol), _ptr(fhat), info, _stream(stream)))
         return list(info)
+
+    def lsqr_path(self, y, lambdas, omega, max_iter, tol, fhat_path, stream=None):
+        lam = _lam(lambdas)
+        K, R = len(lam), self.problem.R
+        info = (GtSolveInfo * (K * R))()
+        _check(self._lib.gt_plan_lsqr_path(self.handle, _ptr(y), int(K), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                           _omega(omega), int(max_iter), float(tol), _ptr(fhat_path), info,
+                                           _stream(stream)))
+        return [list(info[j * R:(j + 1) * R]) for j in range(K)]
 
     def fista(self, y, lambdas, omega, max_iter, L, eta, tol, fhat, stream=None):
         lam = _lam(lambdas)

@@ -17,6 +17,7 @@ import workloads as W
 from oracle import fista as ofista
 from oracle import index_set as oidx
 from oracle import transform as otr
+from paper_2010_10199_amd import lib
 from tests.gpu_util import (TOL, gpu_adjoint, gpu_trafo, max_err, max_tol, oracle_adjoint_at, oracle_forward_at, rel,
                             say)
 from tests.test_gpu_solvers import _fista_gpu
@@ -125,3 +126,57 @@ def test_config4_fista_reduced_vs_oracle(prec):
         act = sum(np.linalg.norm(ref.fhat[iset.term_slice(i)]) > 0 for i in range(iset.n_terms))
         say(f"[config4 fista] {prec} lambda={lam:.4g} rel {e:.3e} active groups {act}")
         assert e <= (1e-5 if prec == "f32" else 1e-10)
+
+
+@pytest.fixture(scope="module")
+def config3_lsqr_slice():
+    """The batched-LSQR workload's index set (d=20, d_s=3, N=32/12/6: 1,351 groups, 166,111
+    coefficients) on an 800-node slice: the sparse trigonometric target (8 monomials) + 1 %
+    noise, 16 lambda = logspace(-4, 1), and the oracle's 5-iterate LSQR for every lambda
+    (dense matrix of eq. FM as its operator)."""
+    from oracle import lsqr as olsqr
+    d, ds, N = C3
+    M, K = 800, 5
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = W.uniform_nodes(W.rng(3, W.P_NODES, 1), M, d, "f32")
+    target, _ = W.sparse_trig_target(3, x, N)
+    y = W.add_noise(W.rng(3, W.P_NOISE, 1), target, 0.01).astype(np.complex64)
+    lams = np.logspace(-4, 1, 16)
+    A = otr.dense_matrix(iset, x)
+    mv = lambda v: A @ v
+    rmv = lambda u: (u.conj() @ A).conj()
+    ref = np.stack([olsqr.lsqr(mv, rmv, y.astype(np.complex128), iset.n_coeffs, lam, None, K).fhat for lam in lams])
+    del A
+    return d, ds, N, M, K, iset, x, y, lams, ref
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_config3_lsqr_sixteen_lambdas_vs_oracle(config3_lsqr_slice, prec):
+    """All 16 lambda values in one call (lsqr_solve_path: one shared bidiagonalisation) and
+    as 16 right-hand sides with their own lambda (lsqr_solve), against the oracle's iterates
+    for every lambda; the two GPU forms agree with each other."""
+    import torch
+    from tests.gpu_util import cdtype, dtype_code, to_dev
+    d, ds, N, M, K, iset, x, y, lams, ref = config3_lsqr_slice
+    L = len(lams)
+    xd = to_dev(x.astype(np.float32 if prec == "f32" else np.float64))
+    yd = to_dev(y if prec == "f32" else y.astype(np.complex128))
+    p1, k1 = lib.make_problem(d, ds, N, M=M, R=1, dtype=dtype_code(prec))
+    path = torch.empty(L * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
+    info = lib.lsqr_solve_path(p1, xd, yd, lams, None, K, 0.0, path)
+    got_path = path.cpu().numpy().astype(np.complex128).reshape(L, -1)
+    pR, kR = lib.make_problem(d, ds, N, M=M, R=L, dtype=dtype_code(prec))
+    outR = torch.empty(L * iset.n_coeffs, dtype=cdtype(prec), device="cuda")
+    lib.lsqr_solve(pR, xd, yd.repeat(L), lams, None, K, 0.0, outR)
+    got_rhs = outR.cpu().numpy().astype(np.complex128).reshape(L, -1)
+    tol = 1e-5 if prec == "f32" else 1e-10
+    worst = 0.0
+    for j, lam in enumerate(lams):
+        e1, e2 = rel(got_path[j], ref[j]), rel(got_rhs[j], ref[j])
+        worst = max(worst, e1, e2)
+        assert info[j][0].iters == K
+        say(f"[config3 lsqr] {prec} lambda={lam:.3e}: path {e1:.2e} per-rhs {e2:.2e}")
+        assert e1 <= tol and e2 <= tol
+    agree = rel(got_path, got_rhs)
+    say(f"[config3 lsqr] {prec} worst {worst:.2e}; path vs per-rhs {agree:.2e}")
+    assert agree <= (1e-5 if prec == "f32" else 1e-12)
