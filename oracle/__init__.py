@@ -15,6 +15,8 @@ What it computes, each function citing the passage it follows:
   (Definition def:skatoons with eq. somafm), its adjoint (Sec. 3, the stacked adjoint
   after the error remark), the dense d-dimensional Fourier matrix (eq. FM) and the
   analytic node gradient (derivative of the definition; not in the paper).
+* ``cosine``     - the grouped transform in the half-period cosine basis on [0, 1]^d
+  (Sec. 5 with the extension remark of Sec. 3): index set, forward, adjoint, dense matrix.
 * ``lsqr``       - LSQR (Paige & Saunders) for the weighted Tikhonov problem
   (Sec. 4.1, eq. new_min_prob).
 * ``fista``      - group-lasso proximal map (Lemma lemma:lennykrawitz, Theorem
@@ -24,4 +26,4 @@ What it computes, each function citing the passage it follows:
 
 Everything is float64 / complex128.  Parity pins: see ``tests/test_oracle_*.py``.
 """
-from . import index_set, transform, lsqr, fista  # noqa: F401
+from . import index_set, transform, cosine, lsqr, fista  # noqa: F401

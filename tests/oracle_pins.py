@@ -17,6 +17,7 @@ import os
 
 import numpy as np
 
+from oracle import cosine as ocos
 from oracle import fista as ofista
 from oracle import index_set as oidx
 from oracle import lsqr as olsqr
@@ -618,6 +619,103 @@ def pin_testfun_gsi_closed_form() -> float:
     return float(np.max(np.abs(rho - want / (3.0 * (1.0 - P * P)))))
 
 
+# ---------------------------------------------------------------- cosine basis (Sec. 5)
+def _cos_full_frequencies(d, ds, N):
+    """k in N_0^d of the cosine groups, from the ordering rule (independent enumeration)."""
+    K = []
+    for t in range(ds + 1):
+        for u in itertools.combinations(range(d), t):
+            band = list(range(1, N[t - 1])) if t else []
+            for ell in itertools.product(band, repeat=t):
+                k = [0] * d
+                for c, v in zip(u, ell):
+                    k[c] = v
+                K.append(k)
+    return np.array(K, dtype=np.int64)
+
+
+def pin_cos_dense_matrix(seed=51, d=4, ds=3, N=(6, 4, 4), M=31) -> float:
+    """Cosine forward, adjoint and dense matrix against the basis of Sec. 5 evaluated node by
+    node and frequency by frequency with math.cos (k in N_0^d from the ordering rule)."""
+    g = np.random.default_rng(seed)
+    iset = ocos.cosine_index_set(d, ds, N)
+    x = g.random((M, d))
+    K = _cos_full_frequencies(d, ds, N)
+    if not np.array_equal(K, iset.full_frequencies()):
+        return 1.0
+    A = np.array([[math.prod(math.sqrt(2.0) * math.cos(math.pi * kj * xj) if kj else 1.0
+                             for kj, xj in zip(k, xm)) for k in K] for xm in x])
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    return max(rel(ocos.forward(iset, x, fh), A @ fh), rel(ocos.adjoint(iset, x, y), A.T @ y),
+               rel(ocos.dense_matrix(iset, x), A))
+
+
+def pin_cos_dct(d=3, N=6) -> float:
+    """U = P(D), nodes on the tensor grid x_m = (m + 1/2) / N: the groups {1..N-1}^{|u|} over
+    all u partition {0..N-1}^d, and the grouped cosine transform is a d-dimensional DCT:
+    forward = scipy.fft.dctn(type 3) of fhat_k prod_{k_j > 0} 2^{-1/2}; adjoint = dctn(type 2)
+    of the samples times prod_j (1/2 if k_j = 0 else 2^{-1/2})."""
+    import scipy.fft
+    iset = ocos.cosine_index_set(d, d, [N] * d)
+    grid = np.array(list(itertools.product(range(N), repeat=d)))
+    x = (grid + 0.5) / N
+    K = iset.full_frequencies()
+    if len(K) != N ** d:
+        return 1.0
+    g = np.random.default_rng(52)
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    Cc = np.zeros((N,) * d, dtype=complex)
+    for val, k in zip(fh, K):
+        Cc[tuple(k)] = val * 2.0 ** (-0.5 * np.count_nonzero(k))
+    ref = scipy.fft.dctn(Cc.real, type=3) + 1j * scipy.fft.dctn(Cc.imag, type=3)
+    e1 = rel(ocos.forward(iset, x, fh), np.array([ref[tuple(m)] for m in grid]))
+    y = g.standard_normal(len(grid)) + 1j * g.standard_normal(len(grid))
+    Y = np.zeros((N,) * d, dtype=complex)
+    for val, m in zip(y, grid):
+        Y[tuple(m)] = val
+    D = scipy.fft.dctn(Y.real, type=2) + 1j * scipy.fft.dctn(Y.imag, type=2)
+    want = np.array([D[tuple(k)] * np.prod([0.5 if kj == 0 else 2.0 ** -0.5 for kj in k]) for k in K])
+    return max(e1, rel(ocos.adjoint(iset, x, y), want))
+
+
+def pin_cos_orthogonality(d=3, ds=2, N=(8, 4), M=9) -> float:
+    """On the full tensor grid of M > N - 1 half-period points per axis the grouped cosine
+    matrix has orthogonal columns of squared norm M^d (discrete cosine orthogonality,
+    sum_m cos(pi j (2m + 1) / (2M)) = 0 for 0 < j < 2M)."""
+    iset = ocos.cosine_index_set(d, ds, N)
+    x = (np.array(list(itertools.product(range(M), repeat=d))) + 0.5) / M
+    A = ocos.dense_matrix(iset, x)
+    G = A.T @ A
+    return float(np.abs(G - M ** d * np.eye(iset.n_coeffs)).max() / M ** d)
+
+
+def pin_cos_adjoint_identity(seed=53, d=5, ds=3, N=(10, 6, 4), M=40) -> float:
+    g = np.random.default_rng(seed)
+    iset = ocos.cosine_index_set(d, ds, N)
+    x = g.random((M, d))
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    y = g.standard_normal(M) + 1j * g.standard_normal(M)
+    lhs = np.vdot(y, ocos.forward(iset, x, fh))
+    rhs = np.vdot(ocos.adjoint(iset, x, y), fh)
+    return float(abs(lhs - rhs) / (np.linalg.norm(y) * np.linalg.norm(ocos.forward(iset, x, fh))))
+
+
+def pin_cos_even_periodic(seed=54, d=3, ds=3, N=(6, 4, 4), M=25) -> float:
+    """Each basis function is even and 2-periodic in every coordinate: reflecting a node's
+    coordinate (x -> -x) or shifting it by 2 leaves the forward transform unchanged."""
+    g = np.random.default_rng(seed)
+    iset = ocos.cosine_index_set(d, ds, N)
+    x = g.random((M, d))
+    fh = g.standard_normal(iset.n_coeffs) + 1j * g.standard_normal(iset.n_coeffs)
+    f = ocos.forward(iset, x, fh)
+    x2 = x.copy()
+    x2[:, 0] = -x2[:, 0]
+    x2[:, 1] = x2[:, 1] + 2.0
+    x2[:, 2] = 2.0 - x2[:, 2]
+    return rel(ocos.forward(iset, x2, fh), f)
+
+
 PINS = [
     ("printed_counts", pin_printed_counts, {}, 0.0),
     ("ordering", pin_ordering, {}, 0.0),
@@ -662,4 +760,11 @@ PINS = [
     ("testfun_anova", pin_testfun_anova, {}, 1e-15),
     ("l2_error_quadrature", pin_l2_error_quadrature, {}, 1e-10),
     ("testfun_gsi_closed_form", pin_testfun_gsi_closed_form, {}, 1e-5),
+    ("cos_dense_matrix", pin_cos_dense_matrix, {}, 1e-12),
+    ("cos_dct_1d", pin_cos_dct, dict(d=1, N=8), 1e-12),
+    ("cos_dct_2d", pin_cos_dct, dict(d=2, N=6), 1e-12),
+    ("cos_dct_3d", pin_cos_dct, dict(d=3, N=4), 1e-12),
+    ("cos_orthogonality", pin_cos_orthogonality, {}, 1e-12),
+    ("cos_adjoint_identity", pin_cos_adjoint_identity, {}, 1e-12),
+    ("cos_even_periodic", pin_cos_even_periodic, {}, 1e-12),
 ]

@@ -30,6 +30,20 @@ MUTATIONS = [
     ("oracle.transform", "otr", "for a in range(0, x.shape[0], _CHUNK):\n        b = min(x.shape[0], a + _CHUNK)\n        theta",
      "for a in range(0, x.shape[0] - 1, _CHUNK):\n        b = min(x.shape[0] - 1, a + _CHUNK)\n        theta",
      "selected adjoint entries drop the last node"),
+    ("oracle.cosine", "ocos", "out *= np.sqrt(2.0) * np.cos(np.pi * np.outer(xu[:, j], ell[:, j].astype(np.float64)))",
+     "out *= np.cos(np.pi * np.outer(xu[:, j], ell[:, j].astype(np.float64)))", "cosine basis without sqrt(2)"),
+    ("oracle.cosine", "ocos", "out *= np.sqrt(2.0) * np.cos(np.pi * np.outer(xu[:, j], ell[:, j].astype(np.float64)))",
+     "out *= np.sqrt(2.0) * np.cos(2 * np.pi * np.outer(xu[:, j], ell[:, j].astype(np.float64)))",
+     "cosine basis of the full period"),
+    ("oracle.cosine", "ocos", "return list(range(1, N))", "return list(range(0, N - 1))",
+     "cosine group includes frequency 0"),
+    ("oracle.cosine", "ocos", "out[:, sl] = Y.sum(axis=1, keepdims=True)", "out[:, sl] = Y.mean(axis=1, keepdims=True)",
+     "cosine adjoint empty set averaged"),
+    ("oracle.cosine", "ocos", "acc += Y[:, a:b] @ _basis_matrix(x[a:b][:, list(u)], iset.freqs[i])",
+     "acc += Y[:, a:b] @ _basis_matrix(x[a:b][:, list(u)[::-1]], iset.freqs[i])", "cosine adjoint coordinates swapped"),
+    ("oracle.cosine", "ocos", "A *= np.where(kj > 0, np.sqrt(2.0) * np.cos(np.pi * np.outer(x[:, j], kj)), 1.0)",
+     "A *= np.where(kj > 0, np.sqrt(2.0) * np.cos(np.pi * np.outer(x[:, j], kj)), 0.0)",
+     "cosine dense matrix zero on inactive coordinates"),
     ("oracle.index_set", "oidx", "[k for k in range(-N // 2, N // 2) if k != 0]",
      "[k for k in range(-N // 2 + 1, N // 2 + 1) if k != 0]", "band shifted by one"),
     ("oracle.index_set", "oidx", "out.extend(itertools.combinations(range(d), t))",
@@ -79,7 +93,9 @@ def test_mutation_is_caught(monkeypatch, modname, attr, old, new, what):
     mutant = _mutated(modname, old, new)
     monkeypatch.setattr(P, attr, mutant)
     caught = []
-    for name, fn, kw, tol in P.PINS:
+    # pins that use the mutated module first (a pin that does not use it cannot catch it)
+    order = sorted(P.PINS, key=lambda p: (attr + ".") not in inspect.getsource(p[1]))
+    for name, fn, kw, tol in order:
         try:
             err = fn(**kw)
         except Exception:          # a crash also exposes the mistake
