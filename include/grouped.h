@@ -56,6 +56,18 @@ typedef enum {
 } gt_status;
 
 enum { GT_C64 = 1, GT_C128 = 2 };   /* complex float (FP32 path) / complex double (FP64 path) */
+
+/* Basis of the grouped transform (gt_problem.basis).
+ *   GT_BASIS_EXP: e^{2 pi i <k, x>} on the torus, groups of k_j in I_N minus {0} (Sec. 2-3).
+ *   GT_BASIS_COS: the half-period cosine basis on [0, 1]^d of the paper's non-periodic
+ *     variant (Sec. 5; the extension remark after the adjoint display in Sec. 3):
+ *     phi_k(x) = sqrt(2)^{|supp k|} prod_j cos(pi k_j x_j), groups {k : supp k = u,
+ *     1 <= k_j <= N_u - 1}, the same sizes (N_u - 1)^{|u|} and the same order (k_j ascending
+ *     1..N-1 inside a group, last coordinate fastest); the empty set holds k = 0 (phi_0 = 1).
+ *     Nodes are meant in [0, 1]^d; any finite node is taken through the even, 2-periodic
+ *     extension of the basis.  Bandwidths up to 2048.  Every entry point accepts either
+ *     basis; the solvers and sensitivity indices apply unchanged (the basis is orthonormal). */
+enum { GT_BASIS_EXP = 0, GT_BASIS_COS = 1 };
 enum { GT_MAX_ORDER = 3 };          /* largest |u| the GPU path implements */
 
 /* Problem description (Sec. 2-4).  Plain data; copied by every call. */
@@ -76,6 +88,7 @@ typedef struct gt_problem {
                                   order of the unmasked index set: 0 drops the term, whose coefficients are then
                                   absent from every coefficient vector (an index set I_N(U) for a subset U, as the
                                   refit on an active set uses, eq. activeset); the empty set is always kept */
+  int32_t basis;               /* GT_BASIS_EXP (0) or GT_BASIS_COS */
 } gt_problem;
 
 /* Solver report, one entry per right-hand side. */

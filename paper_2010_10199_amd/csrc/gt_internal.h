@@ -147,8 +147,21 @@ inline size_t poly_pack_lds(const OrderHost &o) {
 
 }  // namespace gt
 
+namespace gt {
+struct CosTerm {      // cosine basis, one non-empty term: order, bandwidth, internal/external offsets
+  int32_t t, N;
+  int64_t int_off, ext_off;
+};
+}  // namespace gt
+
 struct gt_plan {
   gt_problem prob{};
+  int basis = GT_BASIS_EXP;           // GT_BASIS_COS: exponential groups of bandwidth 2N at nodes x / 2
+  double node_scale = 1.0;            // node map t = node_scale * x (1/2 for the cosine basis)
+  int64_t ncoef_int = 0;              // coefficients of the exponential index set the kernels run on
+  std::vector<int64_t> ext_off;       // per term: offset in the caller's coefficient vector
+  gt::CosTerm *d_cterms = nullptr;    // cosine basis: per non-empty term order, bandwidth, offsets
+  void *d_gcos = nullptr;             // cosine basis: R x ncoef_int exponential coefficients
   std::vector<int64_t> offs;          // ragged offsets (R+1) or empty
   bool ragged = false;
   int dtype = GT_C64;

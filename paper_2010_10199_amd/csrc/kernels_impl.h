@@ -129,8 +129,9 @@ __device__ __forceinline__ int wrap_start(int fl, int mh, int n) {
 }
 
 // ------------------------------------------------------------------ node preparation
+// (scale: 1, or 1/2 for the cosine basis, whose nodes x map to t = x / 2 on the torus)
 template <typename T>
-__global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T *__restrict__ xT,
+__global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T scale, T *__restrict__ xT,
                                 int32_t *__restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Mtot * d) return;
@@ -141,6 +142,7 @@ __global__ void k_prepare_nodes(const T *__restrict__ x, int64_t Mtot, int d, T 
     atomicOr(flag, 1);
     v = (T)0;
   }
+  v *= scale;   // exact for 1 and 1/2
   if (!(v >= (T)-0.5 && v < (T)0.5)) {   // reduce modulo 1 only when outside [-1/2, 1/2)
     v = v - floor(v + (T)0.5);
     if (v >= (T)0.5 || v < (T)-0.5) v = (T)-0.5;
@@ -884,9 +886,10 @@ __global__ __launch_bounds__(kGatherBS) void k_node_grad(const T *__restrict__ x
 }
 
 // gx[i][c] = sum over orders and over right-hand sides sharing node i of the partials.
+// (scale: d t / d x of the node map, 1/2 for the cosine basis, else 1)
 template <typename T>
 __global__ void k_reduce_gx(const T *__restrict__ gxp, int norders, int64_t Vtot, int64_t Mtot, int R, bool ragged,
-                            int d, T *__restrict__ gx) {
+                            int d, T scale, T *__restrict__ gx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Mtot * d) return;
   const int64_t node = i / d;
@@ -900,7 +903,99 @@ __global__ void k_reduce_gx(const T *__restrict__ gxp, int norders, int64_t Vtot
       for (int r = 0; r < R; ++r) s += base[((int64_t)r * Mtot + node) * d + c];
     }
   }
-  gx[i] = s;
+  gx[i] = scale * s;
+}
+
+// ------------------------------------------------------------------ cosine basis
+// Half-period cosine groups (Sec. 5): phi_k(x) = sqrt(2)^{|u|} prod_{j in u} cos(pi k_j x_j),
+// k_j = 1..N-1.  With t = x / 2, cos(pi k x) = (e^{2 pi i k t} + e^{-2 pi i k t}) / 2, so the
+// cosine group of bandwidth N is the exponential group of bandwidth 2N (frequencies -N..N-1)
+// at the nodes t with coefficients ghat_l = 2^{-|u|/2} fhat_{|l|} (zero where some |l_j| = N),
+// and the adjoint folds the exponential adjoint: fhat_k = 2^{-|u|/2} sum over the 2^{|u|} sign
+// patterns s of hhat_{s k} (the basis is real, so no conjugation enters).
+// Internal index per axis a = 0..2N-2 holds l = a - N (a < N) or a - N + 1; external e = 0..N-2
+// holds k = e + 1.  Both layouts row-major, last axis fastest.
+// One workgroup per (term, right-hand side): ghat over the term's internal group.
+template <typename T>
+__global__ __launch_bounds__(kVecBS) void k_cos_expand(const cx_t<T> *__restrict__ fhat, const T *__restrict__ colscale,
+                                                       int64_t ncoef, const CosTerm *__restrict__ ct,
+                                                       int64_t ncoef_int, cx_t<T> *__restrict__ ghat) {
+  const int r = blockIdx.y;
+  if (blockIdx.x == 0) {   // the empty set (phi_0 = 1)
+    if (threadIdx.x == 0) {
+      const cx_t<T> v = fhat[(int64_t)r * ncoef];
+      const T c = colscale ? colscale[0] : (T)1;
+      ghat[(int64_t)r * ncoef_int] = cmake<T>(c * v.x, c * v.y);
+    }
+    return;
+  }
+  const CosTerm tm = ct[blockIdx.x - 1];
+  const int t = tm.t, N = tm.N, Ki = 2 * N - 1, Ke = N - 1;
+  int64_t size = 1;
+  for (int j = 0; j < t; ++j) size *= Ki;
+  const T norm = t == 1 ? (T)0.70710678118654752440 : (t == 2 ? (T)0.5 : (T)0.35355339059327376220);
+  for (int64_t i = threadIdx.x; i < size; i += kVecBS) {
+    int64_t rest = i, e = 0, pw = 1;
+    bool zero = false;
+    for (int j = t - 1; j >= 0; --j) {   // last axis fastest
+      const int a = (int)(rest % Ki);
+      rest /= Ki;
+      const int l = a < N ? a - N : a - N + 1;
+      const int k = l < 0 ? -l : l;
+      zero |= k == N;
+      e += (int64_t)(k - 1) * pw;
+      pw *= Ke;
+    }
+    cx_t<T> out = cmake<T>((T)0, (T)0);
+    if (!zero) {
+      const cx_t<T> v = fhat[(int64_t)r * ncoef + tm.ext_off + e];
+      const T c = norm * (colscale ? colscale[tm.ext_off + e] : (T)1);
+      out = cmake<T>(c * v.x, c * v.y);
+    }
+    ghat[(int64_t)r * ncoef_int + tm.int_off + i] = out;
+  }
+}
+
+// One workgroup per (term, right-hand side): fhat over the term's external group.
+template <typename T>
+__global__ __launch_bounds__(kVecBS) void k_cos_fold(const cx_t<T> *__restrict__ hhat, int64_t ncoef_int,
+                                                     const CosTerm *__restrict__ ct, const T *__restrict__ colscale,
+                                                     int64_t ncoef, cx_t<T> *__restrict__ fhat) {
+  const int r = blockIdx.y;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      const cx_t<T> v = hhat[(int64_t)r * ncoef_int];
+      const T c = colscale ? colscale[0] : (T)1;
+      fhat[(int64_t)r * ncoef] = cmake<T>(c * v.x, c * v.y);
+    }
+    return;
+  }
+  const CosTerm tm = ct[blockIdx.x - 1];
+  const int t = tm.t, N = tm.N, Ki = 2 * N - 1, Ke = N - 1;
+  int64_t size = 1;
+  for (int j = 0; j < t; ++j) size *= Ke;
+  const T norm = t == 1 ? (T)0.70710678118654752440 : (t == 2 ? (T)0.5 : (T)0.35355339059327376220);
+  for (int64_t e = threadIdx.x; e < size; e += kVecBS) {
+    int kk[3] = {0, 0, 0};
+    int64_t rest = e;
+    for (int j = t - 1; j >= 0; --j) {
+      kk[j] = (int)(rest % Ke) + 1;
+      rest /= Ke;
+    }
+    T sr = 0, si = 0;
+    for (int sgn = 0; sgn < (1 << t); ++sgn) {   // sign patterns, a fixed order
+      int64_t idx = 0;
+      for (int j = 0; j < t; ++j) {
+        const int l = (sgn >> j) & 1 ? -kk[j] : kk[j];
+        idx = idx * Ki + (l < 0 ? l + N : l + N - 1);
+      }
+      const cx_t<T> v = hhat[(int64_t)r * ncoef_int + tm.int_off + idx];
+      sr += v.x;
+      si += v.y;
+    }
+    const T c = norm * (colscale ? colscale[tm.ext_off + e] : (T)1);
+    fhat[(int64_t)r * ncoef + tm.ext_off + e] = cmake<T>(c * sr, c * si);
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -980,15 +1075,15 @@ static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStre
     prof_begin(s, t == 1 ? "pack_fwd_1d" : t == 2 ? "pack_fwd_2d" : "pack_fwd_3d");
     if (t == 1) {
       if (int rc = set_lds(k_pack_fwd<T, 1>, lds)) return rc;
-      hipLaunchKernelGGL((k_pack_fwd<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+      hipLaunchKernelGGL((k_pack_fwd<T, 1>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef_int,
                          pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     } else if (t == 2) {
       if (int rc = set_lds(k_pack_fwd<T, 2>, lds)) return rc;
-      hipLaunchKernelGGL((k_pack_fwd<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+      hipLaunchKernelGGL((k_pack_fwd<T, 2>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef_int,
                          pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     } else {
       if (int rc = set_lds(k_pack_fwd<T, 3>, lds)) return rc;
-      hipLaunchKernelGGL((k_pack_fwd<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef,
+      hipLaunchKernelGGL((k_pack_fwd<T, 3>), grid, dim3(kPackBS), lds, s, (const C *)fhat, colscale, pl->ncoef_int,
                          pl->d_terms, op, (C *)pl->d_grid, pl->grid_total, slices);
     }
     prof_end(s);
@@ -1013,7 +1108,7 @@ static int join_side(gt_plan *pl, hipStream_t s) {
 }
 
 template <typename T>
-int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
+static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
   if (ngi == 0) return launch_pack<T>(pl, fhat, colscale, s);
@@ -1037,7 +1132,7 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
 #define GT_LAUNCH_PPACK(MH)                                                                                      \
   {                                                                                                              \
     if (int rc = set_lds(k_pack_poly2<MH>, plds)) return rc;                                                     \
-    hipLaunchKernelGGL((k_pack_poly2<MH>), pgrid, dim3(kPackBS), plds, st, (const C *)fhat, colscale, pl->ncoef, \
+    hipLaunchKernelGGL((k_pack_poly2<MH>), pgrid, dim3(kPackBS), plds, st, (const C *)fhat, colscale, pl->ncoef_int, \
                        pl->d_terms, opf, nslab, (C *)o.d_kpoly);                                                 \
   }
           GT_DISPATCH_M(o.m, GT_LAUNCH_PPACK)
@@ -1123,7 +1218,7 @@ int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hi
     if (fk)
       if (int rc = join_side(pl, s)) return rc;
     prof_begin(s, "reduce_f");
-    hipLaunchKernelGGL((k_reduce_f<T>), dim3(4 * ngi), dim3(256), 0, s, (const C *)fhat, pl->ncoef, pl->d_gitems,
+    hipLaunchKernelGGL((k_reduce_f<T>), dim3(4 * ngi), dim3(256), 0, s, (const C *)fhat, pl->ncoef_int, pl->d_gitems,
                        (const C *)pl->d_fpart, g1 - g0, pl->Vtot, blk > 0 ? 1 : 0, (C *)f);
     prof_end(s);
     if (int rc = check_launch("k_reduce_f")) return rc;
@@ -1145,7 +1240,7 @@ static Tile2Args tile2_args(const gt_plan *pl) {
 }
 
 template <typename T>
-int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
+static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
   const bool fk = fork_side(pl, s);
@@ -1241,18 +1336,18 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     if (t == 1) {
       if (int rc = set_lds(k_dft_adj<T, 1>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 1>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, 0, 0, 1);
+                         colscale, pl->ncoef_int, (C *)fhat, 0, 0, 1);
     } else if (t == 2) {
       if (int rc = set_lds(k_dft_adj<T, 2>, lds)) return rc;
       // up to four workgroups per term (column ranges of at least 8 frequencies)
       const int nsplit = std::max(1, std::min(4, (o.N - 1) / 8));
       hipLaunchKernelGGL((k_dft_adj<T, 2>), dim3(nt * nsplit, pl->R), dim3(2 * kPackBS), lds, st,
-                         (const C *)o.d_tsum, pl->d_terms, op, colscale, pl->ncoef, (C *)fhat,
+                         (const C *)o.d_tsum, pl->d_terms, op, colscale, pl->ncoef_int, (C *)fhat,
                          stage_h ? o.ntile : -o.ntile, o.ts, nsplit);
     } else {
       if (int rc = set_lds(k_dft_adj<T, 3>, lds)) return rc;
       hipLaunchKernelGGL((k_dft_adj<T, 3>), grid, dim3(kPackBS), lds, st, (const C *)o.d_gsum, pl->d_terms, op,
-                         colscale, pl->ncoef, (C *)fhat, 0, 0, 1);
+                         colscale, pl->ncoef_int, (C *)fhat, 0, 0, 1);
     }
     prof_end(st);
     if (int rc = check_launch("k_dft_adj")) return rc;
@@ -1263,7 +1358,7 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
     hipLaunchKernelGGL((k_empty_part<T>), dim3(ngi), dim3(kGatherBS), 0, st, pl->d_gitems, (const C *)y,
                        pl->d_ysum);
     hipLaunchKernelGGL((k_empty_adj<T>), dim3(pl->R), dim3(kGatherBS), 0, st, pl->d_gitem_begin,
-                       (const double *)pl->d_ysum, pl->ncoef, (C *)fhat);
+                       (const double *)pl->d_ysum, pl->ncoef_int, (C *)fhat);
     prof_end(st);
     if (int rc = check_launch("k_empty_adj")) return rc;
   }
@@ -1273,14 +1368,46 @@ int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hi
 }
 
 template <typename T>
+static int cos_expand(gt_plan *pl, const void *fhat, const T *colscale, hipStream_t s) {
+  using C = cx_t<T>;
+  hipLaunchKernelGGL((k_cos_expand<T>), dim3((unsigned)pl->nterms, (unsigned)pl->R), dim3(kVecBS), 0, s,
+                     (const C *)fhat, colscale, pl->ncoef, pl->d_cterms, pl->ncoef_int, (C *)pl->d_gcos);
+  return check_launch("k_cos_expand");
+}
+
+// Forward and adjoint in the plan's basis.  The exponential basis runs the transform kernels
+// directly; the cosine basis expands the coefficients (with the column scaling) into the
+// plan's exponential coefficient buffer first, or folds the exponential adjoint out of it.
+template <typename T>
+int launch_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
+  if (pl->basis != GT_BASIS_COS) return forward_core<T>(pl, fhat, colscale, f, s);
+  if (int rc = cos_expand<T>(pl, fhat, colscale, s)) return rc;
+  return forward_core<T>(pl, pl->d_gcos, nullptr, f, s);
+}
+
+template <typename T>
+int launch_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
+  using C = cx_t<T>;
+  if (pl->basis != GT_BASIS_COS) return adjoint_core<T>(pl, y, colscale, fhat, s);
+  if (int rc = adjoint_core<T>(pl, y, nullptr, pl->d_gcos, s)) return rc;
+  hipLaunchKernelGGL((k_cos_fold<T>), dim3((unsigned)pl->nterms, (unsigned)pl->R), dim3(kVecBS), 0, s,
+                     (const C *)pl->d_gcos, pl->ncoef_int, pl->d_cterms, colscale, pl->ncoef, (C *)fhat);
+  return check_launch("k_cos_fold");
+}
+
+template <typename T>
 int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hipStream_t s) {
   using C = cx_t<T>;
   if (pl->ds == 0) {
     // no term depends on the nodes
     const int64_t total = pl->Mtot * pl->d;
     hipLaunchKernelGGL((k_reduce_gx<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)nullptr, 0,
-                       pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T *)gx);
+                       pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T)pl->node_scale, (T *)gx);
     return check_launch("k_reduce_gx");
+  }
+  if (pl->basis == GT_BASIS_COS) {
+    if (int rc = cos_expand<T>(pl, fhat, nullptr, s)) return rc;
+    fhat = pl->d_gcos;
   }
   if (int rc = launch_pack<T>(pl, fhat, nullptr, s)) return rc;
   if (!pl->d_gxp) {
@@ -1333,7 +1460,7 @@ int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hip
   if (rc == GT_OK) {
     const int64_t total = pl->Mtot * pl->d;
     hipLaunchKernelGGL((k_reduce_gx<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)gxp,
-                       pl->ds, pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T *)gx);
+                       pl->ds, pl->Vtot, pl->Mtot, pl->R, pl->ragged, pl->d, (T)pl->node_scale, (T *)gx);
     rc = check_launch("k_reduce_gx");
   }
   return rc;
@@ -1345,7 +1472,7 @@ int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pl->d_flag);
   if (total > 0)
     hipLaunchKernelGGL((k_prepare_nodes<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)x,
-                       pl->Mtot, pl->d, (T *)pl->d_x, pl->d_flag);
+                       pl->Mtot, pl->d, (T)pl->node_scale, (T *)pl->d_x, pl->d_flag);
   return check_launch("k_prepare_nodes");
 }
 

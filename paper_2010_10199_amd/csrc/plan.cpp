@@ -159,10 +159,11 @@ int validate_problem(const gt_problem *p) {
   if (p->d < 1) return fail(GT_EINVAL, "d must be >= 1");
   if (p->ds < 0 || p->ds > p->d) return fail(GT_EINVAL, "need 0 <= ds <= d");
   if (p->ds > kMaxOrder) return fail(GT_EUNSUPPORTED, "terms of order > 3 are not implemented on the GPU path");
+  if (p->basis != GT_BASIS_EXP && p->basis != GT_BASIS_COS) return fail(GT_EINVAL, "basis must be GT_BASIS_EXP or GT_BASIS_COS");
   for (int t = 1; t <= p->ds; ++t) {
     int N = p->N[t - 1];
     if (N < 2 || (N % 2)) return fail(GT_EINVAL, "bandwidths must be even and >= 2");
-    if (N > 4096) return fail(GT_EUNSUPPORTED, "bandwidth above 4096");
+    if (N > (p->basis == GT_BASIS_COS ? 2048 : 4096)) return fail(GT_EUNSUPPORTED, "bandwidth above 4096 (cosine: 2048)");
   }
   if (p->R < 1) return fail(GT_EINVAL, "R must be >= 1");
   if (p->dtype != GT_C64 && p->dtype != GT_C128) return fail(GT_EINVAL, "dtype must be GT_C64 or GT_C128");
@@ -324,6 +325,8 @@ void free_plan(gt_plan *pl) {
   dev_free(pl->d_ysum, nullptr);
   dev_free(pl->d_flag, nullptr);
   dev_free(pl->d_gxp, nullptr);
+  dev_free(pl->d_cterms, nullptr);
+  dev_free(pl->d_gcos, nullptr);
   for (auto &o : pl->ord) {
     dev_free(o.d_deconv, nullptr);
     dev_free(o.d_roots, nullptr);
@@ -533,6 +536,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   if (!pl) return fail(GT_ENOMEM, "host allocation");
   pl->prob = *p;
   pl->prob.offsets = nullptr;
+  pl->basis = p->basis;
+  pl->node_scale = p->basis == GT_BASIS_COS ? 0.5 : 1.0;
   pl->dtype = p->dtype;
   pl->rsize = p->dtype == GT_C64 ? sizeof(float) : sizeof(double);
   pl->d = p->d;
@@ -576,13 +581,16 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     pl->ev_fork = pl->ev_join = nullptr;
   }
 
-  // ---- terms in coefficient order (ci: index in the unmasked enumeration, for the term mask)
-  int64_t coef = 0, grid = 0, ci = 0;
+  // ---- terms in coefficient order (ci: index in the unmasked enumeration, for the term mask);
+  //      coef: offsets of the index set the kernels run on, coef_ext: of the caller's vectors
+  int64_t coef = 0, coef_ext = 0, grid = 0, ci = 0;
   for (int t = 0; t <= p->ds; ++t) {
     OrderHost &o = pl->ord[t];
     o.term_begin = (int32_t)pl->terms.size();
     if (t > 0) {
-      o.N = p->N[t - 1];
+      // the cosine basis runs on the exponential groups of twice the bandwidth (see the
+      // cosine kernels), so every grid size and table below is the exponential one's
+      o.N = p->N[t - 1] * (p->basis == GT_BASIS_COS ? 2 : 1);
       o.n = 2 * (int)std::ceil(sigma * o.N / 2.0);
       if (o.n < o.N + 2) o.n = o.N + 2;
       o.m = p->m ? p->m : choose_m(p->dtype, (double)o.n / o.N);
@@ -592,8 +600,11 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     }
     std::vector<int> c(t);
     for (int i = 0; i < t; ++i) c[i] = i;
-    int64_t gsz = 1;
-    for (int k = 0; k < t; ++k) gsz *= (o.N - 1);
+    int64_t gsz = 1, gsz_ext = 1;
+    for (int k = 0; k < t; ++k) {
+      gsz *= (o.N - 1);
+      gsz_ext *= (p->N[t - 1] - 1);
+    }
     while (true) {
       const bool keep = t == 0 || !p->term_mask || p->term_mask[ci];
       ++ci;
@@ -606,6 +617,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
         dt.coef_off = coef;
         dt.grid_off = t > 0 ? grid : 0;
         coef += t > 0 ? gsz : 1;
+        pl->ext_off.push_back(coef_ext);
+        coef_ext += t > 0 ? gsz_ext : 1;
         if (t > 0) grid += o.gsize;
         pl->terms.push_back(dt);
       }
@@ -620,7 +633,8 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     o.term_end = (int32_t)pl->terms.size();
   }
   pl->nterms = (int32_t)pl->terms.size();
-  pl->ncoef = coef;
+  pl->ncoef = coef_ext;
+  pl->ncoef_int = coef;
   pl->grid_total = grid;
 
   // ---- per-order tables, LDS checks
@@ -793,6 +807,21 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
         (rc = dev_alloc(&o.d_gpart, (size_t)o.sitems.size() * o.gpart_stride * csz, s)) ||
         (rc = dev_alloc(&o.d_gsum, t == 2 ? 0 : (size_t)pl->R * (o.term_end - o.term_begin) * (size_t)o.ncell * csz,
                         s))) {
+      free_plan(pl);
+      return rc;
+    }
+  }
+
+  // ---- cosine basis: per-term table of the coefficient conversion, exponential coefficients
+  if (pl->basis == GT_BASIS_COS) {
+    std::vector<CosTerm> ct;
+    for (int i = 1; i < pl->nterms; ++i) {
+      const DevTerm &dt = pl->terms[i];
+      ct.push_back(CosTerm{dt.t, p->N[dt.t - 1], dt.coef_off, pl->ext_off[i]});
+    }
+    if (ct.empty()) ct.push_back(CosTerm{0, 2, 0, 0});   // (unused; keeps the table non-empty)
+    if ((rc = upload_raw(ct, &pl->d_cterms)) ||
+        (rc = dev_alloc(&pl->d_gcos, (size_t)pl->R * pl->ncoef_int * csz, s))) {
       free_plan(pl);
       return rc;
     }

@@ -1011,7 +1011,7 @@ static int fista_setup(gt_plan *pl, FistaWork<T> &w, Scratch &sc, const double *
   if ((rc = w.get(pl, sc, eta > 1.0))) return rc;
   if (omega && (rc = weight_scale<T>(omega, pl->ncoef, sc, (T **)nullptr, s))) return rc;
   std::vector<int64_t> hoff(ngroups + 1);
-  for (int i = 0; i < ngroups; ++i) hoff[i] = pl->terms[i].coef_off;
+  for (int i = 0; i < ngroups; ++i) hoff[i] = pl->ext_off[i];
   hoff[ngroups] = pl->ncoef;
   GT_HIP(hipMemcpyAsync(w.goff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
   GT_HIP(hipStreamSynchronize(s));   // hoff is a host temporary

@@ -21,6 +21,7 @@ GT_C64, GT_C128 = 1, 2
 GT_MAX_ORDER = 3
 GT_SOLVE_CONVERGED, GT_SOLVE_MAX_ITER, GT_SOLVE_BREAKDOWN, GT_SOLVE_BACKTRACK_CAP = 1, 2, 4, 8
 GT_GATHER_SORTED, GT_GATHER_CELL, GT_GATHER_POLY = 0, 1, 2
+GT_BASIS_EXP, GT_BASIS_COS = 0, 1
 
 # every symbol include/grouped.h declares
 EXPORTS = [
@@ -37,7 +38,7 @@ class GtProblem(C.Structure):
     _fields_ = [
         ("d", C.c_int32), ("ds", C.c_int32), ("N", C.c_int32 * GT_MAX_ORDER), ("M", C.c_int64),
         ("R", C.c_int32), ("offsets", C.POINTER(C.c_int64)), ("dtype", C.c_int32), ("m", C.c_int32),
-        ("sigma", C.c_double), ("term_mask", C.POINTER(C.c_uint8)),
+        ("sigma", C.c_double), ("term_mask", C.POINTER(C.c_uint8)), ("basis", C.c_int32),
     ]
 
 
@@ -123,10 +124,12 @@ def _check(rc: int):
 
 def make_problem(d: int, ds: int, N: Sequence[int], M: int = 0, R: int = 1, dtype: int = GT_C64,
                  m: int = 0, sigma: float = 0.0, offsets: Optional[Sequence[int]] = None,
-                 term_mask: Optional[Sequence[int]] = None):
+                 term_mask: Optional[Sequence[int]] = None, basis: int = GT_BASIS_EXP):
     """Build a GtProblem; returns (problem, keepalive) - keep the second alive while in use.
-    term_mask: None, or gt_num_terms(d, ds) flags (0 drops the term; see gt_problem)."""
+    term_mask: None, or gt_num_terms(d, ds) flags (0 drops the term; see gt_problem);
+    basis: GT_BASIS_EXP or GT_BASIS_COS."""
     p = GtProblem()
+    p.basis = int(basis)
     p.d, p.ds = int(d), int(ds)
     for i in range(GT_MAX_ORDER):
         p.N[i] = int(N[i]) if i < len(N) else 0

@@ -116,3 +116,6 @@ def test_allocation_failure_hook_and_plan_handles_on_cpu():
     assert L.gt_plan_trafo(bogus, None, None, None) == lib.GT_EINVAL
     assert L.gt_plan_destroy(None) == lib.GT_OK
     assert L.gt_release_all() == lib.GT_OK
+    pb, keepb = lib.make_problem(3, 2, [4, 4], M=4, dtype=lib.GT_C128, basis=7)
+    assert L.gt_plan_create(C.byref(pb), x.ctypes.data, None, C.byref(h)) == lib.GT_EINVAL
+    assert "basis" in L.gt_last_error().decode()

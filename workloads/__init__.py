@@ -50,6 +50,14 @@ def uniform_nodes(g: np.random.Generator, M: int, d: int, precision: str = "f64"
     return np.ascontiguousarray(x)
 
 
+def unit_cube_nodes(g: np.random.Generator, M: int, d: int, precision: str = "f64") -> np.ndarray:
+    """M x d nodes iid uniform on [0, 1)^d (the domain of the cosine basis), row-major; drawn
+    in float64 and rounded to the run's precision (a value that rounds up to 1 stays 1,
+    which is inside the closed cube)."""
+    x = g.random((M, d)).astype(real_dtype(precision))
+    return np.ascontiguousarray(x)
+
+
 def complex_normal(g: np.random.Generator, shape, precision: str = "f64") -> np.ndarray:
     """Circularly symmetric complex normal: real and imaginary parts iid N(0, 1/2)."""
     z = (g.standard_normal(shape) + 1j * g.standard_normal(shape)) * math.sqrt(0.5)
