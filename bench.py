@@ -425,6 +425,78 @@ def run_c3(steps: int, all_lambdas: bool):
     return out
 
 
+def run_cosine(steps: int):
+    """The non-periodic variant (Sec. 5, half-period cosine basis on [0, 1]^d) on the shape of
+    the paper's adult-data model: d = 12, d_s = 2, N = 82 / 10 (79 terms, 6,319
+    coefficients), M = 36,160 synthetic nodes uniform on [0, 1]^12 (the paper's training size;
+    the census data itself is not used), FP32.  Forward + adjoint throughput on a plan, and an
+    LSQR fit over 8 lambda values in one lsqr_solve_path call (40 iterations) for samples of a
+    smooth target with five active ANOVA terms + 1 % noise."""
+    import torch
+    import workloads as W
+    from paper_2010_10199_amd import lib
+    d, ds, N, M = 12, 2, (82, 10), 36160
+    ncoef, nterms = lib.gt_num_coeffs(d, ds, N), lib.gt_num_terms(d, ds)
+    x = W.unit_cube_nodes(W.rng(8, W.P_NODES), M, d, "f32")
+    fh = W.complex_normal(W.rng(8, W.P_COEFFS), (ncoef,), "f32")
+    yv = W.complex_normal(W.rng(8, W.P_SAMPLES), (M,), "f32")
+    xd, fd, yd = (torch.from_numpy(a).cuda() for a in (x, fh, yv))
+    f_out = torch.empty(M, dtype=torch.complex64, device="cuda")
+    a_out = torch.empty(ncoef, dtype=torch.complex64, device="cuda")
+    p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C64, basis=lib.GT_BASIS_COS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = lib.Plan(p, xd, keepalive=keep)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    plan.trafo(fd, f_out)
+    plan.adjoint(yd, a_out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.trafo(fd, f_out)
+        plan.adjoint(yd, a_out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    # smooth target: 3 one- and 2 two-dimensional terms built from cos(pi x) pieces, + 1 % noise
+    xs = x.astype(np.float64)
+    tgt = (np.cos(np.pi * xs[:, 0]) + 0.5 * np.cos(2 * np.pi * xs[:, 1]) + xs[:, 2] ** 2 - 1.0 / 3.0
+           + np.cos(np.pi * xs[:, 3]) * np.cos(np.pi * xs[:, 4]) + (xs[:, 5] - 0.5) * (xs[:, 6] - 0.5))
+    y = W.add_noise(W.rng(8, W.P_NOISE), tgt, 0.01).astype(np.complex64)
+    lams = np.logspace(-2, 2, 8)
+    path = torch.empty(len(lams) * ncoef, dtype=torch.complex64, device="cuda")
+    yt = torch.from_numpy(y).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = plan.lsqr_path(yt, lams, None, 40, 0.0, path)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    sols = path.reshape(len(lams), ncoef)
+    resid = []
+    for j in range(len(lams)):
+        plan.trafo(sols[j].contiguous(), f_out)
+        torch.cuda.synchronize()
+        resid.append(float(np.linalg.norm(f_out.cpu().numpy() - y) / np.linalg.norm(y)))
+    rho = torch.empty(nterms, dtype=torch.float64, device="cuda")
+    best = int(np.argmin(resid))
+    lib.sensitivity(p, sols[best].contiguous(), rho)
+    r = rho.cpu().numpy()
+    coords, _ = lib.gt_term_table(d, ds, N)
+    top = [tuple(int(c) for c in coords[i] if c >= 0) for i in np.argsort(-r)[:5]]
+    plan.close()
+    print(f"[bench]   cosine: {ms:.3f} ms per fwd+adj; lsqr path {fit_s:.3f} s", file=sys.stderr, flush=True)
+    return {"workload": f"cosine basis, adult-data shape: d={d}, d_s={ds}, N={N[0]}/{N[1]}, {nterms} terms, "
+                        f"{ncoef} coefficients, M={M} uniform nodes on [0,1]^12, FP32",
+            "plan_s": plan_s, "fwd_adj": {"value": 2 * M * nterms / (ms * 1e-3), "unit": "node-terms/s", "ms": ms},
+            "lsqr_path": {"lambdas": [float(v) for v in lams], "iters": 40, "s": fit_s,
+                          "rel_residual": resid, "best_lambda": float(lams[best]),
+                          "top5_terms_by_sensitivity": top,
+                          "true_terms": [(0,), (1,), (2,), (3, 4), (5, 6)]}}
+
+
 def run_active_set():
     """The pipeline of Sec. 4.1 on the solver workload (B-spline target with 3 one- and 2
     two-dimensional terms, 1 % noise), FP32: LSQR fit on U_2, global sensitivity indices
@@ -865,6 +937,9 @@ def main():
                     "active_set_is_printed_U*": sum(r[e]["active_set_is_printed_U*"] for r in fruns)} for e in exps}
         print("[bench] autograd", file=sys.stderr, flush=True)
         out["autograd"] = run_autograd()
+    if not args.no_solvers:
+        print("[bench] cosine basis", file=sys.stderr, flush=True)
+        out["cosine"] = run_cosine(max(5, args.steps // 2))
     if not args.no_c3:
         print("[bench] batched-lsqr workload (d=20)", file=sys.stderr, flush=True)
         out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas)
