@@ -1267,8 +1267,8 @@ static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fha
       hipLaunchKernelGGL((k_spread_binned<T, 1, MH>), grid, dim3(64 * kSpreadWaves), lds, st, (const T *)pl->d_x, pl->Mtot,       \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     } else {                                                                                                      \
-      if (int rc = set_lds(k_spread_binned<T, 3, MH>, lds)) return rc;                                            \
-      hipLaunchKernelGGL((k_spread_binned<T, 3, MH>), grid, dim3(64 * kSpreadWaves), lds, st, (const T *)pl->d_x, pl->Mtot,       \
+      if (int rc = set_lds(k_spread_cell3<T, MH>, lds)) return rc;                                                \
+      hipLaunchKernelGGL((k_spread_cell3<T, MH>), grid, dim3(64 * kSpreadWaves), lds, st, (const T *)pl->d_x, pl->Mtot,           \
                          o.d_sitems, pl->d_terms, op, sa, (const C *)y, (C *)o.d_gpart, o.gpart_stride);         \
     }                                                                                                             \
   }

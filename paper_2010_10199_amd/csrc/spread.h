@@ -204,6 +204,124 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
   for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
 }
 
+// Order-3 spread, MFMA tiles without window padding.  For one cell the contribution
+//   g[j1][j2][j3] += sum_v (y_v psi0_v[j1]) psi1_v[j2] psi2_v[j3]
+// is the product of a (real/imaginary part, j1) x node matrix with a node x (j2, j3) matrix:
+// rows 2W (one 16-row tile at W = 8), columns W^2 in 16-column tiles (column 16 ct + i holds
+// j2 = (16 ct + i) / W, j3 = (16 ct + i) % W).  At the FP32 path's W = 8 a step of four nodes
+// takes 4 MFMAs instead of the 16 of a tile per j2 padded to 16 x 16; at W = 16 the count is
+// unchanged.  Lane (node b, i) evaluates the window of its own point i mod W on all three axes
+// (one Horner sum each, the point's coefficients held in registers) and takes the other
+// points it needs from the lanes holding them (shuffles within the node's 16 lanes).  Column
+// tiles are taken CP at a time (accumulator registers), each pass walking the cell's nodes.
+// Per cell the accumulators are added into the workgroup's FP64 LDS grid (atomics, as in
+// k_spread_binned), which is written out as the workgroup's partial grid.
+template <typename T, int MH>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_cell3(const T *__restrict__ xT, int64_t Mx,
+                                                                    const SpreadItem *__restrict__ items,
+                                                                    const DevTerm *__restrict__ terms,
+                                                                    OrderParams<T> op, SpreadArgs sa,
+                                                                    const cx_t<T> *__restrict__ y,
+                                                                    cx_t<T> *__restrict__ gpart, int64_t gstride) {
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc;
+  constexpr int W = 2 * MH;
+  constexpr int RT = (2 * W + 15) / 16, CT = (W * W + 15) / 16;
+  constexpr int CP = sizeof(T) == 4 ? (CT < 4 ? CT : 4) : (CT < 4 ? CT : 4);   // column tiles per pass
+  static_assert(RT * CP <= 8, "accumulator registers");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *G = reinterpret_cast<double2 *>(smem_raw);
+  const SpreadItem it = items[blockIdx.x];
+  const int tl = blockIdx.y;
+  const DevTerm tm = terms[op.term_begin + tl];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, i16 = l & 15, kk = l >> 4, base = l & 48;
+  const int n = op.n, P = op.P, gsize = op.gsize;
+  for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) G[i] = make_double2(0.0, 0.0);
+  WinPoint<T> wp;   // the lane's own window point i mod W, all three axes
+  wp.load(op.poly, i16 % W, W);
+  __syncthreads();
+  const int64_t key0 = ((int64_t)tl * sa.B + it.b) * sa.ncell;
+  const int64_t vbase = (int64_t)it.r * sa.vstride;
+  const T *x0p = xT + (int64_t)tm.c0 * Mx, *x1p = xT + (int64_t)tm.c1 * Mx, *x2p = xT + (int64_t)tm.c2 * Mx;
+  const T two_n = (T)(2 * n);
+  for (int c = it.c0 + wv; c < it.c1; c += kSpreadWaves) {   // cells round-robin over the waves
+    const int64_t p0 = sa.cstart[key0 + c], p1 = sa.cstart[key0 + c + 1];
+    if (p1 <= p0) continue;
+    const int fl0 = c / (n * n), rem = c - fl0 * n * n, fl1 = rem / n, fl2 = rem - fl1 * n;
+    const T zc0 = (T)(n - 2 * fl0 - 1), zc1 = (T)(n - 2 * fl1 - 1), zc2 = (T)(n - 2 * fl2 - 1);
+    const int rs0 = wrap_start(fl0, MH, n), rs1 = wrap_start(fl1, MH, n);
+    for (int ct0 = 0; ct0 < CT; ct0 += CP) {
+      acc_t acc[RT][CP];
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int u = 0; u < CP; ++u) acc[a][u] = acc_t{0, 0, 0, 0};
+      for (int64_t b0 = p0; b0 < p1; b0 += 64) {
+        const int64_t q = b0 + l;
+        const bool valid = q < p1;
+        const int32_t node = sa.perm[valid ? q : p0];
+        cx_t<T> yl = y[vbase + node];
+        const T za = fma(two_n, x0p[node], zc0);
+        const T zb = fma(two_n, x1p[node], zc1);
+        const T zd = fma(two_n, x2p[node], zc2);
+        if (!valid) yl = cmake<T>(0, 0);
+        const int steps = (int)((p1 - b0 + 3) >> 2) < 16 ? (int)((p1 - b0 + 3) >> 2) : 16;
+        for (int st = 0; st < steps; ++st) {
+          const int src = 4 * st + kk;
+          const T w0 = wp(__shfl(za, src, 64));
+          const T w1 = wp(__shfl(zb, src, 64));
+          const T w2 = wp(__shfl(zd, src, 64));
+          const T yr = __shfl(yl.x, src, 64), yi = __shfl(yl.y, src, 64);
+          T av[RT];
+#pragma unroll
+          for (int a = 0; a < RT; ++a) {
+            const int row = 16 * a + i16;
+            const int part = row / W, j1 = row % W;
+            const T p0v = ((16 * a) % W == 0) ? w0 : __shfl(w0, base | j1, 64);
+            av[a] = row < 2 * W ? p0v * (part ? yi : yr) : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < CP; ++u) {
+            const int ct = ct0 + u;
+            if (ct >= CT) break;
+            const int col = 16 * ct + i16;
+            const int j2 = col / W, j3 = col % W;
+            const T p2v = ((16 * ct) % W == 0) ? w2 : __shfl(w2, base | j3, 64);
+            const T p1v = __shfl(w1, base | (j2 < W ? j2 : 0), 64);
+            const T bv = col < W * W ? p1v * p2v : (T)0;
+#pragma unroll
+            for (int a = 0; a < RT; ++a) acc[a][u] = MF::run(av[a], bv, acc[a][u]);
+          }
+        }
+      }
+      // accumulator element e of lane l: row MF::row(l, e) of row tile a, column 16 ct + i16
+#pragma unroll
+      for (int u = 0; u < CP; ++u) {
+        const int ct = ct0 + u;
+        if (ct >= CT) break;
+        const int col = 16 * ct + i16;
+        if (col >= W * W) continue;
+        const int j2 = col / W, j3 = col % W;
+        const int g1 = (rs1 + j2) % n;
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = 16 * a + MF::row(l, e);
+            if (row >= 2 * W) continue;
+            const int part = row / W, j1 = row % W;
+            const int g0 = (rs0 + j1) % n;
+            double2 *dst = &G[((int64_t)g0 * n + g1) * P + fl2 + j3];
+            atomicAdd(part ? &dst->y : &dst->x, (double)acc[a][u][e]);
+          }
+      }
+    }
+  }
+  __syncthreads();
+  cx_t<T> *out = gpart + (int64_t)blockIdx.x * gstride + tm.gpart_off;
+  for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
+}
+
 // Orders the LDS accesses of one wavefront: staging writes by some lanes before reads by
 // other lanes of the same wavefront (and those reads before the next overwrite).
 __device__ __forceinline__ void wave_lds_sync() {
