@@ -172,6 +172,46 @@ int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n);
 enum { GT_GATHER_SORTED = 0, GT_GATHER_CELL = 1, GT_GATHER_POLY = 2 };
 int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path);
 
+/* Selects the forward gather of order t (1..ds) by hand (GT_GATHER_*), building what that form
+ * needs; synchronises the plan's last stream first.  GT_EUNSUPPORTED when the form is not
+ * available for this plan (GT_GATHER_POLY: order 2, FP32, coefficient buffer <= 1 GiB). */
+int gt_plan_set_gather_path(gt_plan *plan, int32_t t, int32_t path);
+
+/* ------------------------------------------------------------------ tuning and graphs
+ * (not in the paper: launch choices among forms that compute the same product of
+ * Definition def:skatoons and its adjoint, differing in rounding order only)
+ *
+ * gt_plan_tune times, on the plan's own nodes and with HIP events on `stream` (a created
+ * stream, not the legacy default one), in this order:
+ *   1. per order the forward gathers the plan can take (GT_GATHER_SORTED / CELL / POLY),
+ *      keeping the fastest forward for each order in turn;
+ *   2. order 2: the resident wavefronts per compute unit of the tile spread
+ *      (8, 12, ..., 32, as the staging LDS allows), by the adjoint's time;
+ *   3. whether order 1 runs on the plan's second stream (forward + adjoint);
+ *   4. whether gt_plan_trafo / gt_plan_adjoint launch eagerly or replay a graph of their
+ *      launches captured by the plan (forward + adjoint).
+ * It allocates (and frees) one coefficient and one sample buffer for the timing runs, and
+ * synchronises `stream`.  The choice is kept by the plan and cached per device and problem
+ * signature (d, d_s, bandwidths, window widths, grid sizes, terms, R, node count, dtype,
+ * basis, ragged or not): a plan created later with the same signature takes it without
+ * timing.  gt_release_all clears the cache.
+ *
+ * gt_plan_tuning writes the JSON report of the plan's tuning (the candidates' milliseconds
+ * and the choices; "cached": true when the plan took a cached choice; "{}" when none) into
+ * buf (len bytes, NUL-terminated, truncated to fit) and returns the length it needs including
+ * the NUL, or a negative GT_E* code for a handle that is not a live plan.
+ *
+ * gt_plan_set_graph(on) turns graph replay on or off by hand.  With it on, gt_plan_trafo and
+ * gt_plan_adjoint capture their launch sequence on `stream` the first time they see an
+ * (input, output) pair (up to 8 pairs per plan, the oldest dropped first) and replay it
+ * afterwards; they launch eagerly on the legacy default stream, while `stream` is being
+ * captured by the caller, and while per-launch profiling is on.  Only these two calls replay
+ * graphs; the solvers and the node gradient launch eagerly.  Changing the plan's forms drops
+ * its graphs (after a device synchronisation). */
+int gt_plan_tune(gt_plan *plan, void *stream);
+int64_t gt_plan_tuning(const gt_plan *plan, char *buf, int64_t len);
+int gt_plan_set_graph(gt_plan *plan, int32_t on);
+
 /* ------------------------------------------------------------------ solvers
  * lsqr_solve: R independent weighted Tikhonov problems (eq. new_min_prob), one per
  * right-hand side r with its own lambda[r] >= 0 (lambda = 0: eq. min_prob), solved by

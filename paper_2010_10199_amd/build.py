@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libgrouped.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "kernels_f32.hip", "kernels_f64.hip", "solvers.hip", "binning.hip"]
+SOURCES = ["plan.cpp", "tune.cpp", "kernels_f32.hip", "kernels_f64.hip", "solvers.hip", "binning.hip"]
 
 
 def hipcc() -> str:

@@ -108,6 +108,9 @@ struct OrderHost {
   std::vector<struct GatherItem> gitems;
   struct GatherItem *d_gitems = nullptr;
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
+  int32_t path = GT_GATHER_SORTED;    // forward form of this order (GT_GATHER_*)
+  int32_t waves_cu = kTileWavesPerCU; // order 2: resident wavefronts per compute unit of the tile spread
+  std::vector<int64_t> cstart_host;   // the binning's cell starts (host copy, for work lists and the tuner)
   std::vector<CellItem> citems;       // cell gather work items (empty: k_gather_sorted is used)
   CellItem *d_citems = nullptr;
   void *d_kpoly = nullptr;            // order 2 FP32: per-cell window-polynomial coefficients of the grids (k_pack_poly2)
@@ -187,6 +190,17 @@ struct gt_plan {
   void *d_gxp = nullptr;              // node-gradient partials (orders x Vtot x d), allocated on first use
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;         // second stream (default priority) for the order-1 kernels
+  bool use_side = true;               // fork order 1 onto the side stream (a tuning choice)
+  bool use_graph = false;             // gt_plan_trafo / gt_plan_adjoint replay a captured graph (a tuning choice)
+  struct GraphEntry {
+    int dir;                          // 0 forward, 1 adjoint
+    const void *in;
+    void *out;
+    hipStream_t stream;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;     // captured launch sequences, most recent last
+  std::string tuning;                 // report of the last gt_plan_tune (JSON)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t lds_limit = 65536;           // LDS per workgroup
   int num_cu = 256;                   // compute units of the device
@@ -250,5 +264,14 @@ void dev_free(void *p, hipStream_t s);
 
 // live plans (gt_release_all, and the check that a handle is one)
 bool plan_is_live(const gt_plan *pl);
+
+// tuning (tune.cpp / plan.cpp)
+int set_gather_path(gt_plan *pl, int t, int path);
+int set_tile_waves(gt_plan *pl, int waves_cu);
+int apply_cached_tuning(gt_plan *pl);
+void clear_tuning_cache();
+void drop_graphs(gt_plan *pl);
+int run_plan_call(gt_plan *pl, int dir, const void *in, void *out, hipStream_t s);
+int tune_plan(gt_plan *pl, hipStream_t s);
 
 }  // namespace gt

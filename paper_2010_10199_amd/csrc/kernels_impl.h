@@ -1095,9 +1095,9 @@ static int launch_pack(gt_plan *pl, const void *fhat, const T *colscale, hipStre
 // Orders are independent until the final sums, so the order-1 kernels (and the empty
 // set's) run on the plan's side stream, forked from and joined back into the caller's
 // stream with events (inside a graph capture this makes parallel branches).  Not while
-// per-launch profiling is on.
+// per-launch profiling is on, nor when the plan's tuning turned it off.
 static bool fork_side(gt_plan *pl, hipStream_t s) {
-  if (!pl->side || prof_enabled() || pl->ds < 2) return false;
+  if (!pl->side || !pl->use_side || prof_enabled() || pl->ds < 2) return false;
   if (hipEventRecord(pl->ev_fork, s) != hipSuccess) return false;
   return hipStreamWaitEvent(pl->side, pl->ev_fork, 0) == hipSuccess;
 }
@@ -1123,7 +1123,7 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
       const OrderHost &o = pl->ord[t];
       bool packed = false;
       if constexpr (std::is_same<T, float>::value) {
-        if (blk == 0 && t == 2 && o.d_kpoly) {   // order 2: pack straight into per-cell polynomials
+        if (blk == 0 && t == 2 && o.path == GT_GATHER_POLY) {   // order 2: pack straight into per-cell polynomials
           const OrderParams<float> opf = order_params<float>(pl, 2);
           const int nt2 = o.term_end - o.term_begin, nslab = (o.n + kPolyRows - 1) / kPolyRows;
           const size_t plds = poly_pack_lds(o);
@@ -1147,14 +1147,14 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
       const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
       if (tb >= te) continue;
       OrderParams<T> op = order_params<T>(pl, t);
-      if (!o.citems.empty()) {   // cell gather: one wavefront per run of a cell's nodes
+      if (o.path != GT_GATHER_SORTED) {   // cell gather: one wavefront per run of a cell's nodes
         const int c0 = o.citem_begin[tb - o.term_begin], c1 = o.citem_begin[te - o.term_begin];
         if (c1 <= c0) continue;
         const int64_t vstride = pl->ragged ? 0 : pl->M;
         dim3 grid((unsigned)((c1 - c0 + 3) / 4), pl->ragged ? 1u : (unsigned)pl->R);
         prof_begin(st, t == 1 ? "gather_1d" : t == 2 ? "gather_2d" : "gather_3d");
         if constexpr (std::is_same<T, float>::value) {
-          if (t == 2 && o.d_kpoly) {
+          if (t == 2 && o.path == GT_GATHER_POLY) {
             hipLaunchKernelGGL((k_gather_poly2<T>), grid, dim3(256), 0, st, (const T *)o.d_xs, o.d_citems + c0,
                                c1 - c0, o.d_perm, op, (const C *)o.d_kpoly, vstride, -g0,
                                (C *)pl->d_fpart, pl->Vtot);

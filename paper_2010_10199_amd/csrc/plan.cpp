@@ -308,6 +308,7 @@ int upload_raw(const std::vector<V> &h, V **d) {
 void free_plan(gt_plan *pl) {
   if (!pl) return;
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  drop_graphs(pl);
   if (pl->side) {
     (void)hipStreamSynchronize(pl->side);
     (void)hipStreamDestroy(pl->side);
@@ -383,7 +384,7 @@ static int setup_tile_spread(gt_plan *pl, const std::vector<int64_t> &cs) {
   const int reff = pl->ragged ? 1 : pl->R;
   // (the LDS of a compute unit equals the per-workgroup limit on this GPU)
   const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * 3 * pl->rsize;   // complex + real rows
-  o.tile_wg_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(kTileWavesPerCU / kTileWaves, pl->lds_limit / lds2));
+  o.tile_wg_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(o.waves_cu / kTileWaves, pl->lds_limit / lds2));
   const int64_t want_waves = std::max<int64_t>(1, (int64_t)pl->num_cu * kTileWaves * o.tile_wg_cu / reff);
   std::vector<int32_t> waves;
   std::vector<int32_t> tileseg((size_t)nt * B * ntiles + 1, 0);
@@ -430,76 +431,147 @@ static int setup_tile_spread(gt_plan *pl, const std::vector<int64_t> &cs) {
   return GT_OK;
 }
 
-// Cell gather items (k_gather_cell): runs of at most 64 sorted positions inside one grid
-// cell of one term and dataset.  Kept only when the runs fill at least kCellGatherFill of the
-// lanes they occupy (otherwise the order keeps k_gather_sorted, whose workgroups take any 1024
-// consecutive positions).
-static int setup_cell_gather(gt_plan *pl, const std::vector<int64_t> (&cstarts)[kMaxOrder + 1], hipStream_t s) {
-  for (int t = 1; t <= pl->ds; ++t) {
-    OrderHost &o = pl->ord[t];
-    o.citems.clear();
-    o.citem_begin.clear();
-    const int nt = o.term_end - o.term_begin;
-    if (nt == 0 || (int64_t)nt * pl->Mtot >= (int64_t(1) << 31)) continue;
-    const int B = pl->ragged ? pl->R : 1;
-    const std::vector<int64_t> &cs = cstarts[t];
-    // lane fill of the items (runs of <= 64 nodes of one cell), decided before building them
-    int64_t nitems = 0;
-    for (size_t k = 0; k + 1 < cs.size(); ++k) nitems += (cs[k + 1] - cs[k] + 63) / 64;
-    const double fill = nitems == 0 ? 0.0 : (double)((int64_t)nt * pl->Mtot) / (64.0 * (double)nitems);
-    if (fill < kCellGatherFill || nitems >= (int64_t(1) << 31)) continue;
-    std::vector<CellItem> items;
-    items.reserve((size_t)nitems);
-    std::vector<int32_t> begin(nt + 1, 0);
-    for (int tl = 0; tl < nt; ++tl) {
-      begin[tl] = (int32_t)items.size();
-      for (int b = 0; b < B; ++b) {
-        const int64_t key0 = ((int64_t)tl * B + b) * o.nkey;
-        for (int64_t k = 0; k < o.nkey; ++k) {
-          const int64_t c0 = cs[key0 + k], c1 = cs[key0 + k + 1];
-          if (c1 <= c0) continue;
-          // the cell of binning key k (order 2 numbers cells tile-major, see the binning)
-          int32_t cell[3] = {0, 0, 0};
-          if (t == 1) {
-            cell[0] = (int32_t)k;
-          } else if (t == 2) {
-            const int64_t TT = (int64_t)o.ts * o.ts, tile = k / TT, rem = k - tile * TT;
-            cell[0] = (int32_t)((tile / o.ntile) * o.ts + rem / o.ts);
-            cell[1] = (int32_t)((tile % o.ntile) * o.ts + rem % o.ts);
-          } else {
-            cell[0] = (int32_t)(k / ((int64_t)o.n * o.n));
-            cell[1] = (int32_t)((k / o.n) % o.n);
-            cell[2] = (int32_t)(k % o.n);
-          }
-          for (int64_t q = c0; q < c1; q += 64) {
-            CellItem ci{};
-            ci.q0 = (int32_t)q;
-            ci.count = (int32_t)std::min<int64_t>(64, c1 - q);
-            ci.tl = tl;
-            ci.r = pl->ragged ? b : 0;
-            ci.cell[0] = cell[0];
-            ci.cell[1] = cell[1];
-            ci.cell[2] = cell[2];
-            items.push_back(ci);
-          }
+// Cell gather items (k_gather_cell, k_gather_poly2): runs of at most 64 sorted positions inside
+// one grid cell of one term and dataset, from the binning's cell starts of order t (host copy).
+// Returns the lane fill of the items in *fill; builds them only when `force` or when they fill
+// at least kCellGatherFill of the lanes they occupy (otherwise the order keeps
+// k_gather_sorted, whose workgroups take any 1024 consecutive positions).
+static int build_cell_items(gt_plan *pl, int t, bool force, double *fill_out) {
+  OrderHost &o = pl->ord[t];
+  if (fill_out) *fill_out = 0.0;
+  if (!o.citems.empty()) return GT_OK;   // built before
+  const int nt = o.term_end - o.term_begin;
+  if (nt == 0 || (int64_t)nt * pl->Mtot >= (int64_t(1) << 31)) return GT_OK;
+  const int B = pl->ragged ? pl->R : 1;
+  const std::vector<int64_t> &cs = o.cstart_host;
+  // lane fill of the items (runs of <= 64 nodes of one cell), decided before building them
+  int64_t nitems = 0;
+  for (size_t k = 0; k + 1 < cs.size(); ++k) nitems += (cs[k + 1] - cs[k] + 63) / 64;
+  const double fill = nitems == 0 ? 0.0 : (double)((int64_t)nt * pl->Mtot) / (64.0 * (double)nitems);
+  if (fill_out) *fill_out = fill;
+  if ((!force && fill < kCellGatherFill) || nitems == 0 || nitems >= (int64_t(1) << 31)) return GT_OK;
+  std::vector<CellItem> items;
+  items.reserve((size_t)nitems);
+  std::vector<int32_t> begin(nt + 1, 0);
+  for (int tl = 0; tl < nt; ++tl) {
+    begin[tl] = (int32_t)items.size();
+    for (int b = 0; b < B; ++b) {
+      const int64_t key0 = ((int64_t)tl * B + b) * o.nkey;
+      for (int64_t k = 0; k < o.nkey; ++k) {
+        const int64_t c0 = cs[key0 + k], c1 = cs[key0 + k + 1];
+        if (c1 <= c0) continue;
+        // the cell of binning key k (order 2 numbers cells tile-major, see the binning)
+        int32_t cell[3] = {0, 0, 0};
+        if (t == 1) {
+          cell[0] = (int32_t)k;
+        } else if (t == 2) {
+          const int64_t TT = (int64_t)o.ts * o.ts, tile = k / TT, rem = k - tile * TT;
+          cell[0] = (int32_t)((tile / o.ntile) * o.ts + rem / o.ts);
+          cell[1] = (int32_t)((tile % o.ntile) * o.ts + rem % o.ts);
+        } else {
+          cell[0] = (int32_t)(k / ((int64_t)o.n * o.n));
+          cell[1] = (int32_t)((k / o.n) % o.n);
+          cell[2] = (int32_t)(k % o.n);
+        }
+        for (int64_t q = c0; q < c1; q += 64) {
+          CellItem ci{};
+          ci.q0 = (int32_t)q;
+          ci.count = (int32_t)std::min<int64_t>(64, c1 - q);
+          ci.tl = tl;
+          ci.r = pl->ragged ? b : 0;
+          ci.cell[0] = cell[0];
+          ci.cell[1] = cell[1];
+          ci.cell[2] = cell[2];
+          items.push_back(ci);
         }
       }
     }
-    begin[nt] = (int32_t)items.size();
-    o.citems.swap(items);
-    o.citem_begin.swap(begin);
-    if (int rc = upload_raw(o.citems, &o.d_citems)) return rc;
-    // order 2, FP32: the gather evaluates per-cell polynomials (k_pack_poly2 / k_gather_poly2)
-    // when their coefficients take at most kPolyMaxBytes and the pack's arrays fit in LDS
-    if (t == 2 && pl->dtype == GT_C64) {
-      constexpr int NQ = Deg<float>::value + 1;
-      const size_t bytes = (size_t)pl->R * nt * o.n * o.n * NQ * NQ * 2 * sizeof(float);
-      if (bytes <= kPolyMaxBytes && poly_pack_lds(o) <= pl->lds_limit)
-        if (int rc = dev_alloc(&o.d_kpoly, bytes, s)) return rc;
+  }
+  begin[nt] = (int32_t)items.size();
+  o.citems.swap(items);
+  o.citem_begin.swap(begin);
+  return upload_raw(o.citems, &o.d_citems);
+}
+
+// Order 2, FP32: the gather can evaluate per-cell polynomials (k_pack_poly2 / k_gather_poly2)
+// when their coefficients take at most kPolyMaxBytes and the pack's arrays fit in LDS (needs
+// the cell items).  Allocates the coefficient buffer; false when the form is not available.
+static int build_poly(gt_plan *pl, bool *ok) {
+  OrderHost &o = pl->ord[2];
+  *ok = false;
+  if (o.d_kpoly) {
+    *ok = true;
+    return GT_OK;
+  }
+  if (pl->dtype != GT_C64 || o.citems.empty()) return GT_OK;
+  constexpr int NQ = Deg<float>::value + 1;
+  const int nt = o.term_end - o.term_begin;
+  const size_t bytes = (size_t)pl->R * nt * o.n * o.n * NQ * NQ * 2 * sizeof(float);
+  if (bytes > kPolyMaxBytes || poly_pack_lds(o) > pl->lds_limit) return GT_OK;
+  if (int rc = dev_alloc(&o.d_kpoly, bytes, nullptr)) return rc;
+  *ok = true;
+  return GT_OK;
+}
+
+// The default forward form per order: the polynomial gather when available, else the cell
+// gather when its items fill the lanes, else the sorted gather.
+static int setup_cell_gather(gt_plan *pl) {
+  for (int t = 1; t <= pl->ds; ++t) {
+    OrderHost &o = pl->ord[t];
+    o.path = GT_GATHER_SORTED;
+    if (o.term_end == o.term_begin) continue;
+    if (int rc = build_cell_items(pl, t, false, nullptr)) return rc;
+    if (o.citems.empty()) continue;
+    o.path = GT_GATHER_CELL;
+    if (t == 2) {
+      bool ok = false;
+      if (int rc = build_poly(pl, &ok)) return rc;
+      if (ok) o.path = GT_GATHER_POLY;
     }
   }
   return GT_OK;
 }
+
+}  // namespace
+
+// Selects a forward form for order t (building what it needs); GT_EUNSUPPORTED when the form
+// is not available for this plan.
+int gt::set_gather_path(gt_plan *pl, int t, int path) {
+  OrderHost &o = pl->ord[t];
+  drop_graphs(pl);
+  if (path == GT_GATHER_SORTED) {
+    o.path = path;
+    return GT_OK;
+  }
+  if (int rc = build_cell_items(pl, t, true, nullptr)) return rc;
+  if (o.citems.empty()) return fail(GT_EUNSUPPORTED, "no cell items for this order");
+  if (path == GT_GATHER_POLY) {
+    bool ok = false;
+    if (t != 2) return fail(GT_EUNSUPPORTED, "the polynomial gather is for order 2");
+    if (int rc = build_poly(pl, &ok)) return rc;
+    if (!ok) return fail(GT_EUNSUPPORTED, "the polynomial gather is not available for this plan");
+  }
+  o.path = path;
+  return GT_OK;
+}
+
+// Rebuilds the order-2 tile spread's work list for `waves_cu` resident wavefronts per compute
+// unit (the tuner's trials).
+int gt::set_tile_waves(gt_plan *pl, int waves_cu) {
+  OrderHost &o = pl->ord[2];
+  if (pl->ds < 2 || o.term_end == o.term_begin) return GT_OK;
+  drop_graphs(pl);
+  dev_free(o.d_waves2, nullptr);
+  dev_free(o.d_tileseg, nullptr);
+  dev_free(o.d_patch, nullptr);
+  dev_free(o.d_tsum, nullptr);
+  o.d_waves2 = o.d_tileseg = nullptr;
+  o.d_patch = o.d_tsum = nullptr;
+  o.waves_cu = waves_cu;
+  return setup_tile_spread(pl, o.cstart_host);
+}
+
+namespace {
 
 // Deconvolution factors, roots of unity and window polynomials of an order depend only on
 // (N, n, m, polynomial degree) (the shape b follows from N and n); their long-double
@@ -850,11 +922,12 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
     hipError_t e2 = hipStreamSynchronize(s);
     if (e2 != hipSuccess) rc = hip_fail(e2, "node binning");
   }
-  std::vector<int64_t> cstarts[kMaxOrder + 1];
   for (int t = 1; rc == GT_OK && t <= p->ds; ++t)
-    if (pl->ord[t].term_end > pl->ord[t].term_begin) rc = fetch_cell_starts(pl, t, s, cstarts[t]);
-  if (rc == GT_OK && p->ds >= 2 && pl->ord[2].term_end > pl->ord[2].term_begin) rc = setup_tile_spread(pl, cstarts[2]);
-  if (rc == GT_OK && p->ds >= 1) rc = setup_cell_gather(pl, cstarts, s);
+    if (pl->ord[t].term_end > pl->ord[t].term_begin) rc = fetch_cell_starts(pl, t, s, pl->ord[t].cstart_host);
+  if (rc == GT_OK && p->ds >= 2 && pl->ord[2].term_end > pl->ord[2].term_begin)
+    rc = setup_tile_spread(pl, pl->ord[2].cstart_host);
+  if (rc == GT_OK && p->ds >= 1) rc = setup_cell_gather(pl);
+  if (rc == GT_OK) rc = apply_cached_tuning(pl);
   if (rc) {
     free_plan(pl);
     return rc;
@@ -1043,6 +1116,7 @@ int gt_release_all(void) {
     std::lock_guard<std::mutex> lk(g_tab_mu);
     g_tab.clear();
   }
+  clear_tuning_cache();
   return GT_OK;
 }
 
@@ -1076,7 +1150,7 @@ int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path) {
   GT_LIVE(plan);
   if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
   const OrderHost &o = plan->ord[t];
-  if (path) *path = o.d_kpoly ? GT_GATHER_POLY : (!o.citems.empty() ? GT_GATHER_CELL : GT_GATHER_SORTED);
+  if (path) *path = o.path;
   return GT_OK;
 }
 
@@ -1084,16 +1158,54 @@ int gt_plan_trafo(gt_plan *plan, const void *fhat, void *f, void *stream) {
   GT_LIVE(plan);
   if (!fhat || !f) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
-  return plan->dtype == GT_C64 ? launch_forward<float>(plan, fhat, nullptr, f, (hipStream_t)stream)
-                               : launch_forward<double>(plan, fhat, nullptr, f, (hipStream_t)stream);
+  return run_plan_call(plan, 0, fhat, f, (hipStream_t)stream);
 }
 
 int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream) {
   GT_LIVE(plan);
   if (!fhat || !y) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
-  return plan->dtype == GT_C64 ? launch_adjoint<float>(plan, y, nullptr, fhat, (hipStream_t)stream)
-                               : launch_adjoint<double>(plan, y, nullptr, fhat, (hipStream_t)stream);
+  return run_plan_call(plan, 1, y, fhat, (hipStream_t)stream);
+}
+
+int gt_plan_tune(gt_plan *plan, void *stream) {
+  GT_LIVE(plan);
+  plan->stream = (hipStream_t)stream;
+  return tune_plan(plan, (hipStream_t)stream);
+}
+
+int64_t gt_plan_tuning(const gt_plan *plan, char *buf, int64_t len) {
+  if (!plan_is_live(plan)) return fail(GT_EINVAL, "not a live plan (destroyed or released)");
+  const std::string &js = plan->tuning.empty() ? std::string("{}") : plan->tuning;
+  if (buf && len > 0) {
+    const size_t nc = std::min<size_t>((size_t)len - 1, js.size());
+    memcpy(buf, js.data(), nc);
+    buf[nc] = 0;
+  }
+  return (int64_t)js.size() + 1;
+}
+
+int gt_plan_set_graph(gt_plan *plan, int32_t on) {
+  GT_LIVE(plan);
+  if (plan->stream) {
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  drop_graphs(plan);
+  plan->use_graph = on != 0;
+  return GT_OK;
+}
+
+int gt_plan_set_gather_path(gt_plan *plan, int32_t t, int32_t path) {
+  GT_LIVE(plan);
+  if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  if (path < GT_GATHER_SORTED || path > GT_GATHER_POLY) return fail(GT_EINVAL, "unknown gather form");
+  if (plan->ord[t].term_end == plan->ord[t].term_begin) return fail(GT_EINVAL, "the order has no terms");
+  if (plan->stream) {
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  return set_gather_path(plan, t, path);
 }
 
 int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, void *stream) {

@@ -1,0 +1,351 @@
+// Measured launch choices of a plan, and the plan's own graphs of a transform's launches.
+//
+// Several launch forms compute the same transform (they differ in rounding order only): the
+// forward gather of each order (GT_GATHER_SORTED / CELL / POLY), the resident wavefronts per
+// compute unit of the order-2 tile spread, whether order 1 runs on the plan's second stream,
+// and whether gt_plan_trafo / gt_plan_adjoint replay a captured graph instead of launching
+// eagerly.  gt_plan_tune times the candidates on the plan's own nodes with HIP events and keeps
+// the fastest; the choice is cached per device and problem signature, so that later plans of
+// the same signature (other node draws of one workload) start from it without timing.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "gt_internal.h"
+
+namespace gt {
+namespace {
+
+struct TuneKey {
+  int dev;
+  int32_t d, ds, R, dtype, basis, ragged, nterms;
+  int32_t N[kMaxOrder + 1], m[kMaxOrder + 1], n[kMaxOrder + 1];
+  int64_t Mtot;
+  uint64_t terms_hash;
+  bool operator==(const TuneKey &o) const { return memcmp(this, &o, sizeof(TuneKey)) == 0; }
+};
+
+struct TuneChoice {
+  int32_t path[kMaxOrder + 1];
+  int32_t waves_cu;
+  bool use_side, use_graph;
+  std::string report;
+};
+
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, TuneChoice>> g_tune;
+
+TuneKey key_of(const gt_plan *pl) {
+  TuneKey k;
+  memset(&k, 0, sizeof(k));   // padding bytes take part in the comparison
+  (void)hipGetDevice(&k.dev);
+  k.d = pl->d;
+  k.ds = pl->ds;
+  k.R = pl->R;
+  k.dtype = pl->dtype;
+  k.basis = pl->basis;
+  k.ragged = pl->ragged ? 1 : 0;
+  k.nterms = pl->nterms;
+  for (int t = 1; t <= pl->ds; ++t) {
+    k.N[t] = pl->ord[t].N;
+    k.m[t] = pl->ord[t].m;
+    k.n[t] = pl->ord[t].n;
+  }
+  k.Mtot = pl->Mtot;
+  uint64_t h = 1469598103934665603ull;   // FNV-1a over the terms' coordinate lists
+  for (const DevTerm &dt : pl->terms) {
+    const int32_t v[4] = {dt.t, dt.c0, dt.c1, dt.c2};
+    for (int i = 0; i < 4; ++i) {
+      h ^= (uint64_t)(uint32_t)v[i];
+      h *= 1099511628211ull;
+    }
+  }
+  k.terms_hash = h;
+  return k;
+}
+
+const char *path_name(int p) { return p == GT_GATHER_POLY ? "poly" : p == GT_GATHER_CELL ? "cell" : "sorted"; }
+
+int eager(gt_plan *pl, int dir, const void *in, void *out, hipStream_t s) {
+  if (pl->dtype == GT_C64)
+    return dir == 0 ? launch_forward<float>(pl, in, nullptr, out, s) : launch_adjoint<float>(pl, in, nullptr, out, s);
+  return dir == 0 ? launch_forward<double>(pl, in, nullptr, out, s) : launch_adjoint<double>(pl, in, nullptr, out, s);
+}
+
+// Buffers of the timing runs (contents irrelevant to the timing; cleared once).
+struct TuneBufs {
+  void *fhat = nullptr, *f = nullptr;
+  ~TuneBufs() {
+    dev_free(fhat, nullptr);
+    dev_free(f, nullptr);
+  }
+};
+
+// Mean milliseconds per call of `dirs` (bit 0 forward, bit 1 adjoint) over enough calls for
+// about 20 ms of work (at least 2, at most 50), after one untimed call.
+int time_calls(gt_plan *pl, int dirs, const TuneBufs &b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, double *ms) {
+  auto one = [&]() -> int {
+    if (dirs & 1)
+      if (int rc = run_plan_call(pl, 0, b.fhat, b.f, s)) return rc;
+    if (dirs & 2)
+      if (int rc = run_plan_call(pl, 1, b.f, b.fhat, s)) return rc;
+    return GT_OK;
+  };
+  if (int rc = one()) return rc;
+  GT_HIP(hipEventRecord(e0, s));
+  if (int rc = one()) return rc;
+  GT_HIP(hipEventRecord(e1, s));
+  GT_HIP(hipEventSynchronize(e1));
+  float t1 = 0;
+  GT_HIP(hipEventElapsedTime(&t1, e0, e1));
+  const int reps = std::max(2, std::min(50, (int)(20.0 / std::max(1e-3, (double)t1))));
+  GT_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i)
+    if (int rc = one()) return rc;
+  GT_HIP(hipEventRecord(e1, s));
+  GT_HIP(hipEventSynchronize(e1));
+  float tr = 0;
+  GT_HIP(hipEventElapsedTime(&tr, e0, e1));
+  *ms = (double)tr / reps;
+  return GT_OK;
+}
+
+// Frees what the forms an order did not keep were built with: the polynomial buffer unless the
+// order keeps the polynomial gather, the cell items when it keeps the sorted gather.
+void drop_unused(gt_plan *pl, int t) {
+  OrderHost &o = pl->ord[t];
+  if (o.path != GT_GATHER_POLY && o.d_kpoly) {
+    dev_free(o.d_kpoly, nullptr);
+    o.d_kpoly = nullptr;
+  }
+  if (o.path == GT_GATHER_SORTED && o.d_citems) {
+    dev_free(o.d_citems, nullptr);
+    o.d_citems = nullptr;
+    o.citems.clear();
+    o.citem_begin.clear();
+  }
+}
+
+// A cached choice on a new plan; a form this plan cannot take (no cell items for its nodes)
+// leaves the plan's default for that order.
+void apply(gt_plan *pl, const TuneChoice &c) {
+  for (int t = 1; t <= pl->ds; ++t) {
+    if (pl->ord[t].term_end == pl->ord[t].term_begin || pl->ord[t].path == c.path[t]) continue;
+    if (set_gather_path(pl, t, c.path[t]) == GT_OK)
+      drop_unused(pl, t);
+    else
+      set_error("");
+  }
+  if (pl->ds >= 2 && pl->ord[2].waves_cu != c.waves_cu && set_tile_waves(pl, c.waves_cu) != GT_OK) {
+    set_error("");
+    (void)set_tile_waves(pl, kTileWavesPerCU);
+  }
+  pl->use_side = c.use_side;
+  pl->use_graph = c.use_graph;
+}
+
+}  // namespace
+
+// (a graph may still run on the stream it was launched on, which the caller may since have
+// destroyed: wait for the device before destroying them)
+void drop_graphs(gt_plan *pl) {
+  if (pl->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto &g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+  pl->graphs.clear();
+}
+
+void clear_tuning_cache() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+// A new plan takes the cached choice of its signature, if any (no timing).
+int apply_cached_tuning(gt_plan *pl) {
+  const TuneKey k = key_of(pl);
+  TuneChoice c;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = std::find_if(g_tune.begin(), g_tune.end(), [&](const auto &e) { return e.first == k; });
+    if (it == g_tune.end()) return GT_OK;
+    c = it->second;
+  }
+  apply(pl, c);
+  pl->tuning = c.report;
+  return GT_OK;
+}
+
+// One transform through the plan's graph (captured on first use for these buffers) or eagerly.
+// A graph is not used on the legacy default stream, nor while the caller's stream is itself
+// being captured (then the caller's graph records the launches).
+int run_plan_call(gt_plan *pl, int dir, const void *in, void *out, hipStream_t s) {
+  if (!pl->use_graph || s == nullptr || prof_enabled()) return eager(pl, dir, in, out, s);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  GT_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return eager(pl, dir, in, out, s);
+  for (auto &g : pl->graphs)
+    if (g.dir == dir && g.in == in && g.out == out) {
+      GT_HIP(hipGraphLaunch(g.exec, s));
+      return GT_OK;
+    }
+  constexpr size_t kMaxGraphs = 8;
+  if (pl->graphs.size() >= kMaxGraphs) {
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(pl->graphs.front().exec);
+    pl->graphs.erase(pl->graphs.begin());
+  }
+  GT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  const int rc = eager(pl, dir, in, out, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc != GT_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != GT_OK ? rc : hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+  pl->graphs.push_back({dir, in, out, s, exec});
+  GT_HIP(hipGraphLaunch(exec, s));
+  return GT_OK;
+}
+
+int tune_plan(gt_plan *pl, hipStream_t s) {
+  if (s == nullptr) return fail(GT_EINVAL, "tuning needs a created stream (graph capture is not possible on the default stream)");
+  const size_t csz = 2 * pl->rsize;
+  TuneBufs b;
+  if (int rc = dev_alloc(&b.fhat, (size_t)pl->R * pl->ncoef * csz, nullptr)) return rc;
+  if (int rc = dev_alloc(&b.f, (size_t)pl->Vtot * csz, nullptr)) return rc;
+  GT_HIP(hipMemsetAsync(b.fhat, 0, (size_t)pl->R * pl->ncoef * csz, s));
+  GT_HIP(hipMemsetAsync(b.f, 0, (size_t)pl->Vtot * csz, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GT_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(GT_EHIP, "hipEventCreate");
+  }
+  drop_graphs(pl);
+  pl->use_graph = false;
+  std::string js = "{\"cached\": false";
+  char tmp[160];
+  int rc = GT_OK;
+  double fwd_ms = 0, adj_ms = 0, both_ms = 0;
+  // 1. forward gather per order (coordinate descent, order by order)
+  js += ", \"gather\": {";
+  for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+    OrderHost &o = pl->ord[t];
+    if (o.term_end == o.term_begin) continue;
+    const int keep = o.path;
+    int best = keep;
+    double best_ms = 1e300;
+    snprintf(tmp, sizeof(tmp), "%s\"%d\": {", t > 1 && js.back() != '{' ? ", " : "", t);
+    js += tmp;
+    bool first = true;
+    for (int p = GT_GATHER_SORTED; p <= GT_GATHER_POLY && rc == GT_OK; ++p) {
+      if (p == GT_GATHER_POLY && t != 2) continue;
+      if (set_gather_path(pl, t, p) != GT_OK) {
+        set_error("");
+        continue;
+      }
+      double ms = 0;
+      rc = time_calls(pl, 1, b, s, e0, e1, &ms);
+      if (rc != GT_OK) break;
+      snprintf(tmp, sizeof(tmp), "%s\"%s\": %.4f", first ? "" : ", ", path_name(p), ms);
+      js += tmp;
+      first = false;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = p;
+      }
+    }
+    if (rc == GT_OK) rc = set_gather_path(pl, t, best);
+    if (rc == GT_OK) drop_unused(pl, t);
+    snprintf(tmp, sizeof(tmp), ", \"chosen\": \"%s\"}", path_name(best));
+    js += tmp;
+  }
+  js += "}";
+  // 2. order-2 tile spread: resident wavefronts per compute unit (adjoint)
+  if (rc == GT_OK && pl->ds >= 2 && pl->ord[2].term_end > pl->ord[2].term_begin) {
+    OrderHost &o = pl->ord[2];
+    int best = o.waves_cu;
+    double best_ms = 1e300;
+    js += ", \"tile_waves_cu\": {";
+    bool first = true;
+    int last_wg = -1;
+    for (int w : {8, 12, 16, 20, 24, 28, 32}) {
+      if ((rc = set_tile_waves(pl, w)) != GT_OK) break;
+      if (o.tile_wg_cu == last_wg) continue;   // the staging LDS allows no more workgroups
+      last_wg = o.tile_wg_cu;
+      double ms = 0;
+      if ((rc = time_calls(pl, 2, b, s, e0, e1, &ms)) != GT_OK) break;
+      snprintf(tmp, sizeof(tmp), "%s\"%d\": %.4f", first ? "" : ", ", w, ms);
+      js += tmp;
+      first = false;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = w;
+      }
+    }
+    if (rc == GT_OK) rc = set_tile_waves(pl, best);
+    snprintf(tmp, sizeof(tmp), ", \"chosen\": %d}", best);
+    js += tmp;
+  }
+  // 3. second stream for order 1 on or off (forward + adjoint)
+  if (rc == GT_OK && pl->side && pl->ds >= 2) {
+    double on = 0, off = 0;
+    pl->use_side = true;
+    rc = time_calls(pl, 3, b, s, e0, e1, &on);
+    if (rc == GT_OK) {
+      pl->use_side = false;
+      rc = time_calls(pl, 3, b, s, e0, e1, &off);
+    }
+    pl->use_side = on <= off;
+    snprintf(tmp, sizeof(tmp), ", \"side_stream\": {\"on\": %.4f, \"off\": %.4f, \"chosen\": %s}", on, off,
+             pl->use_side ? "true" : "false");
+    js += tmp;
+  }
+  // 4. graph replay against eager launches (forward + adjoint)
+  if (rc == GT_OK) {
+    double eg = 0, gr = 0;
+    pl->use_graph = false;
+    rc = time_calls(pl, 3, b, s, e0, e1, &eg);
+    if (rc == GT_OK) {
+      pl->use_graph = true;
+      rc = time_calls(pl, 3, b, s, e0, e1, &gr);
+    }
+    pl->use_graph = rc == GT_OK && gr < eg;
+    drop_graphs(pl);   // the timing buffers' graphs
+    snprintf(tmp, sizeof(tmp), ", \"graph\": {\"eager\": %.4f, \"replay\": %.4f, \"chosen\": %s}", eg, gr,
+             pl->use_graph ? "true" : "false");
+    js += tmp;
+    both_ms = std::min(eg, rc == GT_OK ? gr : eg);
+  }
+  if (rc == GT_OK) rc = time_calls(pl, 1, b, s, e0, e1, &fwd_ms);
+  if (rc == GT_OK) rc = time_calls(pl, 2, b, s, e0, e1, &adj_ms);
+  drop_graphs(pl);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != GT_OK) return rc;
+  snprintf(tmp, sizeof(tmp), ", \"forward_ms\": %.4f, \"adjoint_ms\": %.4f, \"step_ms\": %.4f}", fwd_ms, adj_ms, both_ms);
+  js += tmp;
+  TuneChoice c;
+  for (int t = 0; t <= kMaxOrder; ++t) c.path[t] = t <= pl->ds ? pl->ord[t].path : GT_GATHER_SORTED;
+  c.waves_cu = pl->ds >= 2 ? pl->ord[2].waves_cu : kTileWavesPerCU;
+  c.use_side = pl->use_side;
+  c.use_graph = pl->use_graph;
+  pl->tuning = js;
+  c.report = js;
+  c.report.replace(0, strlen("{\"cached\": false"), "{\"cached\": true");
+  const TuneKey k = key_of(pl);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = std::find_if(g_tune.begin(), g_tune.end(), [&](const auto &e) { return e.first == k; });
+  if (it != g_tune.end())
+    it->second = c;
+  else
+    g_tune.push_back({k, c});
+  return GT_OK;
+}
+
+}  // namespace gt

@@ -31,6 +31,7 @@ EXPORTS = [
     "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
     "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc", "lsqr_solve_path", "gt_plan_lsqr_path",
+    "gt_plan_set_gather_path", "gt_plan_tune", "gt_plan_tuning", "gt_plan_set_graph",
 ]
 
 
@@ -90,6 +91,10 @@ def load(path: str = LIB_PATH):
         "gt_plan_node_grad": (C.c_int, [vp, vp, vp, vp, vp]),
         "gt_plan_order_info": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "gt_plan_gather_path": (C.c_int, [vp, i32, C.POINTER(i32)]),
+        "gt_plan_set_gather_path": (C.c_int, [vp, i32, i32]),
+        "gt_plan_tune": (C.c_int, [vp, vp]),
+        "gt_plan_tuning": (i64, [vp, C.c_char_p, i64]),
+        "gt_plan_set_graph": (C.c_int, [vp, i32]),
         "gt_plan_norm_estimate": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "gt_plan_norm_estimate_noalloc": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
@@ -356,6 +361,26 @@ class Plan:
         path = C.c_int32()
         _check(self._lib.gt_plan_gather_path(self.handle, int(t), C.byref(path)))
         return int(path.value)
+
+    def set_gather_path(self, t: int, path: int):
+        _check(self._lib.gt_plan_set_gather_path(self.handle, int(t), int(path)))
+
+    def tune(self, stream=None) -> dict:
+        """gt_plan_tune on `stream` (a created stream); returns the tuning report."""
+        _check(self._lib.gt_plan_tune(self.handle, _stream(stream)))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        import json
+        n = self._lib.gt_plan_tuning(self.handle, None, 0)
+        if n < 0:
+            _check(int(n))
+        buf = C.create_string_buffer(int(n))
+        self._lib.gt_plan_tuning(self.handle, buf, len(buf))
+        return json.loads(buf.value.decode() or "{}")
+
+    def set_graph(self, on: bool = True):
+        _check(self._lib.gt_plan_set_graph(self.handle, 1 if on else 0))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -114,6 +114,10 @@ def test_allocation_failure_hook_and_plan_handles_on_cpu():
     bogus = C.c_void_p(0x1000)       # never a plan; must not be dereferenced
     assert L.gt_plan_destroy(bogus) == lib.GT_EINVAL
     assert L.gt_plan_trafo(bogus, None, None, None) == lib.GT_EINVAL
+    assert L.gt_plan_tune(bogus, None) == lib.GT_EINVAL
+    assert L.gt_plan_tuning(bogus, None, 0) == lib.GT_EINVAL
+    assert L.gt_plan_set_graph(bogus, 1) == lib.GT_EINVAL
+    assert L.gt_plan_set_gather_path(bogus, 1, lib.GT_GATHER_SORTED) == lib.GT_EINVAL
     assert L.gt_plan_destroy(None) == lib.GT_OK
     assert L.gt_release_all() == lib.GT_OK
     pb, keepb = lib.make_problem(3, 2, [4, 4], M=4, dtype=lib.GT_C128, basis=7)
