@@ -39,6 +39,12 @@ def flops_per_node_term(order: int, m: int) -> int:
     return 4 * sum(w ** k for k in range(1, order + 1))
 
 
+def direct_flops_per_node_term(order: int, N: int, R: int) -> int:
+    """Algorithmic FLOPs of one node-term of the direct sums: (N - 1)^order complex MACs per
+    right-hand side, 8 flops each (the phases, computed on the vector units, not counted)."""
+    return 8 * (N - 1) ** order * R
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h"):
@@ -130,8 +136,10 @@ def run_solvers():
        reference solution), by doubling from 8 and then bisection (the error is taken to
        stay below TAU once it is).  FP32 batched has one K for the batch; FP64 plain one K
        per lambda.
-    3. On the clock: each form's calls at its K, wall time of the one-shot library calls
-       (plan creation included; each call synchronises).
+    3. On the clock: each form's solver calls at its K on plans built off the clock (one plan
+       per precision and batch size: FP32 with all lambda values, FP64 with one right-hand
+       side, reused by the per-lambda calls); each call synchronises.  Plan creation is
+       reported beside it, and the totals with plans as second figures.
     FISTA runs take one step constant for all, L = 1.05 x a 50-step FP64 power-iteration
     estimate of ||F||^2 computed once off the clock, with constant steps."""
     import torch
@@ -157,25 +165,38 @@ def run_solvers():
     out = {"workload": f"group-lasso shape: d={SD}, d_s={SDS}, N={SN[0]}/{SN[1]}, 79 terms, {ncoef} coefficients, "
                        f"M={SM} uniform nodes, target: 3 one- and 2 two-dimensional B-spline terms + 1% noise, "
                        f"{SR} lambda values", "tau": TAU, "fista_L": L,
-           "timing": "wall time of the one-shot library calls (plan + solve) at the smallest iteration count "
-                     "whose solution is within tau of the converged FP64 reference; counts found off the clock"}
+           "timing": "wall time of the solver calls on plans built off the clock, at the smallest iteration "
+                     "count whose solution is within tau of the converged FP64 reference (counts found off "
+                     "the clock); plan creation reported beside it"}
+    plans, tunings = {}, {}
+    out["tunings"] = tunings
+
+    def get_plan(prec, R):
+        if (prec, R) not in plans:
+            code = lib.GT_C64 if prec == "f32" else lib.GT_C128
+            prob, keep = lib.make_problem(SD, SDS, SN, M=SM, R=R, dtype=code)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl = lib.Plan(prob, xd[prec], keepalive=keep)
+            torch.cuda.synchronize()
+            plans[(prec, R)] = (pl, time.perf_counter() - t0)
+            tunings[f"{prec}_R{R}"] = pl.tune(torch.cuda.current_stream().cuda_stream)   # off the clock
+        return plans[(prec, R)][0]
 
     def solve(kind, prec, lam, iters, tol=0.0):
         R = len(lam)
-        code = lib.GT_C64 if prec == "f32" else lib.GT_C128
-        prob, keep = lib.make_problem(SD, SDS, SN, M=SM, R=R, dtype=code)
+        pl = get_plan(prec, R)
         cdt = torch.complex64 if prec == "f32" else torch.complex128
         yy = yd[prec].repeat(R)
         fh = torch.zeros(R * ncoef, dtype=cdt, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if kind == "fista":
-            info = lib.fista_group_lasso(prob, xd[prec], yy, lam, None, iters, L, 1.0, tol, fh)
+            info = pl.fista(yy, lam, None, iters, L, 1.0, tol, fh)
         else:
-            info = lib.lsqr_solve(prob, xd[prec], yy, lam, None, iters, tol, fh)
+            info = pl.lsqr(yy, lam, None, iters, tol, fh)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        del keep
         print(f"[bench]   {kind} {prec} R={R} iters={iters} {dt:.3f} s", file=sys.stderr, flush=True)
         return dt, fh.cpu().numpy().reshape(R, ncoef).astype(np.complex128), info
 
@@ -224,10 +245,15 @@ def run_solvers():
             dt, sj, _ = solve(kind, "f64", lam[j:j + 1], k64[j])
             t64 += dt
             e64 = max(e64, err(sj, [j]))
-        res.update({"fp32_batched": {"iters": k32, "s": t32, "max_rel_err": err(s32, every)},
-                    "fp64_plain": {"iters_per_lambda": k64, "s": t64, "max_rel_err": e64},
-                    "speedup": t64 / t32})
+        p32, p64 = plans[("f32", SR)][1], plans[("f64", 1)][1]
+        res.update({"fp32_batched": {"iters": k32, "s": t32, "max_rel_err": err(s32, every), "plan_s": p32,
+                                     "s_with_plan": t32 + p32},
+                    "fp64_plain": {"iters_per_lambda": k64, "s": t64, "max_rel_err": e64, "plan_s": p64,
+                                   "s_with_plan": t64 + p64, "s_with_plan_per_call": t64 + SR * p64},
+                    "speedup": t64 / t32, "speedup_with_plans": (t64 + p64) / (t32 + p32)})
         out[kind] = res
+    for pl, _ in plans.values():
+        pl.close()
     return out
 
 
@@ -278,6 +304,10 @@ def run_c3(steps: int, all_lambdas: bool):
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    tuning = plan.tune(stream.cuda_stream)     # launch forms measured on these nodes (off the clock)
+    tune_s = time.perf_counter() - t0
+    print(f"[bench]   c3 tuning R={CR}: {tune_s:.1f} s {json.dumps(tuning)}", file=sys.stderr, flush=True)
     plan.trafo(fd, f_out)
     plan.adjoint(yd, a_out)
 
@@ -307,14 +337,17 @@ def run_c3(steps: int, all_lambdas: bool):
     name, (cnt, tot) = max(kern.items(), key=lambda kv: kv[1][1])
     order = 2 if "2d" in name else (1 if "1d" in name else 3)
     from math import comb
-    fl = CM * comb(CD, order) * CR * flops_per_node_term(order, m3)
+    if name.startswith("direct"):   # MFMA contraction: useful flops per node-term and right-hand side
+        fl = CM * comb(CD, order) * direct_flops_per_node_term(order, CN[order - 1], CR)
+    else:
+        fl = CM * comb(CD, order) * CR * flops_per_node_term(order, m3)
     out["transform"] = {
-        "R": CR, "m": m3, "plan_s": plan_s, "steps": steps,
+        "R": CR, "m": m3, "plan_s": plan_s, "steps": steps, "tune_s": tune_s, "tuning": tuning,
         "fwd_adj": {"value": 2 * nt / (ms * 1e-3), "unit": "node-terms/s", "ms": ms},
         "forward": {"value": nt / (ms_f * 1e-3), "unit": "node-terms/s", "ms": ms_f},
         "adjoint": {"value": nt / (ms_a * 1e-3), "unit": "node-terms/s", "ms": ms_a},
         "kernels_ms": {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in sorted(kern.items())},
-        "roofline": {"bound": "alu", "kernel": name, "achieved": fl / (tot / cnt * 1e-3) / 1e12,
+        "roofline": {"bound": "mfma" if name.startswith("direct") else "alu", "kernel": name, "achieved": fl / (tot / cnt * 1e-3) / 1e12,
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": fl / (tot / cnt * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, "flops_per_launch": fl,
                      "avg_launch_ms": tot / cnt}}
@@ -332,6 +365,10 @@ def run_c3(steps: int, all_lambdas: bool):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plans[prec] = (lib.Plan(pp, xd_, keepalive=kk), time.perf_counter() - t0)
+    tunings = {}
+    for prec in plans:                         # off the clock, as the plans
+        tunings[prec] = plans[prec][0].tune(torch.cuda.current_stream().cuda_stream)
+        print(f"[bench]   c3 tuning lsqr plan {prec}: {json.dumps(tunings[prec])}", file=sys.stderr, flush=True)
     cdt = {"f32": torch.complex64, "f64": torch.complex128}
 
     def path_run(prec, K, tol=0.0):
@@ -414,10 +451,11 @@ def run_c3(steps: int, all_lambdas: bool):
                       "iters": int(max(i[0].iters for i in rinfo)), "tol": 1e-12, "s": ref_s,
                       "converged": all(bool(i[0].flags & lib.GT_SOLVE_CONVERGED) for i in rinfo)},
         "fp32_batched": {"form": "FP32, 16 lambda in one call, one shared bidiagonalisation", "iters": k32,
-                         "s": t32, "max_rel_err": float(e32.max()), "plan_s": plans["f32"][1]},
+                         "s": t32, "max_rel_err": float(e32.max()), "plan_s": plans["f32"][1],
+                         "tuning": tunings["f32"]},
         "fp64_plain": {"form": "FP64, one gt_plan_lsqr call per lambda", "lambdas_timed": timed_idx,
                        "iters_per_lambda": [k64[j] for j in timed_idx], "s": t64, "max_rel_err": max(e64),
-                       "plan_s": plans["f64"][1]},
+                       "plan_s": plans["f64"][1], "tuning": tunings["f64"]},
         "speedup": (t64 / len(timed_idx) * CR) / t32,
         "speedup_measured_only": t64 / t32,
         "note": ("speedup: FP64-plain time per lambda (timed lambda values) x 16 over the FP32 batched call; "

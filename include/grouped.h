@@ -161,35 +161,55 @@ int gt_plan_node_grad(gt_plan *plan, const void *fhat, const void *g, void *gx, 
 /* Window half-width m and FFT grid size n chosen for order t (1..ds); for reports. */
 int gt_plan_order_info(const gt_plan *plan, int32_t t, int32_t *m, int32_t *n);
 
-/* Which forward gather the plan uses for order t (1..ds); for reports and tests.  All three
- * compute the window sum of Definition def:skatoons via eq. somafm for every node of every
- * term of the order:
+/* Which forward form the plan uses for order t (1..ds); for reports and tests.  The first
+ * three compute the window sum of Definition def:skatoons via eq. somafm for every node of
+ * every term of the order; the fourth the defining sum itself:
  *   GT_GATHER_SORTED  runs of cell-sorted nodes, the term's grid staged in LDS;
  *   GT_GATHER_CELL    one wavefront per run of <= 64 nodes of one grid cell, the grid block as
  *                     scalar operands (when the cells hold enough nodes);
  *   GT_GATHER_POLY    order 2, FP32: per-cell coefficients of the window polynomials (built by
- *                     the forward pack), evaluated per node by Horner sums. */
-enum { GT_GATHER_SORTED = 0, GT_GATHER_CELL = 1, GT_GATHER_POLY = 2 };
+ *                     the forward pack), evaluated per node by Horner sums;
+ *   GT_GATHER_DIRECT  no window and no grid: sum_k fhat_k e^{2 pi i k.x_u} per node and term as
+ *                     a dense contraction on the matrix cores (exact up to rounding), summed over
+ *                     the order's terms in registers.  Shared nodes only, R <= 16, the group's
+ *                     coefficients and the nodes' phases within the LDS. */
+enum { GT_GATHER_SORTED = 0, GT_GATHER_CELL = 1, GT_GATHER_POLY = 2, GT_GATHER_DIRECT = 3 };
 int gt_plan_gather_path(const gt_plan *plan, int32_t t, int32_t *path);
 
-/* Selects the forward gather of order t (1..ds) by hand (GT_GATHER_*), building what that form
+/* Selects the forward form of order t (1..ds) by hand (GT_GATHER_*), building what that form
  * needs; synchronises the plan's last stream first.  GT_EUNSUPPORTED when the form is not
- * available for this plan (GT_GATHER_POLY: order 2, FP32, coefficient buffer <= 1 GiB). */
+ * available for this plan (GT_GATHER_POLY: order 2, FP32, coefficient buffer <= 1 GiB;
+ * GT_GATHER_DIRECT: as stated above). */
 int gt_plan_set_gather_path(gt_plan *plan, int32_t t, int32_t path);
+
+/* The adjoint's form for order t (1..ds):
+ *   GT_ADJ_WINDOW  spread onto the oversampled grid, adjoint FFT, deconvolution (Sec. 3, the
+ *                  adjoint display);
+ *   GT_ADJ_DIRECT  fhat_k = sum_v y_v e^{-2 pi i k.x_{v,u}} as a dense contraction on the matrix
+ *                  cores over node slices, the slices summed in a fixed order (exact up to
+ *                  rounding; shared nodes only, R <= 16, |I_u| <= 256).
+ * gt_plan_set_adjoint_form synchronises the plan's last stream and allocates the slice
+ * partials (at most 512 MiB); GT_EUNSUPPORTED when the form is not available. */
+enum { GT_ADJ_WINDOW = 0, GT_ADJ_DIRECT = 1 };
+int gt_plan_adjoint_form(const gt_plan *plan, int32_t t, int32_t *form);
+int gt_plan_set_adjoint_form(gt_plan *plan, int32_t t, int32_t form);
 
 /* ------------------------------------------------------------------ tuning and graphs
  * (not in the paper: launch choices among forms that compute the same product of
  * Definition def:skatoons and its adjoint, differing in rounding order only)
  *
- * gt_plan_tune times, on the plan's own nodes and with HIP events on `stream` (a created
- * stream, not the legacy default one), in this order:
- *   1. per order the forward gathers the plan can take (GT_GATHER_SORTED / CELL / POLY),
- *      keeping the fastest forward for each order in turn;
- *   2. order 2: the resident wavefronts per compute unit of the tile spread
- *      (8, 12, ..., 32, as the staging LDS allows), by the adjoint's time;
+ * gt_plan_tune times, on the plan's own nodes and with HIP events on `stream`, in this order:
+ *   1. per order the forward forms the plan can take (GT_GATHER_SORTED / CELL / POLY /
+ *      DIRECT), by the time of that order's kernels (launched one at a time with an event
+ *      pair each), keeping the fastest;
+ *   2. order 2: the resident wavefronts per compute unit of the tile spread (12, 20, 28, then
+ *      4 either side of the best, as the staging LDS allows), by the time of the order-2
+ *      adjoint kernels; then per order the adjoint forms (GT_ADJ_WINDOW / DIRECT), by the
+ *      time of that order's adjoint kernels;
  *   3. whether order 1 runs on the plan's second stream (forward + adjoint);
  *   4. whether gt_plan_trafo / gt_plan_adjoint launch eagerly or replay a graph of their
- *      launches captured by the plan (forward + adjoint).
+ *      launches captured by the plan (forward + adjoint; not on the legacy default stream,
+ *      where the plan never captures).
  * It allocates (and frees) one coefficient and one sample buffer for the timing runs, and
  * synchronises `stream`.  The choice is kept by the plan and cached per device and problem
  * signature (d, d_s, bandwidths, window widths, grid sizes, terms, R, node count, dtype,

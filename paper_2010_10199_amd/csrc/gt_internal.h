@@ -109,6 +109,9 @@ struct OrderHost {
   struct GatherItem *d_gitems = nullptr;
   std::vector<int32_t> gitem_begin;   // per term of the order, +1
   int32_t path = GT_GATHER_SORTED;    // forward form of this order (GT_GATHER_*)
+  int32_t adj_form = GT_ADJ_WINDOW;   // adjoint form of this order (GT_ADJ_*)
+  int32_t dir_nslice = 0;             // GT_ADJ_DIRECT: node slices of the adjoint's direct sums
+  void *d_dpart = nullptr;            // GT_ADJ_DIRECT: slice partials, terms x slices x 64 rtw x 16 reals
   int32_t waves_cu = kTileWavesPerCU; // order 2: resident wavefronts per compute unit of the tile spread
   std::vector<int64_t> cstart_host;   // the binning's cell starts (host copy, for work lists and the tuner)
   std::vector<CellItem> citems;       // cell gather work items (empty: k_gather_sorted is used)
@@ -222,6 +225,9 @@ int hip_fail(hipError_t e, const char *what);
 bool prof_enabled();
 void prof_begin(hipStream_t s, const char *name);
 void prof_end(hipStream_t s);
+bool prof_set(bool on);                                   // returns the previous state
+size_t prof_mark();                                       // records so far
+double prof_take_since(size_t mark, const char *suffix);  // ms of later records named *suffix; drops them
 
 // ---- plan construction helpers (plan.cpp) ----
 int validate_problem(const gt_problem *p);
@@ -267,6 +273,13 @@ bool plan_is_live(const gt_plan *pl);
 
 // tuning (tune.cpp / plan.cpp)
 int set_gather_path(gt_plan *pl, int t, int path);
+int set_adjoint_form(gt_plan *pl, int t, int form);
+// direct sums (direct.h): availability per order and direction, and the adjoint's row tiles
+// per wavefront (rows 2 |I_u| padded to 64 rtw; 0 when |I_u| > 256)
+bool direct_fwd_ok(const gt_plan *pl, int t);
+bool direct_adj_ok(const gt_plan *pl, int t);
+int direct_adj_rtw(const gt_plan *pl, int t);
+int direct_fwd_rtw(const gt_plan *pl, int t);
 int set_tile_waves(gt_plan *pl, int waves_cu);
 int apply_cached_tuning(gt_plan *pl);
 void clear_tuning_cache();

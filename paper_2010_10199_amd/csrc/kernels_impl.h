@@ -427,6 +427,7 @@ __global__ __launch_bounds__(256) void k_reduce_f(const cx_t<T> *__restrict__ fh
 }  // namespace gt
 #include "gather.h"   // K3 gather (binned, one slot per term)
 #include "spread.h"   // K4 spread (binned, MFMA)
+#include "direct.h"   // direct sums of small groups (MFMA), forward and adjoint
 namespace gt {
 
 // Empty-set coefficient fhat_empty(r) = sum_v y_v, in two launches: k_empty_part sums one
@@ -1107,20 +1108,113 @@ static int join_side(gt_plan *pl, hipStream_t s) {
   return GT_OK;
 }
 
+static DirectArgs direct_args(const gt_plan *pl, int t) {
+  DirectArgs da;
+  da.K = pl->ord[t].N - 1;
+  da.G = 1;
+  for (int a = 0; a < t; ++a) da.G *= da.K;
+  da.half = pl->ord[t].N / 2;
+  da.R = pl->R;
+  da.M = pl->M;
+  da.ncoef = pl->ncoef_int;
+  return da;
+}
+
+// Direct forward of order t: f += sum over the order's terms (after the window orders'
+// reduction, on the same stream).
+template <typename T>
+static int launch_direct_fwd(gt_plan *pl, int t, const void *fhat, const T *colscale, void *f, hipStream_t s) {
+  using C = cx_t<T>;
+  const OrderHost &o = pl->ord[t];
+  const DirectArgs da = direct_args(pl, t);
+  const int rtw = direct_fwd_rtw(pl, t), ct = pl->R <= 8 ? 1 : 2;
+  const size_t lds = ((size_t)da.G * 8 * ct + (size_t)t * da.K * 64 * rtw) * sizeof(C);
+  const int nb = 64 * rtw;
+  dim3 grid((unsigned)((pl->M + nb - 1) / nb));
+  prof_begin(s, t == 1 ? "direct_fwd_1d" : t == 2 ? "direct_fwd_2d" : "direct_fwd_3d");
+#define GT_LAUNCH_DF(ORD, CT, RTW)                                                                               \
+  {                                                                                                              \
+    if (int rc = set_lds(k_direct_fwd<T, ORD, CT, RTW>, lds)) return rc;                                         \
+    hipLaunchKernelGGL((k_direct_fwd<T, ORD, CT, RTW>), grid, dim3(256), lds, s, (const T *)pl->d_x, pl->d_terms, \
+                       o.term_begin, o.term_end, da, (const C *)fhat, colscale, (C *)f);                          \
+  }
+#define GT_LAUNCH_DF_O(ORD)                     \
+  {                                             \
+    if (ct == 1 && rtw == 2) GT_LAUNCH_DF(ORD, 1, 2) \
+    else if (ct == 1) GT_LAUNCH_DF(ORD, 1, 4)        \
+    else if (rtw == 2) GT_LAUNCH_DF(ORD, 2, 2)       \
+    else GT_LAUNCH_DF(ORD, 2, 4)                     \
+  }
+  if (t == 1) GT_LAUNCH_DF_O(1)
+  else if (t == 2) GT_LAUNCH_DF_O(2)
+  else GT_LAUNCH_DF_O(3)
+#undef GT_LAUNCH_DF_O
+#undef GT_LAUNCH_DF
+  prof_end(s);
+  return check_launch("k_direct_fwd");
+}
+
+// Direct adjoint of order t: slice partials, then their sums into the order's coefficients.
+template <typename T>
+static int launch_direct_adj(gt_plan *pl, int t, const void *y, const T *colscale, void *fhat, hipStream_t s) {
+  using C = cx_t<T>;
+  const OrderHost &o = pl->ord[t];
+  const DirectArgs da = direct_args(pl, t);
+  const int nt = o.term_end - o.term_begin, S = o.dir_nslice, rtw = direct_adj_rtw(pl, t);
+  if (!o.d_dpart || S < 1 || rtw < 1) return fail(GT_EINVAL, "direct adjoint not set up");
+  const size_t lds = (size_t)t * da.K * 64 * sizeof(C);
+  prof_begin(s, t == 1 ? "direct_adj_1d" : t == 2 ? "direct_adj_2d" : "direct_adj_3d");
+#define GT_LAUNCH_DA(ORD, RTW)                                                                                   \
+  {                                                                                                              \
+    if (int rc = set_lds(k_direct_adj<T, ORD, RTW>, lds)) return rc;                                             \
+    hipLaunchKernelGGL((k_direct_adj<T, ORD, RTW>), dim3((unsigned)S, (unsigned)nt), dim3(256), lds, s,          \
+                       (const T *)pl->d_x, pl->d_terms, o.term_begin, da, S, (const C *)y, (T *)o.d_dpart);      \
+  }
+#define GT_LAUNCH_DA_O(ORD)                              \
+  {                                                      \
+    if (rtw == 1) GT_LAUNCH_DA(ORD, 1)                   \
+    else if (rtw == 2) GT_LAUNCH_DA(ORD, 2)              \
+    else if (rtw == 4) GT_LAUNCH_DA(ORD, 4)              \
+    else GT_LAUNCH_DA(ORD, 8)                            \
+  }
+  if (t == 1) GT_LAUNCH_DA_O(1)
+  else if (t == 2) GT_LAUNCH_DA_O(2)
+  else GT_LAUNCH_DA_O(3)
+#undef GT_LAUNCH_DA_O
+#undef GT_LAUNCH_DA
+  if (int rc = check_launch("k_direct_adj")) return rc;
+  hipLaunchKernelGGL((k_direct_adj_sum<T>), dim3((unsigned)((da.G * da.R + 255) / 256), (unsigned)nt), dim3(256), 0, s,
+                     (const T *)o.d_dpart, pl->d_terms, o.term_begin, da, S, 64 * rtw, colscale, (C *)fhat);
+  prof_end(s);
+  return check_launch("k_direct_adj_sum");
+}
+
 template <typename T>
 static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
   if (ngi == 0) return launch_pack<T>(pl, fhat, colscale, s);
-  // terms 1..nterms-1 in blocks of nslots; each block: gathers into slots, then one reduction
+  // The window orders' terms, numbered 1..nt_all in term order without the direct orders'
+  // (position = term - dshift[t]), in blocks of nslots; each block: gathers into slots, then
+  // one reduction.  The direct orders add their sums afterwards.
+  int dshift[kMaxOrder + 1] = {0, 0, 0, 0};
+  int nt_all = 0;
+  for (int t = 1, nd = 0; t <= pl->ds; ++t) {
+    const OrderHost &o = pl->ord[t];
+    dshift[t] = nd;
+    if (o.path == GT_GATHER_DIRECT)
+      nd += o.term_end - o.term_begin;
+    else
+      nt_all += o.term_end - o.term_begin;
+  }
   const int S = std::max(1, pl->nslots);
-  const int nt_all = pl->nterms - 1;
   for (int g0 = 1, blk = 0; blk == 0 || g0 <= nt_all; g0 += S, ++blk) {
-    const int g1 = std::min(pl->nterms, g0 + S);
+    const int g1 = std::min(nt_all + 1, g0 + S);
     const bool fk = fork_side(pl, s);
     for (int t = 1; t <= pl->ds; ++t) {
       const hipStream_t st = (fk && t == 1) ? pl->side : s;
       const OrderHost &o = pl->ord[t];
+      if (o.path == GT_GATHER_DIRECT) continue;
       bool packed = false;
       if constexpr (std::is_same<T, float>::value) {
         if (blk == 0 && t == 2 && o.path == GT_GATHER_POLY) {   // order 2: pack straight into per-cell polynomials
@@ -1144,8 +1238,9 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
       }
       if (blk == 0 && !packed)
         if (int rc = launch_pack<T>(pl, fhat, colscale, st, t)) return rc;
-      const int tb = std::max(g0, o.term_begin), te = std::min(g1, o.term_end);
+      const int tb = std::max(g0 + dshift[t], o.term_begin), te = std::min(g1 + dshift[t], o.term_end);
       if (tb >= te) continue;
+      const int sbase = -(g0 + dshift[t]);   // slot of term u: u + sbase
       OrderParams<T> op = order_params<T>(pl, t);
       if (o.path != GT_GATHER_SORTED) {   // cell gather: one wavefront per run of a cell's nodes
         const int c0 = o.citem_begin[tb - o.term_begin], c1 = o.citem_begin[te - o.term_begin];
@@ -1156,7 +1251,7 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
         if constexpr (std::is_same<T, float>::value) {
           if (t == 2 && o.path == GT_GATHER_POLY) {
             hipLaunchKernelGGL((k_gather_poly2<T>), grid, dim3(256), 0, st, (const T *)o.d_xs, o.d_citems + c0,
-                               c1 - c0, o.d_perm, op, (const C *)o.d_kpoly, vstride, -g0,
+                               c1 - c0, o.d_perm, op, (const C *)o.d_kpoly, vstride, sbase,
                                (C *)pl->d_fpart, pl->Vtot);
             prof_end(st);
             if (int rc = check_launch("k_gather_poly2")) return rc;
@@ -1168,15 +1263,15 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
     if (t == 1)                                                                                                     \
       hipLaunchKernelGGL((k_gather_cell<T, 1, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
                          o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
-                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+                         vstride, sbase, (C *)pl->d_fpart, pl->Vtot);                                                 \
     else if (t == 2)                                                                                                \
       hipLaunchKernelGGL((k_gather_cell<T, 2, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
                          o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
-                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+                         vstride, sbase, (C *)pl->d_fpart, pl->Vtot);                                                 \
     else                                                                                                            \
       hipLaunchKernelGGL((k_gather_cell<T, 3, MH>), grid, dim3(256), 0, st, (const T *)pl->d_x, pl->Mtot,           \
                          o.d_citems + c0, c1 - c0, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, \
-                         vstride, -g0, (C *)pl->d_fpart, pl->Vtot);                                                 \
+                         vstride, sbase, (C *)pl->d_fpart, pl->Vtot);                                                 \
   }
         GT_DISPATCH_M(o.m, GT_LAUNCH_CELL)
 #undef GT_LAUNCH_CELL
@@ -1196,17 +1291,17 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
     if (t == 1) {                                                                                                 \
       if (int rc = set_lds(k_gather_sorted<T, 1, MH>, lds)) return rc;                                            \
       hipLaunchKernelGGL((k_gather_sorted<T, 1, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
-                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, sbase,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     } else if (t == 2) {                                                                                          \
       if (int rc = set_lds(k_gather_sorted<T, 2, MH>, lds)) return rc;                                            \
       hipLaunchKernelGGL((k_gather_sorted<T, 2, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
-                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, sbase,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     } else {                                                                                                      \
       if (int rc = set_lds(k_gather_sorted<T, 3, MH>, lds)) return rc;                                            \
       hipLaunchKernelGGL((k_gather_sorted<T, 3, MH>), grid, dim3(kGatherBS), lds, st, (const T *)pl->d_x, pl->Mtot, \
-                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, -g0,  \
+                         items, o.d_perm, pl->d_terms, op, (const C *)pl->d_grid, pl->grid_total, vstride, sbase,  \
                          (C *)pl->d_fpart, pl->Vtot);                                                            \
     }                                                                                                             \
   }
@@ -1224,6 +1319,9 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
     if (int rc = check_launch("k_reduce_f")) return rc;
     if (nt_all <= 0) break;
   }
+  for (int t = 1; t <= pl->ds; ++t)
+    if (pl->ord[t].path == GT_GATHER_DIRECT)
+      if (int rc = launch_direct_fwd<T>(pl, t, fhat, colscale, f, s)) return rc;
   return GT_OK;
 }
 
@@ -1249,6 +1347,10 @@ static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fha
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     const int nsi = (int)o.sitems.size();
+    if (nt > 0 && o.adj_form == GT_ADJ_DIRECT) {
+      if (int rc = launch_direct_adj<T>(pl, t, y, colscale, fhat, st)) return rc;
+      continue;
+    }
     if (nt == 0 || (t == 2 ? o.nwaves2 == 0 : nsi == 0)) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     SpreadArgs sa;
@@ -1297,7 +1399,7 @@ static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fha
     const hipStream_t st = (fk && t == 1) ? pl->side : s;
     const OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
-    if (nt == 0) continue;
+    if (nt == 0 || o.adj_form == GT_ADJ_DIRECT) continue;
     OrderParams<T> op = order_params<T>(pl, t);
     // order 2: the adjoint DFT stages the column-folded patches in LDS when they fit
     const size_t lds_h = t == 2 ? (size_t)o.ntile * 16 * o.n * sizeof(C) : 0;

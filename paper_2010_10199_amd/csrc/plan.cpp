@@ -75,6 +75,43 @@ void prof_end(hipStream_t s) {
   g_prof_open = -1;
 }
 
+bool prof_set(bool on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  const bool was = g_prof_on;
+  g_prof_on = on;
+  return was;
+}
+
+size_t prof_mark() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof.size();
+}
+
+// Milliseconds of the records made since `mark` whose names end in `suffix` (waits for them),
+// and removes those records.
+double prof_take_since(size_t mark, const char *suffix) {
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (mark < g_prof.size()) {
+      recs.assign(g_prof.begin() + (std::ptrdiff_t)mark, g_prof.end());
+      g_prof.resize(mark);
+    }
+  }
+  const size_t ls = strlen(suffix);
+  double ms = 0;
+  for (auto &r : recs) {
+    float t = 0;
+    const size_t ln = strlen(r.name);
+    if (ln >= ls && strcmp(r.name + ln - ls, suffix) == 0 && hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&t, r.a, r.b) == hipSuccess)
+      ms += t;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  return ms;
+}
+
 // ------------------------------------------------------------------ device allocation
 // Allocation-failure hook (gt_debug_fail_alloc): when armed with k >= 1, the k-th device
 // allocation from then on fails with GT_ENOMEM as if the device were out of memory.
@@ -346,6 +383,7 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_tileseg, nullptr);
     dev_free(o.d_patch, nullptr);
     dev_free(o.d_tsum, nullptr);
+    dev_free(o.d_dpart, nullptr);
   }
   delete pl;
 }
@@ -536,10 +574,71 @@ static int setup_cell_gather(gt_plan *pl) {
 
 // Selects a forward form for order t (building what it needs); GT_EUNSUPPORTED when the form
 // is not available for this plan.
+// Direct sums (direct.h): shared nodes, at most 16 right-hand sides (the columns of the
+// contraction).  Forward LDS: the group's coefficients (G x 8 CT) and the phases of the
+// workgroup's 64 rtw nodes (order x K each; rtw = 4 row tiles per wavefront when that
+// leaves room for two workgroups, else 2); adjoint: |I_u| <= 256 (rows 2 G in at most 8 row
+// tiles per wavefront), samples (64 x 16) and the phases of 64 nodes.
+static int64_t group_size(const gt_plan *pl, int t) {
+  int64_t G = 1;
+  for (int a = 0; a < t; ++a) G *= pl->ord[t].N - 1;
+  return G;
+}
+static size_t direct_fwd_lds(const gt_plan *pl, int t, int rtw) {
+  const int CT = pl->R <= 8 ? 1 : 2;
+  return ((size_t)group_size(pl, t) * 8 * CT + (size_t)t * (pl->ord[t].N - 1) * 64 * rtw) * 2 * pl->rsize;
+}
+int gt::direct_fwd_rtw(const gt_plan *pl, int t) {
+  return direct_fwd_lds(pl, t, 4) <= pl->lds_limit / 2 ? 4 : 2;
+}
+bool gt::direct_fwd_ok(const gt_plan *pl, int t) {
+  return !pl->ragged && pl->R <= 16 && t >= 1 && t <= pl->ds && pl->ord[t].term_end > pl->ord[t].term_begin &&
+         direct_fwd_lds(pl, t, 2) <= pl->lds_limit;
+}
+int gt::direct_adj_rtw(const gt_plan *pl, int t) {
+  const int64_t rows = 2 * group_size(pl, t);
+  return rows <= 64 ? 1 : rows <= 128 ? 2 : rows <= 256 ? 4 : rows <= 512 ? 8 : 0;
+}
+bool gt::direct_adj_ok(const gt_plan *pl, int t) {
+  if (pl->ragged || pl->R > 16 || t < 1 || t > pl->ds || pl->ord[t].term_end == pl->ord[t].term_begin) return false;
+  const size_t lds = ((size_t)64 * 16 + (size_t)t * (pl->ord[t].N - 1) * 64) * 2 * pl->rsize;
+  return direct_adj_rtw(pl, t) > 0 && lds <= pl->lds_limit;
+}
+
+int gt::set_adjoint_form(gt_plan *pl, int t, int form) {
+  OrderHost &o = pl->ord[t];
+  drop_graphs(pl);
+  if (form == GT_ADJ_WINDOW) {
+    o.adj_form = form;
+    return GT_OK;
+  }
+  if (!direct_adj_ok(pl, t)) return fail(GT_EUNSUPPORTED, "the direct adjoint is not available for this order");
+  if (!o.d_dpart) {
+    // node slices: about eight rounds of resident workgroups over the order's terms, at least
+    // 1024 nodes per slice, partials within 512 MiB
+    const int64_t nt = o.term_end - o.term_begin;
+    const int64_t rows = 64 * direct_adj_rtw(pl, t);
+    const int64_t per_slice = nt * rows * 16 * (int64_t)pl->rsize;
+    int64_t S = (8 * 8 * (int64_t)pl->num_cu + nt - 1) / nt;
+    S = std::min<int64_t>(S, std::max<int64_t>(1, pl->M / 1024));
+    S = std::min<int64_t>(S, std::max<int64_t>(1, (int64_t(512) << 20) / per_slice));
+    S = std::max<int64_t>(1, std::min<int64_t>(S, 65535));
+    if (int rc = dev_alloc(&o.d_dpart, (size_t)(per_slice * S), nullptr)) return rc;
+    o.dir_nslice = (int32_t)S;
+  }
+  o.adj_form = form;
+  return GT_OK;
+}
+
 int gt::set_gather_path(gt_plan *pl, int t, int path) {
   OrderHost &o = pl->ord[t];
   drop_graphs(pl);
   if (path == GT_GATHER_SORTED) {
+    o.path = path;
+    return GT_OK;
+  }
+  if (path == GT_GATHER_DIRECT) {
+    if (!direct_fwd_ok(pl, t)) return fail(GT_EUNSUPPORTED, "the direct forward is not available for this order");
     o.path = path;
     return GT_OK;
   }
@@ -1196,10 +1295,29 @@ int gt_plan_set_graph(gt_plan *plan, int32_t on) {
   return GT_OK;
 }
 
+int gt_plan_adjoint_form(const gt_plan *plan, int32_t t, int32_t *form) {
+  GT_LIVE(plan);
+  if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  if (form) *form = plan->ord[t].adj_form;
+  return GT_OK;
+}
+
+int gt_plan_set_adjoint_form(gt_plan *plan, int32_t t, int32_t form) {
+  GT_LIVE(plan);
+  if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
+  if (form != GT_ADJ_WINDOW && form != GT_ADJ_DIRECT) return fail(GT_EINVAL, "unknown adjoint form");
+  if (plan->ord[t].term_end == plan->ord[t].term_begin) return fail(GT_EINVAL, "the order has no terms");
+  if (plan->stream) {
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  return set_adjoint_form(plan, t, form);
+}
+
 int gt_plan_set_gather_path(gt_plan *plan, int32_t t, int32_t path) {
   GT_LIVE(plan);
   if (t < 1 || t > plan->ds) return fail(GT_EINVAL, "no such order in plan");
-  if (path < GT_GATHER_SORTED || path > GT_GATHER_POLY) return fail(GT_EINVAL, "unknown gather form");
+  if (path < GT_GATHER_SORTED || path > GT_GATHER_DIRECT) return fail(GT_EINVAL, "unknown gather form");
   if (plan->ord[t].term_end == plan->ord[t].term_begin) return fail(GT_EINVAL, "the order has no terms");
   if (plan->stream) {
     hipError_t e = hipStreamSynchronize(plan->stream);

@@ -28,6 +28,7 @@ struct TuneKey {
 
 struct TuneChoice {
   int32_t path[kMaxOrder + 1];
+  int32_t adj[kMaxOrder + 1];
   int32_t waves_cu;
   bool use_side, use_graph;
   std::string report;
@@ -65,7 +66,9 @@ TuneKey key_of(const gt_plan *pl) {
   return k;
 }
 
-const char *path_name(int p) { return p == GT_GATHER_POLY ? "poly" : p == GT_GATHER_CELL ? "cell" : "sorted"; }
+const char *path_name(int p) {
+  return p == GT_GATHER_DIRECT ? "direct" : p == GT_GATHER_POLY ? "poly" : p == GT_GATHER_CELL ? "cell" : "sorted";
+}
 
 int eager(gt_plan *pl, int dir, const void *in, void *out, hipStream_t s) {
   if (pl->dtype == GT_C64)
@@ -82,8 +85,9 @@ struct TuneBufs {
   }
 };
 
-// Mean milliseconds per call of `dirs` (bit 0 forward, bit 1 adjoint) over enough calls for
-// about 20 ms of work (at least 2, at most 50), after one untimed call.
+// Mean milliseconds per call of `dirs` (bit 0 forward, bit 1 adjoint): one timed call; when
+// it took less than 20 ms (a first call may include loading code), one more untimed call and
+// then enough timed calls for about 20 ms of work (2 to 50).
 int time_calls(gt_plan *pl, int dirs, const TuneBufs &b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, double *ms) {
   auto one = [&]() -> int {
     if (dirs & 1)
@@ -92,13 +96,17 @@ int time_calls(gt_plan *pl, int dirs, const TuneBufs &b, hipStream_t s, hipEvent
       if (int rc = run_plan_call(pl, 1, b.f, b.fhat, s)) return rc;
     return GT_OK;
   };
-  if (int rc = one()) return rc;
   GT_HIP(hipEventRecord(e0, s));
   if (int rc = one()) return rc;
   GT_HIP(hipEventRecord(e1, s));
   GT_HIP(hipEventSynchronize(e1));
   float t1 = 0;
   GT_HIP(hipEventElapsedTime(&t1, e0, e1));
+  if (t1 >= 20.0f) {
+    *ms = (double)t1;
+    return GT_OK;
+  }
+  if (int rc = one()) return rc;
   const int reps = std::max(2, std::min(50, (int)(20.0 / std::max(1e-3, (double)t1))));
   GT_HIP(hipEventRecord(e0, s));
   for (int i = 0; i < reps; ++i)
@@ -111,6 +119,39 @@ int time_calls(gt_plan *pl, int dirs, const TuneBufs &b, hipStream_t s, hipEvent
   return GT_OK;
 }
 
+// Milliseconds per call of the kernels of order t in direction dir (0 forward, 1 adjoint):
+// the calls launch eagerly on one stream with an event pair per launch, and the launches whose
+// names end in "_<t>d" are summed (pack, gather or direct sums; spread, fold, adjoint DFT or
+// direct sums).  One call; when the order took less than 5 ms, one untimed call and then
+// enough calls for about 20 ms (2 to 20).
+int time_order(gt_plan *pl, int dir, int t, const TuneBufs &b, hipStream_t s, double *ms) {
+  char suffix[8];
+  snprintf(suffix, sizeof(suffix), "_%dd", t);
+  const bool was = prof_set(true);
+  auto calls = [&](int n, double *out) -> int {
+    const size_t mark = prof_mark();
+    for (int i = 0; i < n; ++i) {
+      const int rc = dir == 0 ? run_plan_call(pl, 0, b.fhat, b.f, s) : run_plan_call(pl, 1, b.f, b.fhat, s);
+      if (rc != GT_OK) {
+        (void)prof_take_since(mark, suffix);
+        return rc;
+      }
+    }
+    *out = prof_take_since(mark, suffix) / n;
+    return GT_OK;
+  };
+  double t1 = 0;
+  int rc = calls(1, &t1);
+  if (rc == GT_OK && t1 < 5.0) {
+    double warm = 0;
+    rc = calls(1, &warm);
+    if (rc == GT_OK) rc = calls(std::max(2, std::min(20, (int)(20.0 / std::max(1e-3, t1)))), &t1);
+  }
+  prof_set(was);
+  *ms = t1;
+  return rc;
+}
+
 // Frees what the forms an order did not keep were built with: the polynomial buffer unless the
 // order keeps the polynomial gather, the cell items when it keeps the sorted gather.
 void drop_unused(gt_plan *pl, int t) {
@@ -119,7 +160,7 @@ void drop_unused(gt_plan *pl, int t) {
     dev_free(o.d_kpoly, nullptr);
     o.d_kpoly = nullptr;
   }
-  if (o.path == GT_GATHER_SORTED && o.d_citems) {
+  if ((o.path == GT_GATHER_SORTED || o.path == GT_GATHER_DIRECT) && o.d_citems) {
     dev_free(o.d_citems, nullptr);
     o.d_citems = nullptr;
     o.citems.clear();
@@ -140,6 +181,10 @@ void apply(gt_plan *pl, const TuneChoice &c) {
   if (pl->ds >= 2 && pl->ord[2].waves_cu != c.waves_cu && set_tile_waves(pl, c.waves_cu) != GT_OK) {
     set_error("");
     (void)set_tile_waves(pl, kTileWavesPerCU);
+  }
+  for (int t = 1; t <= pl->ds; ++t) {
+    if (pl->ord[t].term_end == pl->ord[t].term_begin || pl->ord[t].adj_form == c.adj[t]) continue;
+    if (set_adjoint_form(pl, t, c.adj[t]) != GT_OK) set_error("");
   }
   pl->use_side = c.use_side;
   pl->use_graph = c.use_graph;
@@ -213,7 +258,6 @@ int run_plan_call(gt_plan *pl, int dir, const void *in, void *out, hipStream_t s
 }
 
 int tune_plan(gt_plan *pl, hipStream_t s) {
-  if (s == nullptr) return fail(GT_EINVAL, "tuning needs a created stream (graph capture is not possible on the default stream)");
   const size_t csz = 2 * pl->rsize;
   TuneBufs b;
   if (int rc = dev_alloc(&b.fhat, (size_t)pl->R * pl->ncoef * csz, nullptr)) return rc;
@@ -243,14 +287,14 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
     snprintf(tmp, sizeof(tmp), "%s\"%d\": {", t > 1 && js.back() != '{' ? ", " : "", t);
     js += tmp;
     bool first = true;
-    for (int p = GT_GATHER_SORTED; p <= GT_GATHER_POLY && rc == GT_OK; ++p) {
+    for (int p = GT_GATHER_SORTED; p <= GT_GATHER_DIRECT && rc == GT_OK; ++p) {
       if (p == GT_GATHER_POLY && t != 2) continue;
       if (set_gather_path(pl, t, p) != GT_OK) {
         set_error("");
         continue;
       }
       double ms = 0;
-      rc = time_calls(pl, 1, b, s, e0, e1, &ms);
+      rc = time_order(pl, 0, t, b, s, &ms);
       if (rc != GT_OK) break;
       snprintf(tmp, sizeof(tmp), "%s\"%s\": %.4f", first ? "" : ", ", path_name(p), ms);
       js += tmp;
@@ -273,13 +317,15 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
     double best_ms = 1e300;
     js += ", \"tile_waves_cu\": {";
     bool first = true;
-    int last_wg = -1;
-    for (int w : {8, 12, 16, 20, 24, 28, 32}) {
-      if ((rc = set_tile_waves(pl, w)) != GT_OK) break;
-      if (o.tile_wg_cu == last_wg) continue;   // the staging LDS allows no more workgroups
-      last_wg = o.tile_wg_cu;
+    std::vector<int> tried_wg;   // workgroups per compute unit already timed
+    // coarse 12, 20, 28; then the neighbours 4 apart of the best
+    auto trial = [&](int w) -> int {
+      if (w < 8 || w > 32) return GT_OK;
+      if (int r2 = set_tile_waves(pl, w)) return r2;
+      if (std::find(tried_wg.begin(), tried_wg.end(), o.tile_wg_cu) != tried_wg.end()) return GT_OK;
+      tried_wg.push_back(o.tile_wg_cu);   // (the staging LDS may allow no more workgroups)
       double ms = 0;
-      if ((rc = time_calls(pl, 2, b, s, e0, e1, &ms)) != GT_OK) break;
+      if (int r2 = time_order(pl, 1, 2, b, s, &ms)) return r2;
       snprintf(tmp, sizeof(tmp), "%s\"%d\": %.4f", first ? "" : ", ", w, ms);
       js += tmp;
       first = false;
@@ -287,10 +333,43 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
         best_ms = ms;
         best = w;
       }
-    }
+      return GT_OK;
+    };
+    for (int w : {12, 20, 28})
+      if (rc == GT_OK) rc = trial(w);
+    const int coarse = best;
+    if (rc == GT_OK) rc = trial(coarse - 4);
+    if (rc == GT_OK) rc = trial(coarse + 4);
     if (rc == GT_OK) rc = set_tile_waves(pl, best);
     snprintf(tmp, sizeof(tmp), ", \"chosen\": %d}", best);
     js += tmp;
+  }
+  // 2b. adjoint form per order (window or direct sums)
+  if (rc == GT_OK) {
+    js += ", \"adjoint\": {";
+    bool firsto = true;
+    for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+      OrderHost &o = pl->ord[t];
+      if (o.term_end == o.term_begin || !direct_adj_ok(pl, t)) continue;
+      double ms[2] = {0, 0};
+      for (int f = GT_ADJ_WINDOW; f <= GT_ADJ_DIRECT && rc == GT_OK; ++f) {
+        if ((rc = set_adjoint_form(pl, t, f)) != GT_OK) break;
+        rc = time_order(pl, 1, t, b, s, &ms[f]);
+      }
+      if (rc != GT_OK) break;
+      const int best = ms[GT_ADJ_DIRECT] < ms[GT_ADJ_WINDOW] ? GT_ADJ_DIRECT : GT_ADJ_WINDOW;
+      rc = set_adjoint_form(pl, t, best);
+      if (best == GT_ADJ_WINDOW && o.d_dpart) {
+        dev_free(o.d_dpart, nullptr);
+        o.d_dpart = nullptr;
+        o.dir_nslice = 0;
+      }
+      snprintf(tmp, sizeof(tmp), "%s\"%d\": {\"window\": %.4f, \"direct\": %.4f, \"chosen\": \"%s\"}",
+               firsto ? "" : ", ", t, ms[0], ms[1], best == GT_ADJ_DIRECT ? "direct" : "window");
+      js += tmp;
+      firsto = false;
+    }
+    js += "}";
   }
   // 3. second stream for order 1 on or off (forward + adjoint)
   if (rc == GT_OK && pl->side && pl->ds >= 2) {
@@ -306,8 +385,12 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
              pl->use_side ? "true" : "false");
     js += tmp;
   }
-  // 4. graph replay against eager launches (forward + adjoint)
-  if (rc == GT_OK) {
+  // 4. graph replay against eager launches (forward + adjoint); not on the legacy default
+  //    stream, where the plan does not capture
+  if (rc == GT_OK && s == nullptr) {
+    pl->use_graph = false;
+    js += ", \"graph\": \"not on the default stream\"";
+  } else if (rc == GT_OK) {
     double eg = 0, gr = 0;
     pl->use_graph = false;
     rc = time_calls(pl, 3, b, s, e0, e1, &eg);
@@ -328,10 +411,14 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != GT_OK) return rc;
+  if (both_ms == 0) both_ms = fwd_ms + adj_ms;
   snprintf(tmp, sizeof(tmp), ", \"forward_ms\": %.4f, \"adjoint_ms\": %.4f, \"step_ms\": %.4f}", fwd_ms, adj_ms, both_ms);
   js += tmp;
   TuneChoice c;
-  for (int t = 0; t <= kMaxOrder; ++t) c.path[t] = t <= pl->ds ? pl->ord[t].path : GT_GATHER_SORTED;
+  for (int t = 0; t <= kMaxOrder; ++t) {
+    c.path[t] = t <= pl->ds ? pl->ord[t].path : GT_GATHER_SORTED;
+    c.adj[t] = t <= pl->ds ? pl->ord[t].adj_form : GT_ADJ_WINDOW;
+  }
   c.waves_cu = pl->ds >= 2 ? pl->ord[2].waves_cu : kTileWavesPerCU;
   c.use_side = pl->use_side;
   c.use_graph = pl->use_graph;

@@ -20,7 +20,8 @@ GT_OK, GT_EINVAL, GT_ENOMEM, GT_EHIP, GT_EUNSUPPORTED = 0, -1, -2, -3, -4
 GT_C64, GT_C128 = 1, 2
 GT_MAX_ORDER = 3
 GT_SOLVE_CONVERGED, GT_SOLVE_MAX_ITER, GT_SOLVE_BREAKDOWN, GT_SOLVE_BACKTRACK_CAP = 1, 2, 4, 8
-GT_GATHER_SORTED, GT_GATHER_CELL, GT_GATHER_POLY = 0, 1, 2
+GT_GATHER_SORTED, GT_GATHER_CELL, GT_GATHER_POLY, GT_GATHER_DIRECT = 0, 1, 2, 3
+GT_ADJ_WINDOW, GT_ADJ_DIRECT = 0, 1
 GT_BASIS_EXP, GT_BASIS_COS = 0, 1
 
 # every symbol include/grouped.h declares
@@ -31,7 +32,8 @@ EXPORTS = [
     "gt_sensitivity", "gt_active_set", "gt_last_error", "gt_prof_enable", "gt_prof_report", "gt_version",
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
     "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc", "lsqr_solve_path", "gt_plan_lsqr_path",
-    "gt_plan_set_gather_path", "gt_plan_tune", "gt_plan_tuning", "gt_plan_set_graph",
+    "gt_plan_set_gather_path", "gt_plan_tune", "gt_plan_tuning", "gt_plan_set_graph", "gt_plan_adjoint_form",
+    "gt_plan_set_adjoint_form",
 ]
 
 
@@ -92,6 +94,8 @@ def load(path: str = LIB_PATH):
         "gt_plan_order_info": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "gt_plan_gather_path": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "gt_plan_set_gather_path": (C.c_int, [vp, i32, i32]),
+        "gt_plan_adjoint_form": (C.c_int, [vp, i32, C.POINTER(i32)]),
+        "gt_plan_set_adjoint_form": (C.c_int, [vp, i32, i32]),
         "gt_plan_tune": (C.c_int, [vp, vp]),
         "gt_plan_tuning": (i64, [vp, C.c_char_p, i64]),
         "gt_plan_set_graph": (C.c_int, [vp, i32]),
@@ -364,6 +368,15 @@ class Plan:
 
     def set_gather_path(self, t: int, path: int):
         _check(self._lib.gt_plan_set_gather_path(self.handle, int(t), int(path)))
+
+    def adjoint_form(self, t: int) -> int:
+        """GT_ADJ_WINDOW / GT_ADJ_DIRECT for order t."""
+        form = C.c_int32()
+        _check(self._lib.gt_plan_adjoint_form(self.handle, int(t), C.byref(form)))
+        return int(form.value)
+
+    def set_adjoint_form(self, t: int, form: int):
+        _check(self._lib.gt_plan_set_adjoint_form(self.handle, int(t), int(form)))
 
     def tune(self, stream=None) -> dict:
         """gt_plan_tune on `stream` (a created stream); returns the tuning report."""

@@ -21,7 +21,8 @@ CASES = [
     ("cells-3d-R2", 3, 3, (4, 4, 4), 30000, 2),
     ("order2-d5", 5, 2, (16, 8), 20000, 1),
 ]
-NAMES = {lib.GT_GATHER_SORTED: "sorted", lib.GT_GATHER_CELL: "cell", lib.GT_GATHER_POLY: "poly"}
+NAMES = {lib.GT_GATHER_SORTED: "sorted", lib.GT_GATHER_CELL: "cell", lib.GT_GATHER_POLY: "poly",
+         lib.GT_GATHER_DIRECT: "direct"}
 
 
 def _setup(case, prec):
@@ -66,7 +67,7 @@ def test_every_gather_form(case, prec):
     iset, x, fhat, y, plan, bufs, ref_f, ref_a = _setup(case, prec)
     s = torch.cuda.Stream()
     for t in range(1, ds + 1):
-        for path in (lib.GT_GATHER_SORTED, lib.GT_GATHER_CELL, lib.GT_GATHER_POLY):
+        for path in (lib.GT_GATHER_SORTED, lib.GT_GATHER_CELL, lib.GT_GATHER_POLY, lib.GT_GATHER_DIRECT):
             if path == lib.GT_GATHER_POLY and (t != 2 or prec == "f64"):
                 with pytest.raises(lib.GroupedError) as e:
                     plan.set_gather_path(t, path)
@@ -76,6 +77,109 @@ def test_every_gather_form(case, prec):
             assert plan.gather_path(t) == path
             f, a = _run(plan, bufs, s.cuda_stream, R, M, iset.n_coeffs)
             _check_both(f"order {t} {NAMES[path]}", f, a, fhat, y, ref_f, ref_a, prec, ds)
+    for t in range(1, ds + 1):
+        for form in (lib.GT_ADJ_DIRECT, lib.GT_ADJ_WINDOW):
+            plan.set_adjoint_form(t, form)
+            assert plan.adjoint_form(t) == form
+            f, a = _run(plan, bufs, s.cuda_stream, R, M, iset.n_coeffs)
+            _check_both(f"order {t} adjoint form {form}", f, a, fhat, y, ref_f, ref_a, prec, ds)
+    plan.close()
+
+
+# (name, d, ds, N, M, R): every order direct in both directions.  Right-hand sides 1, 9
+# (two column blocks, padded) and 16; groups from 3 to 225 frequencies (the adjoint's row
+# tiles per wavefront 1 to 8); node counts with a ragged last chunk.
+DIRECT_CASES = [
+    ("d5-N12-6-4-R1", 5, 3, (12, 6, 4), 1500, 1),
+    ("d4-N32-16-R9", 4, 2, (32, 16), 2100, 9),
+    ("d6-N8-8-6-R16", 6, 3, (8, 8, 6), 1300, 16),
+    ("d3-N2-2-2-R3", 3, 3, (2, 2, 2), 700, 3),
+]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("case", DIRECT_CASES, ids=[c[0] for c in DIRECT_CASES])
+def test_direct_forms_match_oracle(case, prec):
+    import torch
+    name, d, ds, N, M, R = case
+    say(f"[direct] {name} {prec}")
+    cid = 60 + DIRECT_CASES.index(case)
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = W.uniform_nodes(W.rng(cid, W.P_NODES), M, d, prec)
+    fhat = W.complex_normal(W.rng(cid, W.P_COEFFS), (R, iset.n_coeffs), prec)
+    y = W.complex_normal(W.rng(cid, W.P_SAMPLES), (R, M), prec)
+    p, keep = lib.make_problem(d, ds, N, M=M, R=R, dtype=dtype_code(prec))
+    plan = lib.Plan(p, to_dev(x), keepalive=keep)
+    for t in range(1, ds + 1):
+        plan.set_gather_path(t, lib.GT_GATHER_DIRECT)
+        plan.set_adjoint_form(t, lib.GT_ADJ_DIRECT)
+    ct = torch.complex64 if prec == "f32" else torch.complex128
+    bufs = dict(fhat=to_dev(fhat.reshape(-1)), y=to_dev(y.reshape(-1)),
+                f=torch.empty(R * M, dtype=ct, device="cuda"), a=torch.empty(R * iset.n_coeffs, dtype=ct, device="cuda"))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    f, a = _run(plan, bufs, s.cuda_stream, R, M, iset.n_coeffs)
+    _check_both("direct", f, a, fhat, y, otr.forward(iset, x, fhat), otr.adjoint(iset, x, y), prec, ds)
+    plan.close()
+
+
+def test_direct_forms_availability():
+    """Ragged datasets, more than 16 right-hand sides and (adjoint) groups of more than 256
+    frequencies keep the window forms."""
+    import torch
+    d, ds, M = 3, 2, 400
+    x = W.uniform_nodes(W.rng(70, W.P_NODES), M, d, "f32")
+    for kw, fwd_ok, adj_ok in (
+            (dict(N=(8, 18), M=M, R=1), True, False),            # order 2: 17^2 = 289 frequencies
+            (dict(N=(8, 8), M=M, R=17), False, False),
+            (dict(N=(8, 8), M=0, R=2, offsets=[0, 150, M]), False, False)):
+        p, keep = lib.make_problem(d, ds, kw["N"], M=kw["M"], R=kw["R"], dtype=lib.GT_C64, offsets=kw.get("offsets"))
+        plan = lib.Plan(p, to_dev(x), keepalive=keep)
+        for want, call in ((fwd_ok, lambda: plan.set_gather_path(2, lib.GT_GATHER_DIRECT)),
+                           (adj_ok, lambda: plan.set_adjoint_form(2, lib.GT_ADJ_DIRECT))):
+            if want:
+                call()
+            else:
+                with pytest.raises(lib.GroupedError) as e:
+                    call()
+                assert e.value.code == lib.GT_EUNSUPPORTED
+        plan.close()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_weighted_lsqr_on_direct_forms(prec):
+    """LSQR with Sobolev weights (the column scale enters both direct kernels) on a plan whose
+    orders all use the direct sums, against the oracle's twelfth iterate: 1e-10 in FP64 (as
+    the window forms' iterate test), 1e-3 in FP32 (the iteration carries the transforms'
+    rounding along; a sanity bar, the kernels are the same templates as in FP64)."""
+    import torch
+    from oracle import lsqr as olsqr
+    d, ds, N, M, R = 4, 3, (10, 6, 4), 2500, 2
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = W.uniform_nodes(W.rng(71, W.P_NODES), M, d, prec)
+    y1 = W.complex_normal(W.rng(71, W.P_SAMPLES), (M,), prec)
+    K = iset.full_frequencies()
+    omega = np.prod((1.0 + np.abs(K)) ** 0.5, axis=1)
+    lambdas = [0.5, 20.0]
+    p, keep = lib.make_problem(d, ds, N, M=M, R=R, dtype=dtype_code(prec))
+    plan = lib.Plan(p, to_dev(x), keepalive=keep)
+    for t in range(1, ds + 1):
+        plan.set_gather_path(t, lib.GT_GATHER_DIRECT)
+        plan.set_adjoint_form(t, lib.GT_ADJ_DIRECT)
+    ct = torch.complex64 if prec == "f32" else torch.complex128
+    out = torch.empty(R * iset.n_coeffs, dtype=ct, device="cuda")
+    iters = 12
+    plan.lsqr(to_dev(np.tile(y1, R)), lambdas, to_dev(omega), iters, 0.0, out)
+    torch.cuda.synchronize()
+    fg = out.cpu().numpy().astype(np.complex128).reshape(R, -1)
+    bar = 1e-10 if prec == "f64" else 1e-3
+    for r, lam in enumerate(lambdas):
+        ref = olsqr.lsqr(lambda v: otr.forward(iset, x, v), lambda q: otr.adjoint(iset, x, q), y1, iset.n_coeffs,
+                         lam, omega, iters)
+        e = float(np.linalg.norm(fg[r] - ref.fhat) / np.linalg.norm(ref.fhat))
+        say(f"  lsqr direct {prec} lambda={lam}: rel {e:.3e} (bar {bar:.0e})")
+        assert e <= bar
     plan.close()
 
 
