@@ -774,7 +774,9 @@ def run_autograd(steps: int = 10):
     respect to the coefficients and the nodes.  (a) Whole steps through the
     torch.autograd.Function (a plan per forward: node sort included); (b) the three passes
     (forward, adjoint, node gradient) on one plan; (c) forward + coefficient gradient with
-    GroupedTrafoFixedNodes (one plan for all steps).  Rates in node-terms/s of the passes."""
+    GroupedTrafoFixedNodes (one plan for all steps); (d) whole steps with
+    GroupedTrafoMovingNodes, the nodes moved by a small descent step each time (one plan,
+    its nodes re-binned on the device per step).  Rates in node-terms/s of the passes."""
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
@@ -818,6 +820,27 @@ def run_autograd(steps: int = 10):
     torch.cuda.synchronize()
     t_fixed = (time.perf_counter() - t0) / steps
     fixed.close()
+    # (d) nodes moving every step on one plan: GroupedTrafoMovingNodes (device re-binning)
+    from paper_2010_10199_amd.autograd import GroupedTrafoMovingNodes
+    moving = GroupedTrafoMovingNodes(x, d, ds, N, offsets=offs)
+    xm, fm = x.clone().requires_grad_(True), fh.clone().requires_grad_(True)
+
+    def step_moving():
+        f = moving(fm, xm)
+        (torch.conj(v) * f).real.sum().backward()
+        with torch.no_grad():                     # a descent step on the nodes: they move
+            xm.add_(xm.grad, alpha=-1e-9)
+            xm.grad = None
+
+    for _ in range(2):
+        step_moving()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_moving()
+    torch.cuda.synchronize()
+    t_moving = (time.perf_counter() - t0) / steps
+    moving.close()
     p, keep = lib.make_problem(d, ds, N, M=0, R=B, dtype=lib.GT_C64, offsets=offs)
     plan = lib.Plan(p, x, keepalive=keep)
     f = torch.empty(Mt, dtype=torch.complex64, device="cuda")
@@ -835,16 +858,23 @@ def run_autograd(steps: int = 10):
         times[name] = (time.perf_counter() - t0) / steps
     plan.close()
     nt = Mt * nterms
+    passes = sum(times.values())
     return {"workload": f"ragged: {B} datasets, {Mt} nodes, d={d}, d_s={ds}, N={N[0]}/{N[1]}, {nterms} terms, "
                         f"{nc} coefficients per dataset, FP32",
             "autograd_step_ms": t_step * 1e3,
             "autograd_node_terms_per_s": 3 * nt / t_step,
+            "moving_nodes_step_ms": t_moving * 1e3,
+            "moving_nodes_node_terms_per_s": 3 * nt / t_moving,
+            "moving_over_fixed_plan_passes": t_moving / passes,
             "fixed_nodes_step_ms": t_fixed * 1e3,
             "fixed_nodes_node_terms_per_s": 2 * nt / t_fixed,
             "plan_passes_ms": {k: t * 1e3 for k, t in times.items()},
             "plan_passes_node_terms_per_s": {k: nt / t for k, t in times.items()},
             "note": "autograd steps build a plan (node sort) per forward and count three passes (forward, "
-                    "adjoint, node gradient); fixed-nodes steps reuse one plan and count two (forward, adjoint)"}
+                    "adjoint, node gradient); moving-nodes steps move one plan's nodes (device re-binning) "
+                    "before the same three passes, and moving_over_fixed_plan_passes compares them with the "
+                    "three passes on a plan whose nodes stay; fixed-nodes steps reuse one plan and count two "
+                    "(forward, adjoint)"}
 
 
 def cpu_baseline(sample_nodes: int):

@@ -194,6 +194,19 @@ enum { GT_ADJ_WINDOW = 0, GT_ADJ_DIRECT = 1 };
 int gt_plan_adjoint_form(const gt_plan *plan, int32_t t, int32_t *form);
 int gt_plan_set_adjoint_form(gt_plan *plan, int32_t t, int32_t form);
 
+/* New positions for a plan's nodes (not in the paper: for callers whose nodes move between
+ * transforms, e.g. descent on the nodes with gt_plan_node_grad).  x: device, the layout and
+ * count given at creation (Mtot x d, the plan's real type); datasets, bandwidths, forms and
+ * everything else stay.  The plan keeps its memory and tables: the nodes are wrapped and
+ * checked (one synchronisation of `stream`), re-binned on the device, and the order-2 tile
+ * spread's work list is rebuilt on the device, with no further host round trip.  Orders whose
+ * forward used GT_GATHER_CELL or GT_GATHER_POLY (work items built on the host from the node
+ * positions) take GT_GATHER_SORTED; gt_plan_tune or gt_plan_set_gather_path may choose again.
+ * The first update allocates the re-binning scratch (kept until the plan is destroyed) and
+ * sizes the tile patches for any positions.  Captured graphs are dropped.  NaN or Inf nodes
+ * give GT_EINVAL and leave the plan's nodes undefined until the next successful update. */
+int gt_plan_update_nodes(gt_plan *plan, const void *x, void *stream);
+
 /* ------------------------------------------------------------------ tuning and graphs
  * (not in the paper: launch choices among forms that compute the same product of
  * Definition def:skatoons and its adjoint, differing in rounding order only)

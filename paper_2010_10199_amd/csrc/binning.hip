@@ -91,7 +91,182 @@ __global__ void k_sorted_coords(const T *__restrict__ xT, int64_t Mtot, const De
   xs[2 * pos + 1] = xT[(int64_t)tm.c1 * Mtot + node];
 }
 
+// Order-2 tile spread work list after a re-binning (gt_plan_update_nodes).  The wavefronts
+// keep their runs [qa, qb) of sorted positions, which depend only on the node counts per
+// (term, dataset); what moves with the nodes is which tiles a run meets.  One workgroup:
+//   1. per wavefront the non-empty tiles its run meets (the tiles ending after qa and
+//      starting before qb), counted into segcnt;
+//   2. an exclusive scan of the counts gives each wavefront's first patch segment
+//      (waves[4w + 2]); the total closes tileseg;
+//   3. each wavefront numbers its tiles' segments again and enters, for the tiles whose first
+//      position lies in its run (it is the first wavefront to meet them), the tile's first
+//      segment into tileseg;
+//   4. tiles without nodes (still -1) take the first segment of the next tile that has nodes
+//      (over all terms and datasets in order, the total after the last): a backward fill in
+//      1024 chunks with the carry between chunks.
+// waves: nwaves x {qa, qb, first segment, dataset}; cstart absolute positions per key (term
+// tl's keys start at (tl B + b) nkey; tile t of a (term, dataset) spans keys t TT ..).
+__global__ __launch_bounds__(1024) void k_tile_relist(int32_t *__restrict__ waves, int nwaves,
+                                                      const int64_t *__restrict__ cstart, int64_t Mtot, int B,
+                                                      int64_t nkey, int ntiles, int TT, int64_t ntiles_all,
+                                                      int32_t *__restrict__ segcnt, int32_t *__restrict__ tileseg) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x;
+  auto tiles_of = [&](int w, int64_t &key0, int &t0, int64_t &qa, int64_t &qb) {
+    qa = waves[4 * w];
+    qb = waves[4 * w + 1];
+    const int b = waves[4 * w + 3];
+    const int64_t tl = qa / Mtot;
+    key0 = (tl * B + b) * nkey;
+    int lo = 0, hi = ntiles;   // first tile whose end lies after qa
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cstart[key0 + (int64_t)(mid + 1) * TT] <= qa) lo = mid + 1; else hi = mid;
+    }
+    t0 = lo;
+  };
+  for (int64_t i = tid; i < ntiles_all; i += 1024) tileseg[i] = -1;
+  for (int w = tid; w < nwaves; w += 1024) {
+    int64_t key0, qa, qb;
+    int t0;
+    tiles_of(w, key0, t0, qa, qb);
+    int c = 0;
+    for (int t = t0; t < ntiles && cstart[key0 + (int64_t)t * TT] < qb; ++t)
+      if (cstart[key0 + (int64_t)(t + 1) * TT] > cstart[key0 + (int64_t)t * TT]) ++c;
+    segcnt[w] = c;
+  }
+  __syncthreads();
+  // 2. exclusive scan: chunk sums, scan of the 1024 sums in LDS, then the chunks
+  const int per = (nwaves + 1023) / 1024;
+  const int w0 = tid * per, w1 = min(nwaves, w0 + per);
+  int32_t sum = 0;
+  for (int w = w0; w < w1; ++w) sum += segcnt[w];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = part[tid] - sum;   // exclusive prefix of this chunk
+  for (int w = w0; w < w1; ++w) {
+    waves[4 * w + 2] = run;
+    run += segcnt[w];
+  }
+  const int32_t total = part[1023];
+  __syncthreads();
+  // 3. first segment of each tile, entered by the first wavefront meeting it
+  for (int w = tid; w < nwaves; w += 1024) {
+    int64_t key0, qa, qb;
+    int t0;
+    tiles_of(w, key0, t0, qa, qb);
+    int32_t seg = waves[4 * w + 2];
+    const int64_t tb0 = key0 / TT;   // (tl B + b) ntiles
+    for (int t = t0; t < ntiles && cstart[key0 + (int64_t)t * TT] < qb; ++t) {
+      const int64_t c0 = cstart[key0 + (int64_t)t * TT];
+      if (cstart[key0 + (int64_t)(t + 1) * TT] <= c0) continue;   // no nodes
+      if (c0 >= qa) tileseg[tb0 + t] = seg;
+      ++seg;
+    }
+  }
+  __syncthreads();
+  // 4. backward fill: chunk c holds entries [c per2, (c + 1) per2)
+  const int64_t per2 = (ntiles_all + 1023) / 1024;
+  const int64_t a0 = tid * per2, a1 = min(ntiles_all, a0 + per2);
+  int32_t first = -1;   // first set entry of the chunk
+  for (int64_t i = a0; i < a1; ++i)
+    if (tileseg[i] >= 0) {
+      first = tileseg[i];
+      break;
+    }
+  part[tid] = first;
+  __syncthreads();
+  if (tid == 0) {   // carry: the first set entry to the right of each chunk
+    int32_t next = total;
+    for (int c = 1023; c >= 0; --c) {
+      const int32_t f = part[c];
+      part[c] = next;
+      if (f >= 0) next = f;
+    }
+  }
+  __syncthreads();
+  int32_t next = part[tid];
+  for (int64_t i = a1 - 1; i >= a0; --i) {
+    if (tileseg[i] < 0)
+      tileseg[i] = next;
+    else
+      next = tileseg[i];
+  }
+  if (tid == 0) tileseg[ntiles_all] = total;
+}
+
 }  // namespace
+
+int launch_tile_relist(gt_plan *pl, hipStream_t s) {
+  OrderHost &o = pl->ord[2];
+  if (pl->ds < 2 || o.term_end == o.term_begin || o.nwaves2 == 0) return GT_OK;
+  const int B = pl->ragged ? pl->R : 1;
+  const int64_t ntiles_all = (int64_t)(o.term_end - o.term_begin) * B * o.ntile * o.ntile;
+  hipLaunchKernelGGL(k_tile_relist, dim3(1), dim3(1024), 0, s, o.d_waves2, o.nwaves2, (const int64_t *)o.d_cstart,
+                     pl->Mtot, B, o.nkey, o.ntile * o.ntile, o.ts * o.ts, ntiles_all, pl->rebin.segcnt,
+                     o.d_tileseg);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GT_OK : hip_fail(e, "k_tile_relist");
+}
+
+// Key batches of one order: terms in batches bounded to ~2^26 (term, node) pairs.
+static int bin_batch_terms(const gt_plan *pl, int t) {
+  const int nt = pl->ord[t].term_end - pl->ord[t].term_begin;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 26) / std::max<int64_t>(1, pl->Mtot)));
+}
+
+static int bin_end_bit(const gt_plan *pl, int t) {
+  const OrderHost &o = pl->ord[t];
+  const int B = pl->ragged ? pl->R : 1;
+  const int64_t K = (int64_t)(o.term_end - o.term_begin) * B * o.nkey;
+  int end_bit = 1;
+  while ((int64_t(1) << end_bit) <= K) ++end_bit;
+  return end_bit;
+}
+
+// The launches of one order's binning into o.d_perm, o.d_cstart (and o.d_xs for order 2),
+// given key/value scratch for one batch and the sort's temporary storage (no allocation, no
+// synchronisation).
+template <typename T>
+static int bin_order(gt_plan *pl, int t, hipStream_t s, const int64_t *d_offs, uint32_t *kin, uint32_t *kout,
+                     int32_t *vin, void *tmp, size_t tmp_bytes) {
+  OrderHost &o = pl->ord[t];
+  const int B = pl->ragged ? pl->R : 1;
+  const int nt = o.term_end - o.term_begin;
+  const int64_t Mtot = pl->Mtot, nkey = o.nkey;
+  const int tpb = bin_batch_terms(pl, t), end_bit = bin_end_bit(pl, t);
+  for (int tl0 = 0; tl0 < nt; tl0 += tpb) {
+    const int tl1 = std::min(nt, tl0 + tpb);
+    const int64_t cnt = (int64_t)(tl1 - tl0) * Mtot;
+    hipLaunchKernelGGL((k_bin_keys<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const T *)pl->d_x,
+                       Mtot, pl->d_terms, o.term_begin, tl0, tl1, t, o.n, o.ts, o.ntile, nkey, B, d_offs, kin, vin);
+    size_t tb = tmp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, o.d_perm + (int64_t)tl0 * Mtot,
+                                                       (int)cnt, 0, end_bit, s);
+    if (e != hipSuccess) return hip_fail(e, "radix sort");
+    const uint32_t k0 = (uint32_t)((int64_t)tl0 * B * nkey);
+    const uint32_t k1 = (uint32_t)((int64_t)tl1 * B * nkey);   // inclusive end key (start of next batch)
+    const int64_t nk = (int64_t)k1 - k0 + 1;
+    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, kout, cnt, k0, k1,
+                       (int64_t)tl0 * Mtot, o.d_cstart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "binning kernels");
+  }
+  if (t == 2) {
+    const int64_t cnt = (int64_t)nt * Mtot;
+    hipLaunchKernelGGL((k_sorted_coords<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       (const T *)pl->d_x, Mtot, pl->d_terms, o.term_begin, nt, o.d_perm, (T *)o.d_xs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "sorted coordinates");
+  }
+  return GT_OK;
+}
 
 template <typename T>
 int launch_binning(gt_plan *pl, hipStream_t s) {
@@ -111,19 +286,15 @@ int launch_binning(gt_plan *pl, hipStream_t s) {
     OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
     if (nt == 0) continue;
-    const int64_t nkey = o.nkey;
-    const int64_t K = (int64_t)nt * B * nkey;
+    const int64_t K = (int64_t)nt * B * o.nkey;
     if (K >= (int64_t(1) << 32) - 1 || (int64_t)nt * Mtot >= (int64_t(1) << 31)) {
       rc = fail(GT_EUNSUPPORTED, "too many terms x nodes for 32-bit binning keys");
       break;
     }
     if ((rc = dev_alloc((void **)&o.d_perm, (size_t)nt * Mtot * sizeof(int32_t), s))) break;
     if ((rc = dev_alloc((void **)&o.d_cstart, (size_t)(K + 1) * sizeof(int64_t), s))) break;
-    int end_bit = 1;
-    while ((int64_t(1) << end_bit) <= K) ++end_bit;
-    // batches of terms bounded to ~2^26 pairs
-    const int tpb = (int)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 26) / std::max<int64_t>(1, Mtot)));
-    const int64_t cap = (int64_t)tpb * Mtot;
+    if (t == 2 && (rc = dev_alloc(&o.d_xs, (size_t)nt * Mtot * 2 * sizeof(T), s))) break;
+    const int64_t cap = (int64_t)bin_batch_terms(pl, t) * Mtot;
     uint32_t *kin = nullptr, *kout = nullptr;
     int32_t *vin = nullptr;
     void *tmp = nullptr;
@@ -137,39 +308,10 @@ int launch_binning(gt_plan *pl, hipStream_t s) {
       break;
     }
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, kin, kout, vin, o.d_perm, (int)cap, 0,
-                                                       end_bit, s);
+                                                       bin_end_bit(pl, t), s);
     if (e == hipSuccess) rc = dev_alloc(&tmp, tmp_bytes, s);
     else rc = hip_fail(e, "radix sort sizing");
-    for (int tl0 = 0; tl0 < nt && rc == GT_OK; tl0 += tpb) {
-      const int tl1 = std::min(nt, tl0 + tpb);
-      const int64_t cnt = (int64_t)(tl1 - tl0) * Mtot;
-      hipLaunchKernelGGL((k_bin_keys<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const T *)pl->d_x,
-                         Mtot, pl->d_terms, o.term_begin, tl0, tl1, t, o.n, o.ts, o.ntile, nkey, B,
-                         (const int64_t *)d_offs, kin, vin);
-      size_t tb = tmp_bytes;
-      e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, o.d_perm + (int64_t)tl0 * Mtot, (int)cnt, 0,
-                                             end_bit, s);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "radix sort");
-        break;
-      }
-      const uint32_t k0 = (uint32_t)((int64_t)tl0 * B * nkey);
-      const uint32_t k1 = (uint32_t)((int64_t)tl1 * B * nkey);   // inclusive end key (start of next batch)
-      const int64_t nk = (int64_t)k1 - k0 + 1;
-      hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, kout, cnt, k0, k1,
-                         (int64_t)tl0 * Mtot, o.d_cstart);
-      e = hipGetLastError();
-      if (e != hipSuccess) rc = hip_fail(e, "binning kernels");
-    }
-    if (rc == GT_OK && t == 2) {
-      if ((rc = dev_alloc(&o.d_xs, (size_t)nt * Mtot * 2 * sizeof(T), s)) == GT_OK) {
-        const int64_t cnt = (int64_t)nt * Mtot;
-        hipLaunchKernelGGL((k_sorted_coords<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
-                           (const T *)pl->d_x, Mtot, pl->d_terms, o.term_begin, nt, o.d_perm, (T *)o.d_xs);
-        e = hipGetLastError();
-        if (e != hipSuccess) rc = hip_fail(e, "sorted coordinates");
-      }
-    }
+    if (rc == GT_OK) rc = bin_order<T>(pl, t, s, d_offs, kin, kout, vin, tmp, tmp_bytes);
     // keep the buffers alive until the stream has used them
     (void)hipStreamSynchronize(s);
     dev_free(tmp, s);
@@ -184,7 +326,50 @@ int launch_binning(gt_plan *pl, hipStream_t s) {
   return rc;
 }
 
+// Re-binning after gt_plan_update_nodes: the same launches into the plan's existing perm,
+// cell starts and sorted coordinates, with scratch kept by the plan from its first update on
+// (allocated then, sized for the largest order's key batch); no synchronisation.
+template <typename T>
+int launch_rebin(gt_plan *pl, hipStream_t s) {
+  RebinScratch &sc = pl->rebin;
+  if (!sc.ready) {
+    int64_t cap = 1;
+    size_t tmp_bytes = 0;
+    for (int t = 1; t <= pl->ds; ++t) {
+      const OrderHost &o = pl->ord[t];
+      if (o.term_end == o.term_begin) continue;
+      const int64_t c = (int64_t)bin_batch_terms(pl, t) * pl->Mtot;
+      cap = std::max(cap, c);
+      size_t tb = 0;
+      hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)c, 0,
+                                                         bin_end_bit(pl, t), s);
+      if (e != hipSuccess) return hip_fail(e, "radix sort sizing");
+      tmp_bytes = std::max(tmp_bytes, tb);
+    }
+    int rc;
+    if ((rc = dev_alloc((void **)&sc.kin, cap * sizeof(uint32_t), s)) ||
+        (rc = dev_alloc((void **)&sc.kout, cap * sizeof(uint32_t), s)) ||
+        (rc = dev_alloc((void **)&sc.vin, cap * sizeof(int32_t), s)) || (rc = dev_alloc(&sc.tmp, tmp_bytes, s)))
+      return rc;
+    if (pl->ragged) {
+      if ((rc = dev_alloc((void **)&sc.offs, pl->offs.size() * sizeof(int64_t), s))) return rc;
+      hipError_t e = hipMemcpy(sc.offs, pl->offs.data(), pl->offs.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "binning offsets");
+    }
+    sc.tmp_bytes = tmp_bytes;
+    sc.ready = true;
+  }
+  for (int t = 1; t <= pl->ds; ++t) {
+    if (pl->ord[t].term_end == pl->ord[t].term_begin) continue;
+    if (int rc = bin_order<T>(pl, t, s, sc.offs, sc.kin, sc.kout, sc.vin, sc.tmp, sc.tmp_bytes)) return rc;
+  }
+  return GT_OK;
+}
+
 template int launch_binning<float>(gt_plan *, hipStream_t);
 template int launch_binning<double>(gt_plan *, hipStream_t);
+template int launch_rebin<float>(gt_plan *, hipStream_t);
+template int launch_rebin<double>(gt_plan *, hipStream_t);
 
 }  // namespace gt

@@ -154,6 +154,20 @@ inline size_t poly_pack_lds(const OrderHost &o) {
 }  // namespace gt
 
 namespace gt {
+// Scratch of gt_plan_update_nodes, allocated on a plan's first update and kept: the radix
+// sort's key/value batch and temporary storage, the ragged offsets on the device, and the
+// per-wavefront segment counts of the order-2 tile list.
+struct RebinScratch {
+  bool ready = false;
+  uint32_t *kin = nullptr, *kout = nullptr;
+  int32_t *vin = nullptr;
+  void *tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int64_t *offs = nullptr;
+  int32_t *segcnt = nullptr;
+  int32_t segcnt_cap = 0;
+};
+
 struct CosTerm {      // cosine basis, one non-empty term: order, bandwidth, internal/external offsets
   int32_t t, N;
   int64_t int_off, ext_off;
@@ -204,6 +218,8 @@ struct gt_plan {
   };
   std::vector<GraphEntry> graphs;     // captured launch sequences, most recent last
   std::string tuning;                 // report of the last gt_plan_tune (JSON)
+  gt::RebinScratch rebin;             // gt_plan_update_nodes
+  int64_t node_version = 0;           // updates of the nodes so far
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t lds_limit = 65536;           // LDS per workgroup
   int num_cu = 256;                   // compute units of the device
@@ -239,6 +255,8 @@ template <typename T> int launch_adjoint(gt_plan *pl, const void *y, const T *co
 template <typename T> int launch_node_grad(gt_plan *pl, const void *fhat, const void *g, void *gx, hipStream_t s);
 template <typename T> int launch_prepare_nodes(gt_plan *pl, const void *x, hipStream_t s);
 template <typename T> int launch_binning(gt_plan *pl, hipStream_t s);   // binning.hip
+template <typename T> int launch_rebin(gt_plan *pl, hipStream_t s);     // binning.hip, kept scratch
+int launch_tile_relist(gt_plan *pl, hipStream_t s);                      // binning.hip
 
 // ---- solver drivers (solvers.hip) ----
 // Sensitivity indices (eq. gsi) from term offsets goff (device, nterms + 1): rho[r][u].

@@ -385,6 +385,12 @@ void free_plan(gt_plan *pl) {
     dev_free(o.d_tsum, nullptr);
     dev_free(o.d_dpart, nullptr);
   }
+  dev_free(pl->rebin.kin, nullptr);
+  dev_free(pl->rebin.kout, nullptr);
+  dev_free(pl->rebin.vin, nullptr);
+  dev_free(pl->rebin.tmp, nullptr);
+  dev_free(pl->rebin.offs, nullptr);
+  dev_free(pl->rebin.segcnt, nullptr);
   delete pl;
 }
 
@@ -480,6 +486,8 @@ static int build_cell_items(gt_plan *pl, int t, bool force, double *fill_out) {
   if (!o.citems.empty()) return GT_OK;   // built before
   const int nt = o.term_end - o.term_begin;
   if (nt == 0 || (int64_t)nt * pl->Mtot >= (int64_t(1) << 31)) return GT_OK;
+  if (o.cstart_host.empty())             // (dropped by a node update)
+    if (int rc = fetch_cell_starts(pl, t, pl->stream, o.cstart_host)) return rc;
   const int B = pl->ragged ? pl->R : 1;
   const std::vector<int64_t> &cs = o.cstart_host;
   // lane fill of the items (runs of <= 64 nodes of one cell), decided before building them
@@ -667,6 +675,8 @@ int gt::set_tile_waves(gt_plan *pl, int waves_cu) {
   o.d_waves2 = o.d_tileseg = nullptr;
   o.d_patch = o.d_tsum = nullptr;
   o.waves_cu = waves_cu;
+  if (o.cstart_host.empty())             // (dropped by a node update)
+    if (int rc = fetch_cell_starts(pl, 2, pl->stream, o.cstart_host)) return rc;
   return setup_tile_spread(pl, o.cstart_host);
 }
 
@@ -1265,6 +1275,64 @@ int gt_plan_adjoint(gt_plan *plan, const void *y, void *fhat, void *stream) {
   if (!fhat || !y) return fail(GT_EINVAL, "NULL argument");
   plan->stream = (hipStream_t)stream;
   return run_plan_call(plan, 1, y, fhat, (hipStream_t)stream);
+}
+
+int gt_plan_update_nodes(gt_plan *plan, const void *x, void *stream) {
+  GT_LIVE(plan);
+  if (!x) return fail(GT_EINVAL, "NULL argument");
+  const hipStream_t s = (hipStream_t)stream;
+  plan->stream = s;
+  drop_graphs(plan);
+  const size_t csz = 2 * plan->rsize;
+  // forward forms whose work items follow the node positions on the host take the sorted gather
+  for (int t = 1; t <= plan->ds; ++t) {
+    OrderHost &o = plan->ord[t];
+    o.cstart_host.clear();
+    if (o.path == GT_GATHER_CELL || o.path == GT_GATHER_POLY) o.path = GT_GATHER_SORTED;
+    if (o.d_citems || o.d_kpoly) {
+      GT_HIP(hipStreamSynchronize(s));
+      dev_free(o.d_citems, nullptr);
+      dev_free(o.d_kpoly, nullptr);
+      o.d_citems = nullptr;
+      o.d_kpoly = nullptr;
+      o.citems.clear();
+      o.citem_begin.clear();
+    }
+  }
+  // order-2 tile spread: patches for the most segments any node positions can give
+  OrderHost &o2 = plan->ord[2];
+  if (plan->ds >= 2 && o2.term_end > o2.term_begin && o2.nwaves2 > 0) {
+    const int B = plan->ragged ? plan->R : 1;
+    const int64_t bound = (int64_t)o2.nwaves2 + (int64_t)(o2.term_end - o2.term_begin) * B * o2.ntile * o2.ntile;
+    if (bound >= (int64_t(1) << 31) / 256) return fail(GT_EUNSUPPORTED, "too many tile patches");
+    const int reff = plan->ragged ? 1 : plan->R;
+    if (bound > o2.nseg2) {
+      GT_HIP(hipStreamSynchronize(s));
+      dev_free(o2.d_patch, nullptr);
+      o2.d_patch = nullptr;
+      if (int rc = dev_alloc(&o2.d_patch, (size_t)reff * bound * 256 * csz, nullptr)) return rc;
+      o2.nseg2 = bound;
+    }
+    if (plan->rebin.segcnt_cap < o2.nwaves2) {
+      GT_HIP(hipStreamSynchronize(s));
+      dev_free(plan->rebin.segcnt, nullptr);
+      plan->rebin.segcnt = nullptr;
+      plan->rebin.segcnt_cap = 0;
+      if (int rc = dev_alloc((void **)&plan->rebin.segcnt, (size_t)o2.nwaves2 * sizeof(int32_t), nullptr)) return rc;
+      plan->rebin.segcnt_cap = o2.nwaves2;
+    }
+  }
+  // nodes: wrap, transpose, validate (one synchronisation), then the binning on the device
+  int rc = plan->dtype == GT_C64 ? launch_prepare_nodes<float>(plan, x, s) : launch_prepare_nodes<double>(plan, x, s);
+  if (rc) return rc;
+  int32_t flag = 0;
+  GT_HIP(hipMemcpyAsync(&flag, plan->d_flag, sizeof(flag), hipMemcpyDeviceToHost, s));
+  GT_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(GT_EINVAL, "nodes contain NaN or Inf (the plan's nodes are now undefined)");
+  rc = plan->dtype == GT_C64 ? launch_rebin<float>(plan, s) : launch_rebin<double>(plan, s);
+  if (rc == GT_OK) rc = launch_tile_relist(plan, s);
+  if (rc == GT_OK) ++plan->node_version;
+  return rc;
 }
 
 int gt_plan_tune(gt_plan *plan, void *stream) {

@@ -33,7 +33,7 @@ EXPORTS = [
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
     "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc", "lsqr_solve_path", "gt_plan_lsqr_path",
     "gt_plan_set_gather_path", "gt_plan_tune", "gt_plan_tuning", "gt_plan_set_graph", "gt_plan_adjoint_form",
-    "gt_plan_set_adjoint_form",
+    "gt_plan_set_adjoint_form", "gt_plan_update_nodes",
 ]
 
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "gt_plan_set_gather_path": (C.c_int, [vp, i32, i32]),
         "gt_plan_adjoint_form": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "gt_plan_set_adjoint_form": (C.c_int, [vp, i32, i32]),
+        "gt_plan_update_nodes": (C.c_int, [vp, vp, vp]),
         "gt_plan_tune": (C.c_int, [vp, vp]),
         "gt_plan_tuning": (i64, [vp, C.c_char_p, i64]),
         "gt_plan_set_graph": (C.c_int, [vp, i32]),
@@ -365,6 +366,10 @@ class Plan:
         path = C.c_int32()
         _check(self._lib.gt_plan_gather_path(self.handle, int(t), C.byref(path)))
         return int(path.value)
+
+    def update_nodes(self, x, stream=None):
+        """gt_plan_update_nodes: new positions for the plan's nodes (same count and layout)."""
+        _check(self._lib.gt_plan_update_nodes(self.handle, _ptr(x), _stream(stream)))
 
     def set_gather_path(self, t: int, path: int):
         _check(self._lib.gt_plan_set_gather_path(self.handle, int(t), int(path)))

@@ -162,3 +162,41 @@ def test_fixed_nodes_reuses_its_plan_and_matches():
     say(f"[fixed nodes] grad fhat vs oracle {e:.3e}")
     assert e <= 1e-5
     mod.close()
+
+
+def test_moving_nodes_match_fresh_plans_and_oracle():
+    """GroupedTrafoMovingNodes over three node sets on one plan (device re-binning): forward
+    and both gradients equal those of grouped_trafo's fresh plan for the same nodes, except
+    for the gather forms (the moved plan takes the sorted gather; the fresh plan may take
+    the cell or polynomial gather), so compared at the FP32 bar; the last step against the
+    oracle."""
+    import torch
+    from paper_2010_10199_amd.autograd import GroupedTrafoMovingNodes
+    d, ds, N = 8, 2, (32, 10)
+    iset, offs, x, fh, v = _ragged(53, 6, 300, 2500, d, ds, N, "f32")
+    mod = GroupedTrafoMovingNodes(to_dev(x), d, ds, N, offsets=offs)
+    vt = to_dev(v)
+    for it in range(3):
+        xi = W.uniform_nodes(W.rng(530 + it, W.P_NODES), x.shape[0], d, "f32")
+        xt = to_dev(xi).requires_grad_(True)
+        ft = to_dev(fh).requires_grad_(True)
+        f = mod(ft, xt)
+        (torch.conj(vt) * f).real.sum().backward()
+        gfh2, gx2, f2 = _grads(iset, offs, xi, fh, v, d, ds, N, "f32")
+        torch.cuda.synchronize()
+        e0 = rel(f.detach().cpu().numpy(), f2)
+        e1 = rel(ft.grad.cpu().numpy(), gfh2)
+        e2 = rel(xt.grad.cpu().numpy(), gx2)
+        say(f"[moving nodes] step {it}: f {e0:.2e} grad fhat {e1:.2e} grad x {e2:.2e} (vs a fresh plan)")
+        assert e0 <= 1e-5 and e1 <= 1e-5 and e2 <= 1e-5
+    rfh, rgx = _oracle_grads(iset, offs, xi, fh, v)
+    e1, e2 = rel(ft.grad.cpu().numpy(), rfh), rel(xt.grad.cpu().numpy(), rgx)
+    say(f"[moving nodes] vs oracle: grad fhat {e1:.2e} grad x {e2:.2e}")
+    assert e1 <= 1e-5 and e2 <= 1e-5
+    # a second call before the first call's backward: the backward refuses
+    ft = to_dev(fh).requires_grad_(True)
+    fa = mod(ft, to_dev(x))
+    mod(to_dev(fh), to_dev(xi))
+    with pytest.raises(RuntimeError):
+        (torch.conj(vt) * fa).real.sum().backward()
+    mod.close()
