@@ -263,7 +263,7 @@ CD, CDS, CN, CM, CR = 20, 3, (32, 12, 6), 500000, 16
 C3_FP64_TIMED = (0, 5, 10, 15)       # lambda indices whose FP64-plain solves are timed by default
 
 
-def run_c3(steps: int, all_lambdas: bool):
+def run_c3(steps: int, all_lambdas: bool, transform_only: bool = False):
     """The batched-LSQR workload (Sec. 4.1, eq. new_min_prob): d = 20, d_s = 3, N = 32/12/6,
     M = 500,000 uniform nodes, FP32 bulk arithmetic.
 
@@ -353,6 +353,8 @@ def run_c3(steps: int, all_lambdas: bool):
                      "avg_launch_ms": tot / cnt}}
     print(f"[bench]   c3 transform R={CR}: {ms:.1f} ms per fwd+adj ({2 * nt / (ms * 1e-3):.3e} node-terms/s)",
           file=sys.stderr, flush=True)
+    if transform_only:
+        return out
     # ---- 2. LSQR time to accuracy
     target, _ = W.sparse_trig_target(3, x32, CN)
     y = W.add_noise(W.rng(3, W.P_NOISE), target, 0.01).astype(np.complex64)
@@ -914,6 +916,8 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=3, help="timed forward + adjoint steps of the d=20 workload")
     ap.add_argument("--c3-all-lambdas", action="store_true",
                     help="time the FP64-plain solve of all 16 lambda values (default: 4 of them)")
+    ap.add_argument("--c3-transform-only", action="store_true",
+                    help="d=20 workload: the transform leg only (no LSQR time to accuracy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -970,16 +974,28 @@ def main():
         achieved = fl / avg_s / 1e12
         traffic = None
         tf = os.path.join(ROOT, "profiles", "traffic.json")
+        hbm = {}
         if os.path.exists(tf):
             with open(tf) as fh:
                 tj = json.load(fh)
+            khash = kernel_hash()
             ent = tj.get("kernels", {}).get(name)
-            if ent and ent.get("kernel_hash") == kernel_hash():
+            if ent and ent.get("kernel_hash") == khash:
                 traffic = ent.get("bytes_per_launch")
+            # every kernel's HBM rate from the counted bytes (when taken with these sources)
+            for k, (cnt, tot) in kern.items():
+                e = tj.get("kernels", {}).get(k)
+                if e and e.get("kernel_hash") == khash and cnt > 0 and tot > 0:
+                    gbs = e["bytes_per_launch"] / (tot / cnt * 1e-3) / 1e9
+                    hbm[k] = {"bytes_per_launch": e["bytes_per_launch"], "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS}
         out["roofline"] = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                            "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl}
         out["kernels_ms"] = {k: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3} for k, v in sorted(kern.items())}
+        if traffic is not None:
+            out["roofline"]["traffic_GB/s"] = traffic / avg_s / 1e9
+            out["roofline"]["traffic_frac_of_hbm_peak"] = traffic / avg_s / 1e9 / PEAK_HBM_GBS
+        out["kernels_hbm"] = hbm or None   # counted HBM bytes per launch / launch time, per kernel
         out["roofline"]["timing"] = ("per-launch HIP events over a second pass of the same steps, launched eagerly on one "
                                      "stream (the timed pass uses the tuned launch forms: graph replay and the "
                                      "order-1 kernels on a second stream where the tuning chose them)")
@@ -1015,7 +1031,7 @@ def main():
         out["cosine"] = run_cosine(max(5, args.steps // 2))
     if not args.no_c3:
         print("[bench] batched-lsqr workload (d=20)", file=sys.stderr, flush=True)
-        out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas)
+        out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas, args.c3_transform_only)
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

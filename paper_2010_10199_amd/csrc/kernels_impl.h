@@ -1128,7 +1128,11 @@ static int launch_direct_fwd(gt_plan *pl, int t, const void *fhat, const T *cols
   const OrderHost &o = pl->ord[t];
   const DirectArgs da = direct_args(pl, t);
   const int rtw = direct_fwd_rtw(pl, t), ct = pl->R <= 8 ? 1 : 2;
-  const size_t lds = ((size_t)da.G * 8 * ct + (size_t)t * da.K * 64 * rtw) * sizeof(C);
+  const size_t rows = 64 * (size_t)rtw + kDirPad, KR = (size_t)(da.G / da.K), KR2 = KR + (KR & 1);
+  const size_t breals = (((size_t)da.G + 1) * (16 * ct + 1) + 3) & ~(size_t)3;
+  const size_t lds = breals * sizeof(T) +
+                     (2 * ((size_t)da.K + 1) + (t >= 2 ? KR2 : 0) + (t == 3 ? 2 * (size_t)da.K : 0)) * rows * sizeof(C) +
+                     (size_t)t * 64 * rtw * sizeof(T);
   const int nb = 64 * rtw;
   dim3 grid((unsigned)((pl->M + nb - 1) / nb));
   prof_begin(s, t == 1 ? "direct_fwd_1d" : t == 2 ? "direct_fwd_2d" : "direct_fwd_3d");
@@ -1140,8 +1144,10 @@ static int launch_direct_fwd(gt_plan *pl, int t, const void *fhat, const T *cols
   }
 #define GT_LAUNCH_DF_O(ORD)                     \
   {                                             \
-    if (ct == 1 && rtw == 2) GT_LAUNCH_DF(ORD, 1, 2) \
+    if (ct == 1 && rtw == 1) GT_LAUNCH_DF(ORD, 1, 1) \
+    else if (ct == 1 && rtw == 2) GT_LAUNCH_DF(ORD, 1, 2) \
     else if (ct == 1) GT_LAUNCH_DF(ORD, 1, 4)        \
+    else if (rtw == 1) GT_LAUNCH_DF(ORD, 2, 1)       \
     else if (rtw == 2) GT_LAUNCH_DF(ORD, 2, 2)       \
     else GT_LAUNCH_DF(ORD, 2, 4)                     \
   }
@@ -1162,7 +1168,8 @@ static int launch_direct_adj(gt_plan *pl, int t, const void *y, const T *colscal
   const DirectArgs da = direct_args(pl, t);
   const int nt = o.term_end - o.term_begin, S = o.dir_nslice, rtw = direct_adj_rtw(pl, t);
   if (!o.d_dpart || S < 1 || rtw < 1) return fail(GT_EINVAL, "direct adjoint not set up");
-  const size_t lds = (size_t)t * da.K * 64 * sizeof(C);
+  const size_t lds = (3 * (size_t)da.K + 1 + (t >= 2 ? (size_t)(da.G / da.K) : 0) + (t == 3 ? 2 * (size_t)da.K : 0)) *
+                     kDirRowA * sizeof(C);
   prof_begin(s, t == 1 ? "direct_adj_1d" : t == 2 ? "direct_adj_2d" : "direct_adj_3d");
 #define GT_LAUNCH_DA(ORD, RTW)                                                                                   \
   {                                                                                                              \

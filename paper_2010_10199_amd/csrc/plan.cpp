@@ -583,25 +583,37 @@ static int setup_cell_gather(gt_plan *pl) {
 // Selects a forward form for order t (building what it needs); GT_EUNSUPPORTED when the form
 // is not available for this plan.
 // Direct sums (direct.h): shared nodes, at most 16 right-hand sides (the columns of the
-// contraction).  Forward LDS: the group's coefficients (G x 8 CT) and the phases of the
-// workgroup's 64 rtw nodes (order x K each; rtw = 4 row tiles per wavefront when that
-// leaves room for two workgroups, else 2); adjoint: |I_u| <= 256 (rows 2 G in at most 8 row
-// tiles per wavefront), samples (64 x 16) and the phases of 64 nodes.
+// contraction).  Forward LDS: the coefficients as B rows ((G + 1) x (16 CT + 1) reals) and
+// the phase tables of the workgroup's 64 rtw nodes (two versions of the first axis's K phases
+// plus a zero row, the G / K products of the other axes rounded up to even, and for order 3
+// the two per-axis tables, rows padded by 16); adjoint: |I_u| <= 256 (rows 2 G in at most 8
+// row tiles per wavefront), samples (2 x 16 x 65 reals) and the phase tables of 64 nodes
+// (three versions of the first axis and a zero row, the products of the others, order 3's
+// per-axis tables, rows of 68).
 static int64_t group_size(const gt_plan *pl, int t) {
   int64_t G = 1;
   for (int a = 0; a < t; ++a) G *= pl->ord[t].N - 1;
   return G;
 }
 static size_t direct_fwd_lds(const gt_plan *pl, int t, int rtw) {
-  const int CT = pl->R <= 8 ? 1 : 2;
-  return ((size_t)group_size(pl, t) * 8 * CT + (size_t)t * (pl->ord[t].N - 1) * 64 * rtw) * 2 * pl->rsize;
+  const size_t CT = pl->R <= 8 ? 1 : 2;
+  const size_t K = (size_t)(pl->ord[t].N - 1), G = (size_t)group_size(pl, t), rows = 64 * (size_t)rtw + 16;
+  const size_t KR2 = G / K + ((G / K) & 1);
+  const size_t breals = ((G + 1) * (16 * CT + 1) + 3) & ~(size_t)3;
+  return breals * pl->rsize + (2 * (K + 1) + (t >= 2 ? KR2 : 0) + (t == 3 ? 2 * K : 0)) * rows * 2 * pl->rsize +
+         (size_t)t * 64 * rtw * pl->rsize;
 }
+// row tiles per wavefront: the most (4, 2, 1) that leave room for three workgroups per
+// compute unit, else one (measured on the d = 20 workload's order 3: one and two row tiles
+// alike, four 11 % slower)
 int gt::direct_fwd_rtw(const gt_plan *pl, int t) {
-  return direct_fwd_lds(pl, t, 4) <= pl->lds_limit / 2 ? 4 : 2;
+  for (int rtw : {4, 2})
+    if (direct_fwd_lds(pl, t, rtw) <= pl->lds_limit / 3) return rtw;
+  return 1;
 }
 bool gt::direct_fwd_ok(const gt_plan *pl, int t) {
   return !pl->ragged && pl->R <= 16 && t >= 1 && t <= pl->ds && pl->ord[t].term_end > pl->ord[t].term_begin &&
-         direct_fwd_lds(pl, t, 2) <= pl->lds_limit;
+         direct_fwd_lds(pl, t, 1) <= pl->lds_limit;
 }
 int gt::direct_adj_rtw(const gt_plan *pl, int t) {
   const int64_t rows = 2 * group_size(pl, t);
@@ -609,7 +621,9 @@ int gt::direct_adj_rtw(const gt_plan *pl, int t) {
 }
 bool gt::direct_adj_ok(const gt_plan *pl, int t) {
   if (pl->ragged || pl->R > 16 || t < 1 || t > pl->ds || pl->ord[t].term_end == pl->ord[t].term_begin) return false;
-  const size_t lds = ((size_t)64 * 16 + (size_t)t * (pl->ord[t].N - 1) * 64) * 2 * pl->rsize;
+  const size_t K = (size_t)(pl->ord[t].N - 1), G = (size_t)group_size(pl, t);
+  const size_t lds = (size_t)(2 * 16 * 65 + 3 * 64) * pl->rsize +
+                     (3 * K + 1 + (t >= 2 ? G / K : 0) + (t == 3 ? 2 * K : 0)) * 68 * 2 * pl->rsize;
   return direct_adj_rtw(pl, t) > 0 && lds <= pl->lds_limit;
 }
 
