@@ -128,6 +128,41 @@ def test_config4_fista_reduced_vs_oracle(prec):
         assert e <= (1e-5 if prec == "f32" else 1e-10)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config4_fista_eight_lambdas_dense_oracle(prec):
+    """The group-lasso shape (d=12, d_s=2, N=48/16: 79 groups, 15,415 coefficients) on 3,000
+    nodes with the B-spline target + 1 % noise and all eight lambda values of the benchmark's
+    grid (lambda_max 10^(-3j/7)) in one batched call, 15 constant steps, against the oracle's
+    iterates with the dense matrix of eq. FM as its operator (L = 1.05 x a 20-step oracle
+    power iteration on the same matrix)."""
+    d, ds, N = C4
+    M, K = 3000, 15
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = W.uniform_nodes(W.rng(4, W.P_NODES, 2), M, d, prec)
+    y = W.add_noise(W.rng(4, W.P_NOISE, 2), W.bspline_target(x).astype(np.complex128), 0.01)
+    y = y.astype(np.complex64 if prec == "f32" else np.complex128)
+    A = otr.dense_matrix(iset, x)
+    mv = lambda v: A @ v
+    rmv = lambda u: (u.conj() @ A).conj()
+    g = rmv(y.astype(np.complex128))
+    lam_max = max(np.linalg.norm(g[iset.term_slice(i)]) for i in range(iset.n_terms))
+    lams = [lam_max * 10 ** (-3 * j / 7) for j in range(8)]
+    L = 1.05 * ofista.power_iteration(mv, rmv, iset.n_coeffs, 20)
+    say(f"[config4 fista dense] {prec} M={M} lambda_max={lam_max:.4g} L={L:.4g}")
+    fg, _ = _fista_gpu(d, ds, N, x, np.tile(y, 8).reshape(8, M), lams, prec, K, L)
+    refs = [ofista.fista(mv, rmv, y.astype(np.complex128), iset.offsets, lam, L, K).fhat for lam in lams]
+    big = max(np.linalg.norm(f) for f in refs)
+    worst = 0.0
+    for r, lam in enumerate(lams):
+        # (the zero solution at lambda_max is compared relative to the largest solution)
+        nrm = np.linalg.norm(refs[r])
+        e = float(np.linalg.norm(fg[r] - refs[r]) / (nrm if nrm > 1e-12 * big else big))
+        worst = max(worst, e)
+        say(f"  lambda={lam:.4g}: rel {e:.3e}")
+    assert worst <= (1e-5 if prec == "f32" else 1e-10)
+    del A
+
+
 @pytest.fixture(scope="module")
 def config3_lsqr_slice():
     """The batched-LSQR workload's index set (d=20, d_s=3, N=32/12/6: 1,351 groups, 166,111
