@@ -47,10 +47,38 @@ def direct_flops_per_node_term(order: int, N: int, R: int) -> int:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h"):
+    for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h", "direct.h"):
         with open(os.path.join(ROOT, "paper_2010_10199_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def counted_bytes(tj: dict, record: str, tuning: dict, khash: str):
+    """HBM bytes per launch of a timing record from the counter table, for the kernel form the tuner chose.
+
+    A gather record may have been counted in several forms (a sorted, cell or polynomial sweep, and its
+    packing kernel with it); the entry used is the one of the chosen form.  The kernels of any other record
+    all run in each of its launches and are summed.  None when the table was taken with other kernel
+    sources or lacks the form.
+    """
+    ent = tj.get("kernels", {}).get(record)
+    if not ent or ent.get("kernel_hash") != khash:
+        return None
+    forms = ent.get("forms", {})
+    if len(forms) <= 1:
+        return ent.get("bytes_per_launch")
+    order = record.rsplit("_", 1)[-1][:-1]
+    chosen = (tuning or {}).get("gather", {}).get(order, {}).get("chosen")
+    want = {("gather", "cell"): "k_gather_cell<", ("gather", "sorted"): "k_gather_sorted<",
+            ("gather", "poly"): "k_gather_poly2<", ("pack", "poly"): "k_pack_poly2<"}
+    kind = "pack" if record.startswith("pack") else "gather" if record.startswith("gather") else None
+    if kind is None:
+        return sum(e["bytes_per_launch"] for e in forms.values())
+    sub = want.get((kind, chosen), "k_pack_fwd<" if kind == "pack" else None)
+    for k, e in forms.items():
+        if sub and sub in k:
+            return e["bytes_per_launch"]
+    return None
 
 
 def run_gpu(precision: str, steps: int, warmup: int, profile: bool):
@@ -263,7 +291,7 @@ CD, CDS, CN, CM, CR = 20, 3, (32, 12, 6), 500000, 16
 C3_FP64_TIMED = (0, 5, 10, 15)       # lambda indices whose FP64-plain solves are timed by default
 
 
-def run_c3(steps: int, all_lambdas: bool, transform_only: bool = False):
+def run_c3(steps: int, all_lambdas: bool, transform_only: bool = False, forms: str = "tune"):
     """The batched-LSQR workload (Sec. 4.1, eq. new_min_prob): d = 20, d_s = 3, N = 32/12/6,
     M = 500,000 uniform nodes, FP32 bulk arithmetic.
 
@@ -305,7 +333,13 @@ def run_c3(steps: int, all_lambdas: bool, transform_only: bool = False):
     plan_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    tuning = plan.tune(stream.cuda_stream)     # launch forms measured on these nodes (off the clock)
+    if forms == "direct":                      # every order on the direct sums (for profiling)
+        for t in range(1, CDS + 1):
+            plan.set_gather_path(t, lib.GT_GATHER_DIRECT)
+            plan.set_adjoint_form(t, lib.GT_ADJ_DIRECT)
+        tuning = {"forms": "direct sums for every order, set by hand"}
+    else:
+        tuning = plan.tune(stream.cuda_stream)     # launch forms measured on these nodes (off the clock)
     tune_s = time.perf_counter() - t0
     print(f"[bench]   c3 tuning R={CR}: {tune_s:.1f} s {json.dumps(tuning)}", file=sys.stderr, flush=True)
     plan.trafo(fd, f_out)
@@ -918,6 +952,8 @@ def main():
                     help="time the FP64-plain solve of all 16 lambda values (default: 4 of them)")
     ap.add_argument("--c3-transform-only", action="store_true",
                     help="d=20 workload: the transform leg only (no LSQR time to accuracy)")
+    ap.add_argument("--c3-forms", choices=["tune", "direct"], default="tune",
+                    help="d=20 transform leg: tuned launch forms, or the direct sums for every order")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -979,15 +1015,13 @@ def main():
             with open(tf) as fh:
                 tj = json.load(fh)
             khash = kernel_hash()
-            ent = tj.get("kernels", {}).get(name)
-            if ent and ent.get("kernel_hash") == khash:
-                traffic = ent.get("bytes_per_launch")
+            traffic = counted_bytes(tj, name, r32["tuning"], khash)
             # every kernel's HBM rate from the counted bytes (when taken with these sources)
             for k, (cnt, tot) in kern.items():
-                e = tj.get("kernels", {}).get(k)
-                if e and e.get("kernel_hash") == khash and cnt > 0 and tot > 0:
-                    gbs = e["bytes_per_launch"] / (tot / cnt * 1e-3) / 1e9
-                    hbm[k] = {"bytes_per_launch": e["bytes_per_launch"], "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS}
+                b = counted_bytes(tj, k, r32["tuning"], khash)
+                if b is not None and cnt > 0 and tot > 0:
+                    gbs = b / (tot / cnt * 1e-3) / 1e9
+                    hbm[k] = {"bytes_per_launch": b, "GB/s": gbs, "frac": gbs / PEAK_HBM_GBS}
         out["roofline"] = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                            "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl}
@@ -1031,7 +1065,7 @@ def main():
         out["cosine"] = run_cosine(max(5, args.steps // 2))
     if not args.no_c3:
         print("[bench] batched-lsqr workload (d=20)", file=sys.stderr, flush=True)
-        out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas, args.c3_transform_only)
+        out["batched_lsqr_d20"] = run_c3(args.c3_steps, args.c3_all_lambdas, args.c3_transform_only, args.c3_forms)
     if args.cpu_sample > 0:
         print(f"[bench] cpu oracle sample {args.cpu_sample}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
