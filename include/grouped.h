@@ -219,7 +219,9 @@ int gt_plan_update_nodes(gt_plan *plan, const void *x, void *stream);
  *      4 either side of the best, as the staging LDS allows), by the time of the order-2
  *      adjoint kernels; then per order the adjoint forms (GT_ADJ_WINDOW / DIRECT), by the
  *      time of that order's adjoint kernels;
- *   3. whether order 1 runs on the plan's second stream (forward + adjoint);
+ *   3. whether order 1 runs on the plan's second stream (forward + adjoint), and, for plans
+ *      of orders 1 and 2 that can take them, whether both orders run in shared launches
+ *      (gt_plan_set_fused) instead;
  *   4. whether gt_plan_trafo / gt_plan_adjoint launch eagerly or replay a graph of their
  *      launches captured by the plan (forward + adjoint; not on the legacy default stream,
  *      where the plan never captures).
@@ -240,10 +242,25 @@ int gt_plan_update_nodes(gt_plan *plan, const void *x, void *stream);
  * afterwards; they launch eagerly on the legacy default stream, while `stream` is being
  * captured by the caller, and while per-launch profiling is on.  Only these two calls replay
  * graphs; the solvers and the node gradient launch eagerly.  Changing the plan's forms drops
- * its graphs (after a device synchronisation). */
+ * its graphs (after a device synchronisation).
+ *
+ * gt_plan_set_fused(on) turns the shared launches on or off by hand (Sec. 3, eq. somafm: the
+ * same steps for every group, here for the groups of orders 1 and 2 together).  With it on,
+ * a forward is three launches (the K1 + K2 packs of both orders, the K3 gathers of both
+ * orders, the sum over the groups) and an adjoint three (the K4 spreads of both orders with
+ * the empty set's partial sums, the folds of both orders with the empty set's coefficient,
+ * the K2 + K5 DFTs of both orders), all on `stream`; each part runs the kernel body and work
+ * items of its own launch, so the results are bit for bit those of the separate launches.
+ * Available (else GT_EUNSUPPORTED) for plans whose orders are exactly 1 and 2, both with
+ * window forms (no GT_GATHER_DIRECT, GT_ADJ_WINDOW) and one window width m, whose gather
+ * slots hold every term in one block, and whose order-2 fold takes its tile-sum form within
+ * the LDS limit.  Changing a form of an order afterwards so that this no longer holds
+ * returns the plan to the separate launches; switching drops the plan's graphs (after a
+ * synchronisation of the plan's stream). */
 int gt_plan_tune(gt_plan *plan, void *stream);
 int64_t gt_plan_tuning(const gt_plan *plan, char *buf, int64_t len);
 int gt_plan_set_graph(gt_plan *plan, int32_t on);
+int gt_plan_set_fused(gt_plan *plan, int32_t on);
 
 /* ------------------------------------------------------------------ solvers
  * lsqr_solve: R independent weighted Tikhonov problems (eq. new_min_prob), one per

@@ -11,20 +11,17 @@
 namespace gt {
 
 template <typename T, int ORDER, int MH>
-__global__ __launch_bounds__(kGatherBS) void k_gather_sorted(const T *__restrict__ xT, int64_t Mx,
-                                                             const GatherItem *__restrict__ items,
-                                                             const int32_t *__restrict__ perm,
-                                                             const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                             const cx_t<T> *__restrict__ grids, int64_t grid_total,
-                                                             int64_t vstride, int slot_base,
-                                                             cx_t<T> *__restrict__ slots, int64_t Vtot) {
+__device__ __forceinline__ void gather_sorted_body(const Blk bk, const T *__restrict__ xT, int64_t Mx,
+                                                   const GatherItem *__restrict__ items,
+                                                   const int32_t *__restrict__ perm,
+                                                   const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                                   const cx_t<T> *__restrict__ grids, int64_t grid_total,
+                                                   int64_t vstride, int slot_base, cx_t<T> *__restrict__ slots,
+                                                   int64_t Vtot) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *G = reinterpret_cast<C *>(smem_raw);
-  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each XCD takes a
-  // contiguous range of items (items are grouped by term), so a term's scattered slot writes
-  // meet in one L2 and leave it as whole lines.
-  const GatherItem it = items[xcd_contiguous(blockIdx.x, gridDim.x)];
+  const GatherItem it = items[bk.x];
   const DevTerm tm = terms[op.term_begin + it.tl];
   const C *src = grids + (int64_t)it.r * grid_total + tm.grid_off;
   const int tid = threadIdx.x;
@@ -43,6 +40,21 @@ __global__ __launch_bounds__(kGatherBS) void k_gather_sorted(const T *__restrict
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin; they are renumbered so that each XCD takes
+// a contiguous range of items (items are grouped by term), so a term's scattered slot writes
+// meet in one L2 and leave it as whole lines.
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(kGatherBS) void k_gather_sorted(const T *__restrict__ xT, int64_t Mx,
+                                                             const GatherItem *__restrict__ items,
+                                                             const int32_t *__restrict__ perm,
+                                                             const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                             const cx_t<T> *__restrict__ grids, int64_t grid_total,
+                                                             int64_t vstride, int slot_base,
+                                                             cx_t<T> *__restrict__ slots, int64_t Vtot) {
+  gather_sorted_body<T, ORDER, MH>(Blk{xcd_contiguous(blockIdx.x, gridDim.x), 0}, xT, Mx, items, perm, terms, op,
+                                   grids, grid_total, vstride, slot_base, slots, Vtot);
+}
+
 // K3 gather, one wavefront per run of at most 64 nodes of one grid cell (nodes of a cell
 // are contiguous in the binning's order).  All lanes of the wavefront then touch the same
 // 2m x ... x 2m block of the grid, so its address is uniform: the grid values are read
@@ -52,22 +64,21 @@ __global__ __launch_bounds__(kGatherBS) void k_gather_sorted(const T *__restrict
 // output slot as in k_gather_sorted.  Used when the cells hold enough nodes to keep most
 // lanes busy (see the plan).
 template <typename T, int ORDER, int MH>
-__global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, int64_t Mx,
-                                                     const CellItem *__restrict__ items, int nitems,
-                                                     const int32_t *__restrict__ perm,
-                                                     const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                     const cx_t<T> *__restrict__ grids, int64_t grid_total,
-                                                     int64_t vstride, int slot_base, cx_t<T> *__restrict__ slots,
-                                                     int64_t Vtot) {
+__device__ __forceinline__ void gather_cell_body(const Blk bk, const T *__restrict__ xT, int64_t Mx,
+                                                 const CellItem *__restrict__ items, int nitems,
+                                                 const int32_t *__restrict__ perm,
+                                                 const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                                 const cx_t<T> *__restrict__ grids, int64_t grid_total,
+                                                 int64_t vstride, int slot_base, cx_t<T> *__restrict__ slots,
+                                                 int64_t Vtot) {
   using C = cx_t<T>;
   constexpr int W = 2 * MH;
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // consecutive items (one term) share an XCD, as in k_gather_sorted
-  const int ii = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wv;
+  const int ii = bk.x * 4 + wv;
   if (ii >= nitems) return;   // whole wavefront; no workgroup barrier follows
   const CellItem it = items[ii];
-  const int r = it.r + (int)blockIdx.y;
+  const int r = it.r + bk.y;
   const DevTerm tm = terms[op.term_begin + it.tl];
   const C *__restrict__ G = grids + (int64_t)r * grid_total + tm.grid_off;
   const int n = op.n, P = op.P;
@@ -134,6 +145,19 @@ __global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, i
     }
   }
   if (act) slots[(int64_t)(slot_base + op.term_begin + it.tl) * Vtot + (int64_t)r * vstride + node] = cmake<T>(re, im);
+}
+
+// consecutive items (one term) share an XCD, as in k_gather_sorted
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(256) void k_gather_cell(const T *__restrict__ xT, int64_t Mx,
+                                                     const CellItem *__restrict__ items, int nitems,
+                                                     const int32_t *__restrict__ perm,
+                                                     const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                     const cx_t<T> *__restrict__ grids, int64_t grid_total,
+                                                     int64_t vstride, int slot_base, cx_t<T> *__restrict__ slots,
+                                                     int64_t Vtot) {
+  gather_cell_body<T, ORDER, MH>(Blk{xcd_contiguous(blockIdx.x, gridDim.x), (int)blockIdx.y}, xT, Mx, items, nitems,
+                                 perm, terms, op, grids, grid_total, vstride, slot_base, slots, Vtot);
 }
 
 // ------------------------------------------------------------------ order-2 gather in the
@@ -209,16 +233,16 @@ __device__ __forceinline__ void poly2_passes(const cx_t<float> *Gs, cx_t<float> 
 // need, into LDS, and poly2_passes turns them into the cells' coefficients.  The grid itself
 // is not stored.
 template <int MH>
-__global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__restrict__ fhat,
-                                                        const float *__restrict__ colscale, int64_t ncoef,
-                                                        const DevTerm *__restrict__ terms, OrderParams<float> op,
-                                                        int nslab, cx_t<float> *__restrict__ kpoly) {
+__device__ __forceinline__ void pack_poly2_body(const Blk bk, const cx_t<float> *__restrict__ fhat,
+                                                const float *__restrict__ colscale, int64_t ncoef,
+                                                const DevTerm *__restrict__ terms, const OrderParams<float> &op,
+                                                int nslab, cx_t<float> *__restrict__ kpoly) {
   using C = cx_t<float>;
   constexpr int W = 2 * MH, NQ = Deg<float>::value + 1, HR = kPolyRows + W - 1, HS = NQ + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int K = op.nfreq, n = op.n, P = op.P, h = op.N / 2, mm1 = MH - 1;
   const int nt = op.term_end - op.term_begin;
-  const int tl = blockIdx.x / nslab, F0 = (blockIdx.x - tl * nslab) * kPolyRows, r = blockIdx.y;
+  const int tl = bk.x / nslab, F0 = (bk.x - tl * nslab) * kPolyRows, r = bk.y;
   const DevTerm tm = terms[op.term_begin + tl];
   const C *__restrict__ src = fhat + (int64_t)r * ncoef + tm.coef_off;
   const float *__restrict__ cs = colscale ? colscale + tm.coef_off : nullptr;
@@ -271,6 +295,14 @@ __global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__res
   poly2_passes<MH>(Gs, H, n, P, op.poly, F0, nt, tl, r, kpoly);
 }
 
+template <int MH>
+__global__ __launch_bounds__(kPackBS) void k_pack_poly2(const cx_t<float> *__restrict__ fhat,
+                                                        const float *__restrict__ colscale, int64_t ncoef,
+                                                        const DevTerm *__restrict__ terms, OrderParams<float> op,
+                                                        int nslab, cx_t<float> *__restrict__ kpoly) {
+  pack_poly2_body<MH>(Blk{(int)blockIdx.x, (int)blockIdx.y}, fhat, colscale, ncoef, terms, op, nslab, kpoly);
+}
+
 typedef float v16f_t __attribute__((ext_vector_type(16)));
 
 // Four consecutive 64-byte rows at a wavefront-uniform, 64-byte aligned address into scalar
@@ -297,21 +329,20 @@ __device__ __forceinline__ void sload_rows4(const void *p, v16f_t (&r)[4], float
 // as scalar operands; the node coordinates come from the binning's sorted copy (xs, two
 // per position).  Results go to the term's output slot as in k_gather_sorted.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ xs,
-                                                      const CellItem *__restrict__ items, int nitems,
-                                                      const int32_t *__restrict__ perm,
-                                                      OrderParams<float> op,
-                                                      const cx_t<float> *__restrict__ kpoly, int64_t vstride,
-                                                      int slot_base, cx_t<float> *__restrict__ slots, int64_t Vtot) {
+__device__ __forceinline__ void gather_poly2_body(const Blk bk, const float *__restrict__ xs,
+                                                  const CellItem *__restrict__ items, int nitems,
+                                                  const int32_t *__restrict__ perm, const OrderParams<float> &op,
+                                                  const cx_t<float> *__restrict__ kpoly, int64_t vstride,
+                                                  int slot_base, cx_t<float> *__restrict__ slots, int64_t Vtot) {
   static_assert(std::is_same<T, float>::value, "FP32 only");
   using C = cx_t<float>;
   constexpr int NQ = Deg<float>::value + 1;
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ii = xcd_contiguous(blockIdx.x, gridDim.x) * 4 + wv;
+  const int ii = bk.x * 4 + wv;
   if (ii >= nitems) return;   // whole wavefront; no workgroup barrier follows
   const CellItem it = items[ii];
-  const int r = it.r + (int)blockIdx.y;
+  const int r = it.r + bk.y;
   const int n = op.n, nt = op.term_end - op.term_begin;
   const bool act = l < it.count;
   const int c0 = it.cell[0], c1 = it.cell[1];
@@ -348,6 +379,17 @@ __global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ 
     }
   }
   if (act) slots[(int64_t)(slot_base + op.term_begin + it.tl) * Vtot + (int64_t)r * vstride + node] = cmake<float>(fr, fi);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_poly2(const float *__restrict__ xs,
+                                                      const CellItem *__restrict__ items, int nitems,
+                                                      const int32_t *__restrict__ perm,
+                                                      OrderParams<float> op,
+                                                      const cx_t<float> *__restrict__ kpoly, int64_t vstride,
+                                                      int slot_base, cx_t<float> *__restrict__ slots, int64_t Vtot) {
+  gather_poly2_body<T>(Blk{xcd_contiguous(blockIdx.x, gridDim.x), (int)blockIdx.y}, xs, items, nitems, perm, op, kpoly,
+                       vstride, slot_base, slots, Vtot);
 }
 
 }  // namespace gt

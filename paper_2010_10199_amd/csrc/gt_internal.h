@@ -46,6 +46,12 @@ constexpr int tile_side(int m) { return 17 - 2 * m; }
 constexpr int kPackBS = 512;   // threads of the pack and adjoint-DFT workgroups
 constexpr int kVecBS = 256;
 
+// Block coordinates of a kernel body: the grid's when the body runs as its own kernel, or
+// the part's own numbering inside a launch that runs several bodies side by side.
+struct Blk {
+  int x, y;
+};
+
 template <typename T> struct Deg;                   // window polynomial degree per precision
 template <> struct Deg<float> { static constexpr int value = 7; };
 template <> struct Deg<double> { static constexpr int value = 14; };
@@ -209,6 +215,7 @@ struct gt_plan {
   hipStream_t side = nullptr;         // second stream (default priority) for the order-1 kernels
   bool use_side = true;               // fork order 1 onto the side stream (a tuning choice)
   bool use_graph = false;             // gt_plan_trafo / gt_plan_adjoint replay a captured graph (a tuning choice)
+  bool use_fused = false;             // orders 1 and 2 in shared launches (a tuning choice; fused_available)
   struct GraphEntry {
     int dir;                          // 0 forward, 1 adjoint
     const void *in;
@@ -239,6 +246,15 @@ int hip_fail(hipError_t e, const char *what);
 
 // ---- profiling of launches ----
 bool prof_enabled();
+// Whether the plan's transforms can run in the shared launches of both orders (orders 1 and
+// 2 only, both with window forms and one window width, all gather slots in one block, the
+// order-2 fold in its tile-sum form within the LDS limit).
+bool fused_available(const gt_plan *pl);
+
+// Grid copies of the order-1 binned spread: kSpreadWaves (sums in a fixed order) when they
+// fit in LDS, else 1 (one shared grid, atomic adds).
+int spread1_copies(const gt_plan *pl);
+
 void prof_begin(hipStream_t s, const char *name);
 void prof_end(hipStream_t s);
 bool prof_set(bool on);                                   // returns the previous state

@@ -56,6 +56,20 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
   }
 }
 
+// A value that is the same in every lane of the wavefront, held in a scalar register.  Loads
+// from kernel-argument pointers are scalar loads already when the compiler can see that
+// nothing stores to that memory before them; in a launch that runs several kernel bodies it
+// may not, and the loaded tables would take vector registers instead.
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Bijection on [0, nb) giving the blocks of each XCD (block b runs on XCD b mod 8) one
 // contiguous range of logical indices.
 __device__ __forceinline__ int xcd_contiguous(int b, int nb) {
@@ -87,13 +101,13 @@ __device__ __forceinline__ void window_values(T z, const T *__restrict__ poly, T
   const T z2 = z * z;
 #pragma unroll
   for (int j = 0; j < MH; ++j) {
-    const T *c = poly + j * (D + 1);
-    T e = c[DE];
+    const T *c = poly + j * (D + 1);   // the same table in every lane
+    T e = wave_uniform(c[DE]);
 #pragma unroll
-    for (int q = DE - 2; q >= 0; q -= 2) e = fma(e, z2, c[q]);
-    T o = c[DO];
+    for (int q = DE - 2; q >= 0; q -= 2) e = fma(e, z2, wave_uniform(c[q]));
+    T o = wave_uniform(c[DO]);
 #pragma unroll
-    for (int q = DO - 2; q >= 1; q -= 2) o = fma(o, z2, c[q]);
+    for (int q = DO - 2; q >= 1; q -= 2) o = fma(o, z2, wave_uniform(c[q]));
     o *= z;
     psi[j] = e + o;
     psi[2 * MH - 1 - j] = e - o;
@@ -159,16 +173,17 @@ static __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 // The last stage's outputs are split over `slices` workgroups per term (each recomputes the
 // earlier, smaller stages), so a launch has slices x terms workgroups.
 template <typename T, int ORDER>
-__global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict__ fhat, const T *__restrict__ colscale,
-                                                      int64_t ncoef, const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                      cx_t<T> *__restrict__ grids, int64_t grid_total, int slices) {
+__device__ __forceinline__ void pack_fwd_body(const Blk bk, const cx_t<T> *__restrict__ fhat,
+                                              const T *__restrict__ colscale, int64_t ncoef,
+                                              const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                              cx_t<T> *__restrict__ grids, int64_t grid_total, int slices) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
   const int tid = threadIdx.x, BS = blockDim.x;
-  const int slice = blockIdx.x % slices;
-  const DevTerm tm = terms[op.term_begin + blockIdx.x / slices];
-  const int r = blockIdx.y;
+  const int slice = bk.x % slices;
+  const DevTerm tm = terms[op.term_begin + bk.x / slices];
+  const int r = bk.y;
   const C *src = fhat + (int64_t)r * ncoef + tm.coef_off;
   const T *cs = colscale ? colscale + tm.coef_off : nullptr;
   C *dst = grids + (int64_t)r * grid_total + tm.grid_off;
@@ -295,6 +310,14 @@ __global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict_
       dst[i] = cmake<T>(re, im);
     }
   }
+}
+
+template <typename T, int ORDER>
+__global__ __launch_bounds__(kPackBS) void k_pack_fwd(const cx_t<T> *__restrict__ fhat, const T *__restrict__ colscale,
+                                                      int64_t ncoef, const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                      cx_t<T> *__restrict__ grids, int64_t grid_total, int slices) {
+  pack_fwd_body<T, ORDER>(Blk{(int)blockIdx.x, (int)blockIdx.y}, fhat, colscale, ncoef, terms, op, grids, grid_total,
+                          slices);
 }
 
 // ------------------------------------------------------------------ K3 gather
@@ -436,10 +459,10 @@ namespace gt {
 // workgroup adds the partials needs a device-scope fence per workgroup, an L2 write-back that
 // slowed the adjoint kernels running beside it.)
 template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_empty_part(const WorkItem *__restrict__ items,
-                                                          const cx_t<T> *__restrict__ y, double *__restrict__ ysum) {
+__device__ __forceinline__ void empty_part_body(const Blk bk, const WorkItem *__restrict__ items,
+                                                const cx_t<T> *__restrict__ y, double *__restrict__ ysum) {
   __shared__ double sh[2 * (kGatherBS / 64)];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[bk.x];
   double a = 0, b = 0;
   if ((int)threadIdx.x < it.count) {
     const cx_t<T> v = y[it.v0 + threadIdx.x];
@@ -448,17 +471,23 @@ __global__ __launch_bounds__(kGatherBS) void k_empty_part(const WorkItem *__rest
   }
   block_sum2(a, b, sh);
   if (threadIdx.x == 0) {
-    ysum[2 * blockIdx.x] = a;
-    ysum[2 * blockIdx.x + 1] = b;
+    ysum[2 * bk.x] = a;
+    ysum[2 * bk.x + 1] = b;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restrict__ item_begin,
-                                                         const double *__restrict__ ysum, int64_t ncoef,
-                                                         cx_t<T> *__restrict__ fhat) {
+__global__ __launch_bounds__(kGatherBS) void k_empty_part(const WorkItem *__restrict__ items,
+                                                          const cx_t<T> *__restrict__ y, double *__restrict__ ysum) {
+  empty_part_body<T>(Blk{(int)blockIdx.x, 0}, items, y, ysum);
+}
+
+template <typename T>
+__device__ __forceinline__ void empty_adj_body(const Blk bk, const int32_t *__restrict__ item_begin,
+                                               const double *__restrict__ ysum, int64_t ncoef,
+                                               cx_t<T> *__restrict__ fhat) {
   __shared__ double sh[2 * (kGatherBS / 64)];
-  const int r = blockIdx.x;
+  const int r = bk.x;
   double a = 0, b = 0;
   for (int i = item_begin[r] + threadIdx.x; i < item_begin[r + 1]; i += kGatherBS) {
     a += ysum[2 * i];
@@ -468,25 +497,32 @@ __global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restri
   if (threadIdx.x == 0) fhat[(int64_t)r * ncoef] = cmake<T>((T)a, (T)b);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kGatherBS) void k_empty_adj(const int32_t *__restrict__ item_begin,
+                                                         const double *__restrict__ ysum, int64_t ncoef,
+                                                         cx_t<T> *__restrict__ fhat) {
+  empty_adj_body<T>(Blk{(int)blockIdx.x, 0}, item_begin, ysum, ncoef, fhat);
+}
+
 // ------------------------------------------------------------------ fold of the spread partials
 // One output per unpadded grid point l of (right-hand side, term): sum over the spread items
 // of that right-hand side and over the halo copies p of l (p = l + m - 1 mod n, + n, ...),
 // in FP64.  Workgroup = 64 points x 4 parts (part q takes items q, q+4, ...), combined in a
 // fixed order.  gsum layout: [r][term_local][outer][n] with outer = n^(order-1).
 template <typename T>
-__global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict__ gpart, int64_t gstride,
-                                                       const int32_t *__restrict__ item_begin,
-                                                       const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                       int order, cx_t<T> *__restrict__ gsum) {
+__device__ __forceinline__ void fold_partials_body(const Blk bk, const cx_t<T> *__restrict__ gpart, int64_t gstride,
+                                                   const int32_t *__restrict__ item_begin,
+                                                   const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                                   int order, cx_t<T> *__restrict__ gsum) {
   __shared__ double part[4][64][2];
   const int n = op.n, P = op.P, mm1 = op.m - 1;
   const int nt = op.term_end - op.term_begin;
   const int64_t outer = order == 1 ? 1 : (order == 2 ? n : (int64_t)n * n);
   const int64_t per_term = outer * n;
-  const int64_t idx = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t idx = (int64_t)bk.x * 64 + (threadIdx.x & 63);
   const int q = threadIdx.x >> 6;
   const bool active = idx < per_term * nt;
-  const int r = blockIdx.y;
+  const int r = bk.y;
   const int tl = active ? (int)(idx / per_term) : 0;
   const int64_t rem = idx - (int64_t)tl * per_term;
   const int64_t o = rem / n;
@@ -542,23 +578,31 @@ __global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_partials(const cx_t<T> *__restrict__ gpart, int64_t gstride,
+                                                       const int32_t *__restrict__ item_begin,
+                                                       const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                       int order, cx_t<T> *__restrict__ gsum) {
+  fold_partials_body<T>(Blk{(int)blockIdx.x, (int)blockIdx.y}, gpart, gstride, item_begin, terms, op, order, gsum);
+}
+
 // ------------------------------------------------------------------ K2 + K5 adjoint
 // One workgroup per (term, right-hand side): the folded grid, pruned forward DFT to the
 // (N-1)^t non-zero frequencies, deconvolve, write in group order.
 template <typename T, int ORDER>
-__global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
-                                                     const DevTerm *__restrict__ terms, OrderParams<T> op,
-                                                     const T *__restrict__ colscale, int64_t ncoef,
-                                                     cx_t<T> *__restrict__ fhat, int ntile, int ts, int nsplit) {
+__device__ __forceinline__ void dft_adj_body(const Blk bk, const cx_t<T> *__restrict__ gsum,
+                                             const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                             const T *__restrict__ colscale, int64_t ncoef,
+                                             cx_t<T> *__restrict__ fhat, int ntile, int ts, int nsplit) {
   using C = cx_t<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *S = reinterpret_cast<C *>(smem_raw);
   const int tid = threadIdx.x, BS = blockDim.x;
   // order 2: nsplit workgroups per term, workgroup sp computing the coefficient columns
   // a2 in [sp K / nsplit, (sp + 1) K / nsplit) (both DFT stages split along a2)
-  const int tl = blockIdx.x / nsplit, sp = blockIdx.x - tl * nsplit;
+  const int tl = bk.x / nsplit, sp = bk.x - tl * nsplit;
   const DevTerm tm = terms[op.term_begin + tl];
-  const int r = blockIdx.y;
+  const int r = bk.y;
   const int nt = op.term_end - op.term_begin;
   const int K = op.nfreq, n = op.n, h = op.N / 2;
   // LDS: the DFT stage arrays, then the table of DFT factors (then, order 2, the column sums)
@@ -747,6 +791,15 @@ __global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(
       dst[i] = cmake<T>(re * sc, im * sc);
     }
   }
+}
+
+template <typename T, int ORDER>
+__global__ __launch_bounds__(ORDER == 2 ? 2 * kPackBS : kPackBS) void k_dft_adj(const cx_t<T> *__restrict__ gsum,
+                                                     const DevTerm *__restrict__ terms, OrderParams<T> op,
+                                                     const T *__restrict__ colscale, int64_t ncoef,
+                                                     cx_t<T> *__restrict__ fhat, int ntile, int ts, int nsplit) {
+  dft_adj_body<T, ORDER>(Blk{(int)blockIdx.x, (int)blockIdx.y}, gsum, terms, op, colscale, ncoef, fhat, ntile, ts,
+                         nsplit);
 }
 
 // ------------------------------------------------------------------ K9 node gradient
@@ -1000,6 +1053,10 @@ __global__ __launch_bounds__(kVecBS) void k_cos_fold(const cx_t<T> *__restrict__
 }
 
 // ------------------------------------------------------------------ launchers
+}  // namespace gt
+#include "fused.h"   // shared launches of orders 1 and 2
+namespace gt {
+
 template <typename T>
 static OrderParams<T> order_params(const gt_plan *pl, int t) {
   const OrderHost &o = pl->ord[t];
@@ -1196,11 +1253,254 @@ static int launch_direct_adj(gt_plan *pl, int t, const void *y, const T *colscal
   return check_launch("k_direct_adj_sum");
 }
 
+static Tile2Args tile2_args(const gt_plan *pl) {
+  const OrderHost &o = pl->ord[2];
+  Tile2Args ta;
+  ta.waves = o.d_waves2;
+  ta.nwaves = o.nwaves2;
+  ta.ntile = o.ntile;
+  ta.nseg = o.nseg2;
+  ta.vstride = pl->ragged ? 0 : pl->M;
+  ta.ragged = pl->ragged ? 1 : 0;
+  return ta;
+}
+
+// ---- shared launches of orders 1 and 2 (fused.h)
+
+// Forward: packs of both orders, gathers of both orders, then the sum over u.
+template <typename T>
+static int fused_forward(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
+  using C = cx_t<T>;
+  const OrderHost &o1 = pl->ord[1], &o2 = pl->ord[2];
+  const int nt1 = o1.term_end - o1.term_begin, nt2 = o2.term_end - o2.term_begin, R = pl->R;
+  const bool poly = std::is_same<T, float>::value && o2.path == GT_GATHER_POLY;
+  // 1. K1 + K2 of both orders (order 2 straight into the window polynomials when it gathers
+  //    in that basis)
+  FwdPackArgs<T> pa;
+  pa.fhat = (const C *)fhat;
+  pa.colscale = colscale;
+  pa.ncoef = pl->ncoef_int;
+  pa.terms = pl->d_terms;
+  pa.grids = (C *)pl->d_grid;
+  pa.grid_total = pl->grid_total;
+  pa.op1 = order_params<T>(pl, 1);
+  pa.op2 = order_params<T>(pl, 2);
+  pa.slices1 = 4;
+  pa.slices2 = 8;
+  pa.nslab = (o2.n + kPolyRows - 1) / kPolyRows;
+  pa.kpoly = (C *)o2.d_kpoly;
+  pa.p1 = Part{0, nt1 * pa.slices1, R};
+  pa.p2 = Part{pa.p1.nx * R, nt2 * (poly ? pa.nslab : pa.slices2), R};
+  const unsigned nbp = (unsigned)(pa.p2.b0 + pa.p2.nx * pa.p2.ny);
+  const size_t plds = std::max(pack_lds<T>(pl, 1), poly ? poly_pack_lds(o2) : pack_lds<T>(pl, 2));
+  prof_begin(s, "pack_fwd_12");
+  if (poly) {
+    if constexpr (std::is_same<T, float>::value) {
+#define GT_LAUNCH_FPACK(MH)                                                                  \
+  {                                                                                          \
+    if (int rc = set_lds(k_fwd_pack2<T, MH>, plds)) return rc;                               \
+    hipLaunchKernelGGL((k_fwd_pack2<T, MH>), dim3(nbp), dim3(kPackBS), plds, s, pa);         \
+  }
+      GT_DISPATCH_M(o2.m, GT_LAUNCH_FPACK)
+#undef GT_LAUNCH_FPACK
+    }
+  } else {
+    if (int rc = set_lds(k_fwd_pack2<T, 0>, plds)) return rc;
+    hipLaunchKernelGGL((k_fwd_pack2<T, 0>), dim3(nbp), dim3(kPackBS), plds, s, pa);
+  }
+  prof_end(s);
+  if (int rc = check_launch("k_fwd_pack2")) return rc;
+  // 2. K3 of both orders, each term into its slot (term u -> slot u - 1)
+  FwdGatherArgs<T> ga;
+  ga.x = (const T *)pl->d_x;
+  ga.Mtot = pl->Mtot;
+  ga.terms = pl->d_terms;
+  ga.grids = (const C *)pl->d_grid;
+  ga.grid_total = pl->grid_total;
+  ga.op1 = pa.op1;
+  ga.op2 = pa.op2;
+  ga.perm1 = o1.d_perm;
+  ga.perm2 = o2.d_perm;
+  ga.xs2 = (const T *)o2.d_xs;
+  ga.kpoly = (const C *)o2.d_kpoly;
+  ga.vstride = pl->ragged ? 0 : pl->M;
+  ga.sbase1 = ga.sbase2 = -1;
+  ga.slots = (C *)pl->d_fpart;
+  ga.Vtot = pl->Vtot;
+  size_t glds = 0;
+  int b0 = 0;
+  auto gpart = [&](const OrderHost &o, int nt, const GatherItem *&gi, const CellItem *&ci, int &nci) {
+    Part p;
+    gi = nullptr;
+    ci = nullptr;
+    nci = 0;
+    if (o.path == GT_GATHER_SORTED) {
+      const int i0 = o.gitem_begin[0], i1 = o.gitem_begin[nt];
+      gi = o.d_gitems + i0;
+      p = Part{b0, i1 - i0, 1};
+      glds = std::max(glds, (size_t)o.gsize * sizeof(C));
+    } else {
+      const int c0 = o.citem_begin[0], c1 = o.citem_begin[nt];
+      ci = o.d_citems + c0;
+      nci = c1 - c0;
+      p = Part{b0, (nci + 3) / 4, pl->ragged ? 1 : R};
+    }
+    b0 += p.nx * p.ny;
+    return p;
+  };
+  ga.p1 = gpart(o1, nt1, ga.gi1, ga.ci1, ga.nci1);
+  ga.p2 = gpart(o2, nt2, ga.gi2, ga.ci2, ga.nci2);
+  prof_begin(s, "gather_12");
+#define GT_LAUNCH_FG(MH, K1, K2)                                                                 \
+  {                                                                                              \
+    if (int rc = set_lds(k_fwd_gather2<T, MH, K1, K2>, glds)) return rc;                         \
+    hipLaunchKernelGGL((k_fwd_gather2<T, MH, K1, K2>), dim3((unsigned)b0), dim3(256), glds, s, ga); \
+  }
+#define GT_LAUNCH_FGATHER(MH)                                                                          \
+  {                                                                                                    \
+    const bool s1 = o1.path == GT_GATHER_SORTED;                                                       \
+    if (o2.path == GT_GATHER_POLY) {                                                                   \
+      if constexpr (std::is_same<T, float>::value) {                                                   \
+        if (s1) GT_LAUNCH_FG(MH, GT_GATHER_SORTED, GT_GATHER_POLY)                                     \
+        else GT_LAUNCH_FG(MH, GT_GATHER_CELL, GT_GATHER_POLY)                                          \
+      }                                                                                                \
+    } else if (o2.path == GT_GATHER_SORTED) {                                                          \
+      if (s1) GT_LAUNCH_FG(MH, GT_GATHER_SORTED, GT_GATHER_SORTED)                                     \
+      else GT_LAUNCH_FG(MH, GT_GATHER_CELL, GT_GATHER_SORTED)                                          \
+    } else {                                                                                           \
+      if (s1) GT_LAUNCH_FG(MH, GT_GATHER_SORTED, GT_GATHER_CELL)                                       \
+      else GT_LAUNCH_FG(MH, GT_GATHER_CELL, GT_GATHER_CELL)                                            \
+    }                                                                                                  \
+  }
+  GT_DISPATCH_M(o1.m, GT_LAUNCH_FGATHER)
+#undef GT_LAUNCH_FGATHER
+#undef GT_LAUNCH_FG
+  prof_end(s);
+  if (int rc = check_launch("k_fwd_gather2")) return rc;
+  // 3. the sum over u per node, with the empty set's coefficient
+  const int ngi = (int)pl->gitems.size();
+  prof_begin(s, "reduce_f");
+  hipLaunchKernelGGL((k_reduce_f<T>), dim3(4 * ngi), dim3(256), 0, s, (const C *)fhat, pl->ncoef_int, pl->d_gitems,
+                     (const C *)pl->d_fpart, nt1 + nt2, pl->Vtot, 0, (C *)f);
+  prof_end(s);
+  return check_launch("k_reduce_f");
+}
+
+// Adjoint: spreads of both orders with the empty set's partial sums, folds of both orders
+// with the empty set's coefficient, then the DFTs of both orders.
+template <typename T>
+static int fused_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
+  using C = cx_t<T>;
+  const OrderHost &o1 = pl->ord[1], &o2 = pl->ord[2];
+  const int nt1 = o1.term_end - o1.term_begin, nt2 = o2.term_end - o2.term_begin, R = pl->R;
+  const int ngi = (int)pl->gitems.size();
+  const OrderParams<T> op1 = order_params<T>(pl, 1), op2 = order_params<T>(pl, 2);
+  const Tile2Args ta = tile2_args(pl);
+  // 1. K4: order 2 on tiles, order 1 binned, the empty set's partial sums
+  AdjSpreadArgs<T> sa;
+  sa.x = (const T *)pl->d_x;
+  sa.Mtot = pl->Mtot;
+  sa.terms = pl->d_terms;
+  sa.y = (const C *)y;
+  sa.si1 = o1.d_sitems;
+  sa.op1 = op1;
+  sa.sa1.perm = o1.d_perm;
+  sa.sa1.cstart = o1.d_cstart;
+  sa.sa1.B = pl->ragged ? R : 1;
+  sa.sa1.ncell = o1.nkey;
+  sa.sa1.vstride = pl->ragged ? 0 : pl->M;
+  sa.sa1.copies = spread1_copies(pl);
+  sa.gpart1 = (C *)o1.d_gpart;
+  sa.gstride1 = o1.gpart_stride;
+  sa.xs2 = (const T *)o2.d_xs;
+  sa.perm2 = (const int32_t *)o2.d_perm;
+  sa.op2 = op2;
+  sa.ta = ta;
+  sa.patch = (C *)o2.d_patch;
+  sa.gitems = pl->d_gitems;
+  sa.ysum = pl->d_ysum;
+  sa.p2 = Part{0, (o2.nwaves2 + kTileWaves - 1) / kTileWaves, pl->ragged ? 1 : R};
+  sa.p1 = Part{sa.p2.nx * sa.p2.ny, (int)o1.sitems.size(), nt1};
+  sa.pe = Part{sa.p1.b0 + sa.p1.nx * sa.p1.ny, ngi, 1};
+  const unsigned nbs = (unsigned)(sa.pe.b0 + sa.pe.nx);
+  // padded so that at most tile_wg_cu workgroups share a compute unit
+  const size_t slds = std::max({(size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T)),
+                                pl->lds_limit / o2.tile_wg_cu,
+                                (size_t)sa.sa1.copies * o1.gsize * sizeof(double2)});
+  prof_begin(s, "spread_12");
+#define GT_LAUNCH_FSPREAD(MH)                                                                \
+  {                                                                                          \
+    if (int rc = set_lds(k_adj_spread2<T, MH>, slds)) return rc;                             \
+    hipLaunchKernelGGL((k_adj_spread2<T, MH>), dim3(nbs), dim3(64 * kTileWaves), slds, s, sa); \
+  }
+  GT_DISPATCH_M(o1.m, GT_LAUNCH_FSPREAD)
+#undef GT_LAUNCH_FSPREAD
+  prof_end(s);
+  if (int rc = check_launch("k_adj_spread2")) return rc;
+  // 2. folds: order-2 patches into column sums (tile-sum form), order-1 partial grids, and
+  //    the empty set's coefficient
+  AdjFoldArgs<T> fa;
+  fa.terms = pl->d_terms;
+  fa.gpart1 = (const C *)o1.d_gpart;
+  fa.gstride1 = o1.gpart_stride;
+  fa.sitem_begin1 = o1.d_sitem_begin;
+  fa.op1 = op1;
+  fa.gsum1 = (C *)o1.d_gsum;
+  fa.patch = (const C *)o2.d_patch;
+  fa.tileseg = o2.d_tileseg;
+  fa.op2 = op2;
+  fa.ta = ta;
+  fa.B = pl->ragged ? R : 1;
+  fa.ts = o2.ts;
+  fa.nunits2 = nt2 * o2.ntile * 4;
+  fa.hcol2 = (C *)o2.d_tsum;
+  fa.gitem_begin = pl->d_gitem_begin;
+  fa.ysum = (const double *)pl->d_ysum;
+  fa.ncoef = pl->ncoef_int;
+  fa.fhat = (C *)fhat;
+  fa.p2 = Part{0, nt2 * o2.ntile, R};
+  const int64_t pts1 = (int64_t)o1.n * nt1;
+  fa.p1 = Part{fa.p2.nx * fa.p2.ny, (int)((pts1 + 63) / 64), R};
+  fa.pe = Part{fa.p1.b0 + fa.p1.nx * fa.p1.ny, R, 1};
+  const unsigned nbf = (unsigned)(fa.pe.b0 + fa.pe.nx);
+  const size_t flds = (size_t)4 * o2.ntile * 64 * sizeof(C);
+  prof_begin(s, "fold_12");
+  if (int rc = set_lds(k_adj_fold2<T>, flds)) return rc;
+  hipLaunchKernelGGL((k_adj_fold2<T>), dim3(nbf), dim3(256), flds, s, fa);
+  prof_end(s);
+  if (int rc = check_launch("k_adj_fold2")) return rc;
+  // 3. K2 + K5 of both orders
+  AdjDftArgs<T> da;
+  da.terms = pl->d_terms;
+  da.colscale = colscale;
+  da.ncoef = pl->ncoef_int;
+  da.fhat = (C *)fhat;
+  da.gsum1 = (const C *)o1.d_gsum;
+  da.op1 = op1;
+  da.hcol2 = (const C *)o2.d_tsum;
+  da.op2 = op2;
+  const size_t lds_h = (size_t)o2.ntile * 16 * o2.n * sizeof(C);
+  const bool stage_h = adj_lds<T>(pl, 2) + lds_h <= pl->lds_limit;
+  da.ntile2 = stage_h ? o2.ntile : -o2.ntile;
+  da.ts2 = o2.ts;
+  da.nsplit2 = std::max(1, std::min(4, (o2.N - 1) / 8));
+  da.p2 = Part{0, nt2 * da.nsplit2, R};
+  da.p1 = Part{da.p2.nx * da.p2.ny, nt1, R};
+  const unsigned nbd = (unsigned)(da.p1.b0 + da.p1.nx * da.p1.ny);
+  const size_t dlds = std::max(adj_lds<T>(pl, 1), adj_lds<T>(pl, 2) + (stage_h ? lds_h : 0));
+  prof_begin(s, "dft_adj_12");
+  if (int rc = set_lds(k_adj_dft2<T>, dlds)) return rc;
+  hipLaunchKernelGGL((k_adj_dft2<T>), dim3(nbd), dim3(2 * kPackBS), dlds, s, da);
+  prof_end(s);
+  return check_launch("k_adj_dft2");
+}
+
 template <typename T>
 static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *f, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
   if (ngi == 0) return launch_pack<T>(pl, fhat, colscale, s);
+  if (pl->use_fused && fused_available(pl)) return fused_forward<T>(pl, fhat, colscale, f, s);
   // The window orders' terms, numbered 1..nt_all in term order without the direct orders'
   // (position = term - dshift[t]), in blocks of nslots; each block: gathers into slots, then
   // one reduction.  The direct orders add their sums afterwards.
@@ -1332,22 +1632,12 @@ static int forward_core(gt_plan *pl, const void *fhat, const T *colscale, void *
   return GT_OK;
 }
 
-static Tile2Args tile2_args(const gt_plan *pl) {
-  const OrderHost &o = pl->ord[2];
-  Tile2Args ta;
-  ta.waves = o.d_waves2;
-  ta.nwaves = o.nwaves2;
-  ta.ntile = o.ntile;
-  ta.nseg = o.nseg2;
-  ta.vstride = pl->ragged ? 0 : pl->M;
-  ta.ragged = pl->ragged ? 1 : 0;
-  return ta;
-}
 
 template <typename T>
 static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fhat, hipStream_t s) {
   using C = cx_t<T>;
   const int ngi = (int)pl->gitems.size();
+  if (pl->use_fused && fused_available(pl)) return fused_adjoint<T>(pl, y, colscale, fhat, s);
   const bool fk = fork_side(pl, s);
   for (int t = 1; t <= pl->ds; ++t) {
     const hipStream_t st = (fk && t == 1) ? pl->side : s;
@@ -1366,7 +1656,8 @@ static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fha
     sa.B = pl->ragged ? pl->R : 1;
     sa.ncell = o.nkey;
     sa.vstride = pl->ragged ? 0 : pl->M;
-    const size_t lds = (size_t)o.gsize * sizeof(double2);
+    sa.copies = t == 1 ? spread1_copies(pl) : 1;
+    const size_t lds = (size_t)sa.copies * o.gsize * sizeof(double2);
     dim3 grid(nsi, nt);
     prof_begin(st, t == 1 ? "spread_1d" : t == 2 ? "spread_2d" : "spread_3d");
 #define GT_LAUNCH_SPREAD(MH)                                                                                      \

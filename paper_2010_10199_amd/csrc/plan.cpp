@@ -627,6 +627,26 @@ bool gt::direct_adj_ok(const gt_plan *pl, int t) {
   return direct_adj_rtw(pl, t) > 0 && lds <= pl->lds_limit;
 }
 
+int gt::spread1_copies(const gt_plan *pl) {
+  if (pl->ds < 1) return 1;
+  return (size_t)kSpreadWaves * pl->ord[1].gsize * 16 <= pl->lds_limit ? kSpreadWaves : 1;
+}
+
+bool gt::fused_available(const gt_plan *pl) {
+  if (pl->ds != 2 || pl->gitems.empty()) return false;
+  const OrderHost &o1 = pl->ord[1], &o2 = pl->ord[2];
+  const int nt1 = o1.term_end - o1.term_begin, nt2 = o2.term_end - o2.term_begin;
+  if (nt1 == 0 || nt2 == 0 || o1.m != o2.m) return false;
+  if (o1.path == GT_GATHER_DIRECT || o2.path == GT_GATHER_DIRECT) return false;
+  if (o1.adj_form != GT_ADJ_WINDOW || o2.adj_form != GT_ADJ_WINDOW) return false;
+  if (pl->nslots < nt1 + nt2) return false;   // every window term's slot in one block
+  // the order-2 fold in its tile-sum form, four wavefronts' tile sums per workgroup, beside
+  // the order-1 fold's 4 KiB
+  if (o2.P > 2 * o2.n || o2.ntile > 32) return false;
+  if (spread1_copies(pl) != kSpreadWaves) return false;   // order 1 in the fixed summation order
+  return (size_t)4 * o2.ntile * 64 * 2 * pl->rsize + 4096 + 64 <= pl->lds_limit;
+}
+
 int gt::set_adjoint_form(gt_plan *pl, int t, int form) {
   OrderHost &o = pl->ord[t];
   drop_graphs(pl);
@@ -1374,6 +1394,19 @@ int gt_plan_set_graph(gt_plan *plan, int32_t on) {
   }
   drop_graphs(plan);
   plan->use_graph = on != 0;
+  return GT_OK;
+}
+
+int gt_plan_set_fused(gt_plan *plan, int32_t on) {
+  GT_LIVE(plan);
+  if (on && !gt::fused_available(plan))
+    return fail(GT_EUNSUPPORTED, "shared launches need orders 1 and 2 only, window forms and one window width");
+  if (plan->stream) {
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  drop_graphs(plan);
+  plan->use_fused = on != 0;
   return GT_OK;
 }
 

@@ -48,6 +48,7 @@ struct SpreadArgs {
   int32_t B;               // datasets (1 for shared nodes)
   int64_t ncell;           // binning keys per (term, dataset)
   int64_t vstride;         // virtual node of (r, node) = r * vstride + node  (M, or 0 when ragged)
+  int32_t copies;          // order 1: 1 (one LDS grid, atomic adds) or kSpreadWaves (grid copies)
 };
 
 // Coefficients of one window point's polynomial, held in registers; zero past the window.
@@ -69,24 +70,33 @@ struct WinPoint {
   }
 };
 
-template <typename T, int ORDER, int MH>
-__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__restrict__ xT, int64_t Mx,
-                                                                     const SpreadItem *__restrict__ items,
-                                                                     const DevTerm *__restrict__ terms,
-                                                                     OrderParams<T> op, SpreadArgs sa,
-                                                                     const cx_t<T> *__restrict__ y,
-                                                                     cx_t<T> *__restrict__ gpart, int64_t gstride) {
+// WV wavefronts per workgroup (kSpreadWaves on its own; fewer inside a shared launch), the
+// item's cells dealt round-robin to them.
+// Order 1 with sa.copies = kSpreadWaves: cell c0 + j adds its patch with plain adds into grid
+// copy j mod kSpreadWaves, and the copies are summed in order at the end.  A copy is only
+// ever written by one wavefront (WV divides kSpreadWaves), in increasing cell order, so the
+// result depends neither on the timing of the wavefronts (the atomic adds into one shared
+// grid meet in any order where neighbouring cells' windows overlap) nor on WV.  The plan
+// takes this whenever the copies fit in LDS.
+template <typename T, int ORDER, int MH, int WV>
+__device__ __forceinline__ void spread_binned_body(const Blk bk, const T *__restrict__ xT, int64_t Mx,
+                                                   const SpreadItem *__restrict__ items,
+                                                   const DevTerm *__restrict__ terms, const OrderParams<T> &op,
+                                                   const SpreadArgs &sa, const cx_t<T> *__restrict__ y,
+                                                   cx_t<T> *__restrict__ gpart, int64_t gstride) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
   constexpr int W = 2 * MH;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2 *G = reinterpret_cast<double2 *>(smem_raw);
-  const SpreadItem it = items[blockIdx.x];
-  const int tl = blockIdx.y;
+  const SpreadItem it = items[bk.x];
+  const int tl = bk.y;
   const DevTerm tm = terms[op.term_begin + tl];
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, i16 = l & 15, kk = l >> 4;
   const int n = op.n, P = op.P, gsize = op.gsize;
-  for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) G[i] = make_double2(0.0, 0.0);
+  static_assert(kSpreadWaves % WV == 0, "a grid copy belongs to one wavefront");
+  const int copies = ORDER == 1 ? sa.copies : 1;
+  for (int i = threadIdx.x; i < copies * gsize; i += 64 * WV) G[i] = make_double2(0.0, 0.0);
   WinPoint<T> wp;
   wp.load(op.poly, i16, W);
   __syncthreads();
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
   const T *x1p = xT + (int64_t)(ORDER >= 2 ? tm.c1 : tm.c0) * Mx;
   const T *x2p = xT + (int64_t)(ORDER >= 3 ? tm.c2 : tm.c0) * Mx;
   const T two_n = (T)(2 * n);
-  for (int c = it.c0 + wv; c < it.c1; c += kSpreadWaves) {   // cells round-robin over the waves
+  for (int c = it.c0 + wv; c < it.c1; c += WV) {   // cells round-robin over the waves
     const int64_t p0 = sa.cstart[key0 + c], p1 = sa.cstart[key0 + c + 1];
     if (p1 <= p0) continue;
     // cell -> first window index per axis; z = 2 n x + (n - 2 fl - 1)
@@ -139,8 +149,12 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
       for (int r = 0; r < 4; ++r) {
         const int row = MF::row(l, r);
         if (i16 < W && row < 2) {
-          double *dst = row == 0 ? &G[fl0 + i16].x : &G[fl0 + i16].y;
-          atomicAdd(dst, (double)dre[r]);
+          double2 *Gc = G + (copies > 1 ? ((c - it.c0) % copies) * gsize : 0);   // this cell's copy
+          double *dst = row == 0 ? &Gc[fl0 + i16].x : &Gc[fl0 + i16].y;
+          if (copies > 1)
+            *dst += (double)dre[r];   // distinct addresses per lane; the wavefront's LDS order
+          else
+            atomicAdd(dst, (double)dre[r]);
         }
       }
     } else {
@@ -200,8 +214,26 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__
     }
   }
   __syncthreads();
-  cx_t<T> *out = gpart + (int64_t)blockIdx.x * gstride + tm.gpart_off;
-  for (int i = threadIdx.x; i < gsize; i += 64 * kSpreadWaves) out[i] = cmake<T>((T)G[i].x, (T)G[i].y);
+  cx_t<T> *out = gpart + (int64_t)bk.x * gstride + tm.gpart_off;
+  for (int i = threadIdx.x; i < gsize; i += 64 * WV) {
+    double re = G[i].x, im = G[i].y;
+    for (int w = 1; w < copies; ++w) {
+      re += G[w * gsize + i].x;
+      im += G[w * gsize + i].y;
+    }
+    out[i] = cmake<T>((T)re, (T)im);
+  }
+}
+
+template <typename T, int ORDER, int MH>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_binned(const T *__restrict__ xT, int64_t Mx,
+                                                                     const SpreadItem *__restrict__ items,
+                                                                     const DevTerm *__restrict__ terms,
+                                                                     OrderParams<T> op, SpreadArgs sa,
+                                                                     const cx_t<T> *__restrict__ y,
+                                                                     cx_t<T> *__restrict__ gpart, int64_t gstride) {
+  spread_binned_body<T, ORDER, MH, kSpreadWaves>(Blk{(int)blockIdx.x, (int)blockIdx.y}, xT, Mx, items, terms, op, sa,
+                                                 y, gpart, gstride);
 }
 
 // Order-3 spread, MFMA tiles without window padding.  For one cell the contribution
@@ -368,10 +400,10 @@ struct Tile2Args {
 };
 
 template <typename T, int MH>
-__global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__restrict__ xs,
-                                                                  const int32_t *__restrict__ perm, OrderParams<T> op,
-                                                                  Tile2Args ta, const cx_t<T> *__restrict__ y,
-                                                                  cx_t<T> *__restrict__ patch) {
+__device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restrict__ xs,
+                                                  const int32_t *__restrict__ perm, const OrderParams<T> &op,
+                                                  const Tile2Args &ta, const cx_t<T> *__restrict__ y,
+                                                  cx_t<T> *__restrict__ patch) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
   using C = cx_t<T>;
@@ -384,12 +416,12 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__res
   const int h = l >> 5, j = l & 31, i16 = l & 15, kk = l >> 4;
   C *SAw = reinterpret_cast<C *>(smem_raw) + (size_t)wv * UB * SR;                                    // UB x SR
   T *SBw = reinterpret_cast<T *>(smem_raw + (size_t)kTileWaves * UB * SR * sizeof(C)) + (size_t)wv * UB * SR;
-  const int w = blockIdx.x * kTileWaves + wv;
+  const int w = bk.x * kTileWaves + wv;
   if (w >= ta.nwaves) return;   // whole wavefront; the kernel has no workgroup barrier
   const int32_t qbeg = ta.waves[4 * w], qend = ta.waves[4 * w + 1];
   int64_t slot = ta.waves[4 * w + 2];
-  const int r = ta.ragged ? ta.waves[4 * w + 3] : (int)blockIdx.y;
-  if (!ta.ragged) slot += (int64_t)blockIdx.y * ta.nseg;
+  const int r = ta.ragged ? ta.waves[4 * w + 3] : bk.y;
+  if (!ta.ragged) slot += (int64_t)bk.y * ta.nseg;
   const int nbat = (qend - qbeg + UB - 1) / UB;
   const int64_t vbase = (int64_t)r * ta.vstride;
   const int n = op.n, ntile = ta.ntile;
@@ -397,7 +429,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__res
   constexpr int NC = MH * (Deg<T>::value + 1);
   T cf[NC];
 #pragma unroll
-  for (int i = 0; i < NC; ++i) cf[i] = op.poly[i];
+  for (int i = 0; i < NC; ++i) cf[i] = wave_uniform(op.poly[i]);
 
   // Loads are issued unconditionally (positions past the wavefront's range are clamped to
   // its last node), so the wait counts stay exact across the unrolled pipeline.
@@ -489,6 +521,14 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__res
     }
   }
   if (dirty) store_patch();
+}
+
+template <typename T, int MH>
+__global__ __launch_bounds__(64 * kTileWaves) void k_spread_tile2(const T *__restrict__ xs,
+                                                                  const int32_t *__restrict__ perm, OrderParams<T> op,
+                                                                  Tile2Args ta, const cx_t<T> *__restrict__ y,
+                                                                  cx_t<T> *__restrict__ patch) {
+  spread_tile2_body<T, MH>(Blk{(int)blockIdx.x, (int)blockIdx.y}, xs, perm, op, ta, y, patch);
 }
 
 // Fold of the order-2 tile patches into the folded grids, in two separable passes with a
@@ -589,20 +629,19 @@ __global__ __launch_bounds__(256) void k_fold_cols(const cx_t<T> *__restrict__ p
 //   covering p, ascending, of the tile sums at (pr, p - tx ts).
 //   Needs P <= 2n and ntile <= 32 (LDS: ntile x 64 entries).
 template <typename T>
-__global__ __launch_bounds__(64) void k_fold_tilesum(const cx_t<T> *__restrict__ patch,
-                                                     const int32_t *__restrict__ tileseg, OrderParams<T> op,
-                                                     Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+__device__ __forceinline__ void fold_tilesum_body(const Blk bk, cx_t<T> *tsum, const cx_t<T> *__restrict__ patch,
+                                                  const int32_t *__restrict__ tileseg, const OrderParams<T> &op,
+                                                  const Tile2Args &ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+  // tsum: this wavefront's LDS, [tx][row of the group][column], 64 per tile
   using C = cx_t<T>;
   constexpr int U = 16;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *tsum = reinterpret_cast<C *>(smem_raw);   // [tx][row of the group][column], 64 per tile
   const int n = op.n, P = op.P, mm1 = op.m - 1, ntile = ta.ntile, ntiles = ntile * ntile;
   const int nt = op.term_end - op.term_begin;
-  const int lane = threadIdx.x;
-  const int g = blockIdx.x & 3;                // patch rows 4g .. 4g + 3
-  const int tty = blockIdx.x >> 2;             // tl * ntile + ty
+  const int lane = threadIdx.x & 63;
+  const int g = bk.x & 3;                // patch rows 4g .. 4g + 3
+  const int tty = bk.x >> 2;             // tl * ntile + ty
   const int tl = tty / ntile, ty = tty - tl * ntile;
-  const int r = blockIdx.y;
+  const int r = bk.y;
   const int b = ta.ragged ? r : 0;
   const int64_t pbase = ta.ragged ? 0 : (int64_t)r * ta.nseg;
   const int32_t *tsg = tileseg + ((int64_t)tl * B + b) * ntiles + ty * ntile;
@@ -637,7 +676,7 @@ __global__ __launch_bounds__(64) void k_fold_tilesum(const cx_t<T> *__restrict__
     }
   }
   if (ct >= 0) tsum[ct * 64 + lane] = cmake<T>(sr, si);
-  __syncthreads();
+  wave_lds_sync();   // the tile sums are this wavefront's own
   for (int o = lane; o < 4 * n; o += 64) {
     const int rl = o / n, l1 = o - rl * n;
     const int p0 = (l1 + mm1) % n;
@@ -652,6 +691,15 @@ __global__ __launch_bounds__(64) void k_fold_tilesum(const cx_t<T> *__restrict__
     }
     hcol[((int64_t)r * nt * ntile + tty) * 16 * n + (4 * g + rl) * n + l1] = cmake<T>(re, im);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_fold_tilesum(const cx_t<T> *__restrict__ patch,
+                                                     const int32_t *__restrict__ tileseg, OrderParams<T> op,
+                                                     Tile2Args ta, int B, int ts, cx_t<T> *__restrict__ hcol) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fold_tilesum_body<T>(Blk{(int)blockIdx.x, (int)blockIdx.y}, reinterpret_cast<cx_t<T> *>(smem_raw), patch, tileseg,
+                       op, ta, B, ts, hcol);
 }
 
 // k_fold_cols_seq: the same sums, one (p, tx, slot) step at a time, for grids narrower than

@@ -33,7 +33,7 @@ EXPORTS = [
     "gt_plan_lsqr", "gt_plan_fista", "fista_group_lasso_path", "gt_release_all", "gt_debug_fail_alloc",
     "gt_debug_alloc_count", "gt_plan_norm_estimate_noalloc", "lsqr_solve_path", "gt_plan_lsqr_path",
     "gt_plan_set_gather_path", "gt_plan_tune", "gt_plan_tuning", "gt_plan_set_graph", "gt_plan_adjoint_form",
-    "gt_plan_set_adjoint_form", "gt_plan_update_nodes",
+    "gt_plan_set_adjoint_form", "gt_plan_update_nodes", "gt_plan_set_fused",
 ]
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "gt_plan_tune": (C.c_int, [vp, vp]),
         "gt_plan_tuning": (i64, [vp, C.c_char_p, i64]),
         "gt_plan_set_graph": (C.c_int, [vp, i32]),
+        "gt_plan_set_fused": (C.c_int, [vp, i32]),
         "gt_plan_norm_estimate": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "gt_plan_norm_estimate_noalloc": (C.c_int, [vp, i32, C.POINTER(dbl), vp]),
         "lsqr_solve": (C.c_int, [P, vp, vp, C.POINTER(dbl), vp, i32, dbl, vp, C.POINTER(GtSolveInfo), vp]),
@@ -399,6 +400,10 @@ class Plan:
 
     def set_graph(self, on: bool = True):
         _check(self._lib.gt_plan_set_graph(self.handle, 1 if on else 0))
+
+    def set_fused(self, on: bool = True):
+        """Orders 1 and 2 in shared launches (three per direction) or in separate ones."""
+        _check(self._lib.gt_plan_set_fused(self.handle, 1 if on else 0))
 
     def close(self):
         if getattr(self, "handle", None):

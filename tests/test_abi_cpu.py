@@ -117,6 +117,7 @@ def test_allocation_failure_hook_and_plan_handles_on_cpu():
     assert L.gt_plan_tune(bogus, None) == lib.GT_EINVAL
     assert L.gt_plan_tuning(bogus, None, 0) == lib.GT_EINVAL
     assert L.gt_plan_set_graph(bogus, 1) == lib.GT_EINVAL
+    assert L.gt_plan_set_fused(bogus, 1) == lib.GT_EINVAL
     assert L.gt_plan_set_gather_path(bogus, 1, lib.GT_GATHER_SORTED) == lib.GT_EINVAL
     assert L.gt_plan_destroy(None) == lib.GT_OK
     assert L.gt_release_all() == lib.GT_OK
