@@ -421,7 +421,7 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
       double fu = 0;
       pl->use_fused = true;
       rc = time_calls(pl, 3, b, s, e0, e1, &fu);
-      pl->use_fused = rc == GT_OK && fu < std::min(on, off);
+      pl->use_fused = rc == GT_OK && fu < 0.95 * std::min(on, off);   // only a clear gain
       snprintf(tmp, sizeof(tmp), ", \"fused\": {\"on\": %.4f, \"off\": %.4f, \"chosen\": %s}", fu,
                std::min(on, off), pl->use_fused ? "true" : "false");
       js += tmp;
