@@ -88,14 +88,9 @@ __global__ __launch_bounds__(256) void k_fwd_gather2(FwdGatherArgs<T> a) {
   static_assert(K1 != GT_GATHER_POLY && (K2 != GT_GATHER_POLY || std::is_same<T, float>::value), "no such form");
   const int b = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
   Blk bk;
-  if (in_part(b, a.p1, bk)) {
-    if constexpr (K1 == GT_GATHER_SORTED)
-      gather_sorted_body<T, 1, MH>(bk, a.x, a.Mtot, a.gi1, a.perm1, a.terms, a.op1, a.grids, a.grid_total, a.vstride,
-                                   a.sbase1, a.slots, a.Vtot);
-    else
-      gather_cell_body<T, 1, MH>(bk, a.x, a.Mtot, a.ci1, a.nci1, a.perm1, a.terms, a.op1, a.grids, a.grid_total,
-                                 a.vstride, a.sbase1, a.slots, a.Vtot);
-  } else if (in_part(b, a.p2, bk)) {
+  // (order 2 tested first: with the polynomial form first the compiler keeps the order-1
+  // cell gather's grid reads as scalar loads, 22 registers against 53 the other way round)
+  if (in_part(b, a.p2, bk)) {
     if constexpr (K2 == GT_GATHER_POLY)
       gather_poly2_body<T>(bk, a.xs2, a.ci2, a.nci2, a.perm2, a.op2, a.kpoly, a.vstride, a.sbase2, a.slots, a.Vtot);
     else if constexpr (K2 == GT_GATHER_SORTED)
@@ -104,6 +99,13 @@ __global__ __launch_bounds__(256) void k_fwd_gather2(FwdGatherArgs<T> a) {
     else
       gather_cell_body<T, 2, MH>(bk, a.x, a.Mtot, a.ci2, a.nci2, a.perm2, a.terms, a.op2, a.grids, a.grid_total,
                                  a.vstride, a.sbase2, a.slots, a.Vtot);
+  } else if (in_part(b, a.p1, bk)) {
+    if constexpr (K1 == GT_GATHER_SORTED)
+      gather_sorted_body<T, 1, MH>(bk, a.x, a.Mtot, a.gi1, a.perm1, a.terms, a.op1, a.grids, a.grid_total, a.vstride,
+                                   a.sbase1, a.slots, a.Vtot);
+    else
+      gather_cell_body<T, 1, MH>(bk, a.x, a.Mtot, a.ci1, a.nci1, a.perm1, a.terms, a.op1, a.grids, a.grid_total,
+                                 a.vstride, a.sbase1, a.slots, a.Vtot);
   }
 }
 
@@ -129,8 +131,10 @@ struct AdjSpreadArgs {
 };
 
 // Workgroups of four wavefronts: the tile spread's own size; the binned order-1 spread runs
-// its cells over four wavefronts instead of kSpreadWaves.  The tile spread's workgroups come
-// first, so they start first.
+// its cells over four wavefronts instead of kSpreadWaves.  The order-1 workgroups come first
+// in the launch, so they start first and run beside the tile spread's (placed after them,
+// the tile spread's first round would fill the compute units and the order-1 work would
+// only start as it drains).
 template <typename T, int MH>
 __global__ __launch_bounds__(64 * kTileWaves) void k_adj_spread2(AdjSpreadArgs<T> a) {
   Blk bk;

@@ -1419,10 +1419,10 @@ static int fused_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fh
   sa.patch = (C *)o2.d_patch;
   sa.gitems = pl->d_gitems;
   sa.ysum = pl->d_ysum;
-  sa.p2 = Part{0, (o2.nwaves2 + kTileWaves - 1) / kTileWaves, pl->ragged ? 1 : R};
-  sa.p1 = Part{sa.p2.nx * sa.p2.ny, (int)o1.sitems.size(), nt1};
-  sa.pe = Part{sa.p1.b0 + sa.p1.nx * sa.p1.ny, ngi, 1};
-  const unsigned nbs = (unsigned)(sa.pe.b0 + sa.pe.nx);
+  sa.p1 = Part{0, (int)o1.sitems.size(), nt1};
+  sa.pe = Part{sa.p1.nx * sa.p1.ny, ngi, 1};
+  sa.p2 = Part{sa.pe.b0 + sa.pe.nx, (o2.nwaves2 + kTileWaves - 1) / kTileWaves, pl->ragged ? 1 : R};
+  const unsigned nbs = (unsigned)(sa.p2.b0 + sa.p2.nx * sa.p2.ny);
   // padded so that at most tile_wg_cu workgroups share a compute unit
   const size_t slds = std::max({(size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T)),
                                 pl->lds_limit / o2.tile_wg_cu,
