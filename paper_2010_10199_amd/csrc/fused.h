@@ -29,6 +29,18 @@ __device__ __forceinline__ bool in_part(int b, const Part &p, Blk &bk) {
   return true;
 }
 
+// The same for a part that starts at a multiple of 8 blocks, its blocks renumbered so that
+// each XCD (block b runs on XCD b mod 8) takes one contiguous range of the part's blocks
+// (as the separate gathers renumber theirs): every part is spread over all XCDs.
+__device__ __forceinline__ bool in_part_xcd(int b, const Part &p, Blk &bk) {
+  int l = b - p.b0;
+  if (l < 0 || l >= p.nx * p.ny) return false;
+  l = xcd_contiguous(l, p.nx * p.ny);
+  bk.y = l / p.nx;
+  bk.x = l - bk.y * p.nx;
+  return true;
+}
+
 template <typename T>
 struct FwdPackArgs {
   const cx_t<T> *fhat;
@@ -79,18 +91,25 @@ struct FwdGatherArgs {
   Part p1, p2;
 };
 
-// The launch's blocks are renumbered XCD-contiguous first (as the separate gathers do), so
-// each part's consecutive items share an XCD's L2.  K1, K2: the orders' gather forms
+// Each part starts at a multiple of 8 blocks and is renumbered XCD-contiguous on its own (as
+// the separate gathers are), so consecutive items share an XCD's L2 and every part runs on all
+// XCDs (renumbering the whole launch at once gave one XCD the order-1 part alone: 52 against
+// 34 µs for the two separate gathers).  K1, K2: the orders' gather forms
 // (GT_GATHER_SORTED, _CELL, _POLY); each instance holds only the two bodies it runs, so it
 // needs no more registers than the larger of them.
 template <typename T, int MH, int K1, int K2>
 __global__ __launch_bounds__(256) void k_fwd_gather2(FwdGatherArgs<T> a) {
   static_assert(K1 != GT_GATHER_POLY && (K2 != GT_GATHER_POLY || std::is_same<T, float>::value), "no such form");
-  const int b = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+  const int b = (int)blockIdx.x;
   Blk bk;
-  // (order 2 tested first: with the polynomial form first the compiler keeps the order-1
-  // cell gather's grid reads as scalar loads, 22 registers against 53 the other way round)
-  if (in_part(b, a.p2, bk)) {
+  if (in_part_xcd(b, a.p1, bk)) {
+    if constexpr (K1 == GT_GATHER_SORTED)
+      gather_sorted_body<T, 1, MH>(bk, a.x, a.Mtot, a.gi1, a.perm1, a.terms, a.op1, a.grids, a.grid_total, a.vstride,
+                                   a.sbase1, a.slots, a.Vtot);
+    else
+      gather_cell_body<T, 1, MH>(bk, a.x, a.Mtot, a.ci1, a.nci1, a.perm1, a.terms, a.op1, a.grids, a.grid_total,
+                                 a.vstride, a.sbase1, a.slots, a.Vtot);
+  } else if (in_part_xcd(b, a.p2, bk)) {
     if constexpr (K2 == GT_GATHER_POLY)
       gather_poly2_body<T>(bk, a.xs2, a.ci2, a.nci2, a.perm2, a.op2, a.kpoly, a.vstride, a.sbase2, a.slots, a.Vtot);
     else if constexpr (K2 == GT_GATHER_SORTED)
@@ -99,13 +118,6 @@ __global__ __launch_bounds__(256) void k_fwd_gather2(FwdGatherArgs<T> a) {
     else
       gather_cell_body<T, 2, MH>(bk, a.x, a.Mtot, a.ci2, a.nci2, a.perm2, a.terms, a.op2, a.grids, a.grid_total,
                                  a.vstride, a.sbase2, a.slots, a.Vtot);
-  } else if (in_part(b, a.p1, bk)) {
-    if constexpr (K1 == GT_GATHER_SORTED)
-      gather_sorted_body<T, 1, MH>(bk, a.x, a.Mtot, a.gi1, a.perm1, a.terms, a.op1, a.grids, a.grid_total, a.vstride,
-                                   a.sbase1, a.slots, a.Vtot);
-    else
-      gather_cell_body<T, 1, MH>(bk, a.x, a.Mtot, a.ci1, a.nci1, a.perm1, a.terms, a.op1, a.grids, a.grid_total,
-                                 a.vstride, a.sbase1, a.slots, a.Vtot);
   }
 }
 

@@ -312,7 +312,14 @@ typedef float v16f_t __attribute__((ext_vector_type(16)));
 // The statement takes two values as (unused) inputs and so follows their computation: a
 // second group takes the partial sums of the first, so each group is consumed as soon as it
 // arrives and two groups are never live at once.
-__device__ __forceinline__ void sload_rows4(const void *p, v16f_t (&r)[4], float dep0, float dep1) {
+// The address is the same in every lane; it is moved into scalar registers explicitly, since
+// the compiler may otherwise hand the "s" operand a vector register pair when it cannot tell
+// that the value is uniform.
+__device__ __forceinline__ void sload_rows4(const void *pv, v16f_t (&r)[4], float dep0, float dep1) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(pv);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(a & 0xffffffffull));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(a >> 32));
+  const void *p = reinterpret_cast<const void *>(((unsigned long long)hi << 32) | lo);
   asm volatile(
       "s_load_dwordx16 %0, %4, 0x0\n\t"
       "s_load_dwordx16 %1, %4, 0x40\n\t"

@@ -1345,7 +1345,7 @@ static int fused_forward(gt_plan *pl, const void *fhat, const T *colscale, void 
       nci = c1 - c0;
       p = Part{b0, (nci + 3) / 4, pl->ragged ? 1 : R};
     }
-    b0 += p.nx * p.ny;
+    b0 += (p.nx * p.ny + 7) / 8 * 8;   // the next part starts at a multiple of 8 blocks
     return p;
   };
   ga.p1 = gpart(o1, nt1, ga.gi1, ga.ci1, ga.nci1);
