@@ -843,7 +843,7 @@ def run_autograd(steps: int = 10):
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
     from paper_2010_10199_amd.autograd import GroupedTrafoFixedNodes
-    fixed = GroupedTrafoFixedNodes(x, d, ds, N, offsets=offs)
+    fixed = GroupedTrafoFixedNodes(x, d, ds, N, offsets=offs, tune=True)   # tuned off the clock
     fc = fh.clone().requires_grad_(True)
 
     def step_fixed():
@@ -861,7 +861,7 @@ def run_autograd(steps: int = 10):
     fixed.close()
     # (d) nodes moving every step on one plan: GroupedTrafoMovingNodes (device re-binning)
     from paper_2010_10199_amd.autograd import GroupedTrafoMovingNodes
-    moving = GroupedTrafoMovingNodes(x, d, ds, N, offsets=offs)
+    moving = GroupedTrafoMovingNodes(x, d, ds, N, offsets=offs, tune=True)   # tuned off the clock
     xm, fm = x.clone().requires_grad_(True), fh.clone().requires_grad_(True)
 
     def step_moving():
@@ -879,9 +879,11 @@ def run_autograd(steps: int = 10):
         step_moving()
     torch.cuda.synchronize()
     t_moving = (time.perf_counter() - t0) / steps
+    tunings = {"fixed_nodes": fixed.tuning, "moving_nodes": moving.tuning}
     moving.close()
     p, keep = lib.make_problem(d, ds, N, M=0, R=B, dtype=lib.GT_C64, offsets=offs)
     plan = lib.Plan(p, x, keepalive=keep)
+    plan.tune(torch.cuda.current_stream().cuda_stream)   # (the same signature: the cached choice)
     f = torch.empty(Mt, dtype=torch.complex64, device="cuda")
     g = torch.empty(B * nc, dtype=torch.complex64, device="cuda")
     gx = torch.empty((Mt, d), dtype=torch.float32, device="cuda")
@@ -909,7 +911,9 @@ def run_autograd(steps: int = 10):
             "fixed_nodes_node_terms_per_s": 2 * nt / t_fixed,
             "plan_passes_ms": {k: t * 1e3 for k, t in times.items()},
             "plan_passes_node_terms_per_s": {k: nt / t for k, t in times.items()},
-            "note": "autograd steps build a plan (node sort) per forward and count three passes (forward, "
+            "tunings": tunings,
+            "note": "the fixed-nodes and moving-nodes objects and the passes' plan are tuned off the clock; "
+                    "autograd steps build a plan (node sort) per forward and count three passes (forward, "
                     "adjoint, node gradient); moving-nodes steps move one plan's nodes (device re-binning) "
                     "before the same three passes, and moving_over_fixed_plan_passes compares them with the "
                     "three passes on a plan whose nodes stay; fixed-nodes steps reuse one plan and count two "

@@ -116,10 +116,12 @@ class GroupedTrafoMovingNodes:
     backward must run before the next call (the plan holds one node set); a backward that
     finds the nodes moved since its forward raises.
 
-    x0: (Mtot, d) real CUDA tensor; calls take (fhat, x) as grouped_trafo does."""
+    x0: (Mtot, d) real CUDA tensor; calls take (fhat, x) as grouped_trafo does.  tune=True times
+    the plan's launch forms on the first nodes (gt_plan_tune, on the current stream) and keeps
+    them for the later nodes."""
 
     def __init__(self, x0: torch.Tensor, d: int, ds: int, N: Sequence[int], R: int = 1,
-                 offsets: Optional[Sequence[int]] = None, m: int = 0, sigma: float = 0.0):
+                 offsets: Optional[Sequence[int]] = None, m: int = 0, sigma: float = 0.0, tune: bool = False):
         if not x0.is_cuda:
             raise RuntimeError("grouped transform runs on the GPU only")
         code = lib.GT_C64 if x0.dtype == torch.float32 else lib.GT_C128 if x0.dtype == torch.float64 else None
@@ -134,6 +136,7 @@ class GroupedTrafoMovingNodes:
         prob, keep = lib.make_problem(d, ds, N, M=Mx if offsets is None else 0, R=self.R, dtype=code, m=m,
                                       sigma=sigma, offsets=self.offsets)
         self.plan = lib.Plan(prob, x_c, keepalive=keep)
+        self.tuning = self.plan.tune(torch.cuda.current_stream().cuda_stream) if tune else None
         self.nout = self.R * Mx if offsets is None else Mx
         self.cdtype = torch.complex64 if code == lib.GT_C64 else torch.complex128
         self.version = 0
@@ -183,10 +186,11 @@ class GroupedTrafoFixedNodes:
     when the object is built, so later changes to x are not seen (build a new object).
 
     x: (Mtot, d) real CUDA tensor; calls take fhat (R, |I|) or (|I|,) complex of the matching
-    precision and return f as grouped_trafo does."""
+    precision and return f as grouped_trafo does.  tune=True times the plan's launch forms
+    once (gt_plan_tune, on the current stream)."""
 
     def __init__(self, x: torch.Tensor, d: int, ds: int, N: Sequence[int], R: int = 1,
-                 offsets: Optional[Sequence[int]] = None, m: int = 0, sigma: float = 0.0):
+                 offsets: Optional[Sequence[int]] = None, m: int = 0, sigma: float = 0.0, tune: bool = False):
         if not x.is_cuda:
             raise RuntimeError("grouped transform runs on the GPU only")
         code = lib.GT_C64 if x.dtype == torch.float32 else lib.GT_C128 if x.dtype == torch.float64 else None
@@ -199,6 +203,7 @@ class GroupedTrafoFixedNodes:
         prob, keep = lib.make_problem(d, ds, N, M=Mx if offsets is None else 0, R=self.R, dtype=code, m=m,
                                       sigma=sigma, offsets=self.offsets)
         self.plan = lib.Plan(prob, x_c, keepalive=keep)
+        self.tuning = self.plan.tune(torch.cuda.current_stream().cuda_stream) if tune else None
         self.nout = self.R * Mx if offsets is None else Mx
         self.cdtype = torch.complex64 if code == lib.GT_C64 else torch.complex128
 

@@ -200,3 +200,35 @@ def test_moving_nodes_match_fresh_plans_and_oracle():
     with pytest.raises(RuntimeError):
         (torch.conj(vt) * fa).real.sum().backward()
     mod.close()
+
+
+def test_tuned_fixed_and_moving_nodes_vs_oracle():
+    """tune=True: the objects' plans take measured launch forms (the shared launches of orders
+    1 and 2 among them); the gradients still meet the FP32 bar against the oracle, for fixed
+    nodes and for nodes moved twice on the tuned plan."""
+    import torch
+    from paper_2010_10199_amd.autograd import GroupedTrafoFixedNodes, GroupedTrafoMovingNodes
+    d, ds, N = 8, 2, (32, 10)
+    iset, offs, x, fh, v = _ragged(54, 6, 300, 2500, d, ds, N, "f32")
+    vt = to_dev(v)
+    fixed = GroupedTrafoFixedNodes(to_dev(x), d, ds, N, offsets=offs, tune=True)
+    say(f"[tuned fixed] {fixed.tuning.get('fused')}")
+    ft = to_dev(fh).requires_grad_(True)
+    (torch.conj(vt) * fixed(ft)).real.sum().backward()
+    rfh, _ = _oracle_grads(iset, offs, x, fh, v)
+    e = rel(ft.grad.cpu().numpy(), rfh)
+    say(f"[tuned fixed] grad fhat vs oracle {e:.3e}")
+    assert e <= 1e-5
+    fixed.close()
+    moving = GroupedTrafoMovingNodes(to_dev(x), d, ds, N, offsets=offs, tune=True)
+    for it in range(2):
+        xi = W.uniform_nodes(W.rng(540 + it, W.P_NODES), x.shape[0], d, "f32")
+        xt = to_dev(xi).requires_grad_(True)
+        ft = to_dev(fh).requires_grad_(True)
+        (torch.conj(vt) * moving(ft, xt)).real.sum().backward()
+        torch.cuda.synchronize()
+        rfh, rgx = _oracle_grads(iset, offs, xi, fh, v)
+        e1, e2 = rel(ft.grad.cpu().numpy(), rfh), rel(xt.grad.cpu().numpy(), rgx)
+        say(f"[tuned moving] step {it}: grad fhat {e1:.2e} grad x {e2:.2e}")
+        assert e1 <= 1e-5 and e2 <= 1e-5
+    moving.close()
