@@ -43,6 +43,11 @@ constexpr int kPolyRows = 3;       // cell rows per workgroup of k_pack_poly2
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
 constexpr int tile_side(int m) { return 17 - 2 * m; }
+// LDS of one wavefront of the order-2 tile spread (reals of `rsize` bytes): the window rows of
+// a batch along both axes (kTileBatch x kTileRow each) and the batch's samples.
+constexpr size_t tile_lds_wave(size_t rsize) {
+  return ((size_t)2 * kTileBatch * kTileRow + (size_t)2 * kTileBatch) * rsize;
+}
 constexpr int kPackBS = 512;   // threads of the pack and adjoint-DFT workgroups
 constexpr int kVecBS = 256;
 

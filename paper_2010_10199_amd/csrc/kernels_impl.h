@@ -1424,7 +1424,7 @@ static int fused_adjoint(gt_plan *pl, const void *y, const T *colscale, void *fh
   sa.p2 = Part{sa.pe.b0 + sa.pe.nx, (o2.nwaves2 + kTileWaves - 1) / kTileWaves, pl->ragged ? 1 : R};
   const unsigned nbs = (unsigned)(sa.p2.b0 + sa.p2.nx * sa.p2.ny);
   // padded so that at most tile_wg_cu workgroups share a compute unit
-  const size_t slds = std::max({(size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T)),
+  const size_t slds = std::max({kTileWaves * tile_lds_wave(sizeof(T)),
                                 pl->lds_limit / o2.tile_wg_cu,
                                 (size_t)sa.sa1.copies * o1.gsize * sizeof(double2)});
   prof_begin(s, "spread_12");
@@ -1676,7 +1676,7 @@ static int adjoint_core(gt_plan *pl, const void *y, const T *colscale, void *fha
 #define GT_LAUNCH_TILE2(MH)                                                                                       \
   {                                                                                                               \
     /* padded so that at most tile_wg_cu workgroups share a compute unit */                                   \
-    const size_t lds2 = std::max<size_t>((size_t)kTileWaves * kTileBatch * kTileRow * (sizeof(C) + sizeof(T)),    \
+    const size_t lds2 = std::max<size_t>(kTileWaves * tile_lds_wave(sizeof(T)),    \
                                          pl->lds_limit / o.tile_wg_cu);                                           \
     if (int rc = set_lds(k_spread_tile2<T, MH>, lds2)) return rc;                                                 \
     hipLaunchKernelGGL((k_spread_tile2<T, MH>), dim3((unsigned)((o.nwaves2 + kTileWaves - 1) / kTileWaves),     \

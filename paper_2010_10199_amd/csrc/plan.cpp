@@ -427,7 +427,7 @@ static int setup_tile_spread(gt_plan *pl, const std::vector<int64_t> &cs) {
   const int64_t total = (int64_t)nt * pl->Mtot;
   const int reff = pl->ragged ? 1 : pl->R;
   // (the LDS of a compute unit equals the per-workgroup limit on this GPU)
-  const size_t lds2 = (size_t)kTileWaves * kTileBatch * kTileRow * 3 * pl->rsize;   // complex + real rows
+  const size_t lds2 = kTileWaves * tile_lds_wave(pl->rsize);
   o.tile_wg_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(o.waves_cu / kTileWaves, pl->lds_limit / lds2));
   const int64_t want_waves = std::max<int64_t>(1, (int64_t)pl->num_cu * kTileWaves * o.tile_wg_cu / reff);
   std::vector<int32_t> waves;

@@ -371,11 +371,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 //
 // Each wavefront owns a run of sorted positions of one (term, dataset) from the plan's work
 // list and walks it in batches of 32: lanes 0..31 evaluate the window along axis 0 of one
-// node each (times the sample), lanes 32..63 along axis 1, and stage the shifted,
-// zero-padded 16-vectors in LDS; 8 MFMA steps read them back as operands (rows past the end
-// of a short batch carry zero samples).  The nodes of a batch usually share one tile; when
-// a tile ends inside the batch, the batch is run once per tile with the other tiles'
-// samples zeroed.  At each tile change the wavefront stores its finished patch, with plain
+// node each, lanes 32..63 along axis 1, and both halves stage their shifted, zero-padded
+// real 16-vectors in LDS with the same instructions; the batch's samples go to LDS beside
+// them.  8 MFMA steps read the rows back as operands and form A = y psi(axis 0) as they
+// read it (the same single product as staging it, so the patch does not change), samples of
+// nodes outside the batch or the tile being zero.  The nodes of a batch usually share one
+// tile; when a tile ends inside the batch, the batch is run once per tile with the other
+// tiles' samples zeroed.  At each tile change the wavefront stores its finished patch, with plain
 // stores, in its next patch slot (slots are numbered per wavefront in tile order); the
 // fold kernel adds the patches into the grids in a fixed order.  Nothing is shared between
 // wavefronts, so there are no atomics and no workgroup barriers.
@@ -399,6 +401,54 @@ struct Tile2Args {
   int32_t ragged;          // datasets own their samples: r = dataset, one set of slots
 };
 
+// floor(f / TS) for 0 <= f < 2^15 + 3 (every grid index: n <= 8 x 4096 + 2) as
+// floor(f K / 2^S), K = ceil(2^S / TS), with the full-rate 24-bit multiply: S is the largest
+// shift with f K < 2^32 and f (K TS - 2^S) < 2^S over that range (then the product's excess
+// over f / TS stays below 1 / TS, so the floor is exact).
+constexpr unsigned kCellMax = (1u << 15) + 3;
+constexpr int div_shift(int ts) {
+  for (int S = 23; S >= 8; --S) {
+    const unsigned long long K = ((1ull << S) + ts - 1) / ts, e = K * ts - (1ull << S);
+    if (K * kCellMax < (1ull << 32) && e * kCellMax < (1ull << S) && K < (1ull << 24)) return S;
+  }
+  return -1;
+}
+template <int TS>
+__device__ __forceinline__ int div_tile(int f) {
+  if constexpr (TS == 1) {
+    return f;
+  } else {
+    constexpr int S = div_shift(TS);
+    static_assert(S > 0, "no exact 24-bit division for this tile side");
+    constexpr unsigned K = (unsigned)(((1ull << S) + TS - 1) / TS);
+    return (int)(__umul24((unsigned)f, K) >> S);
+  }
+}
+
+// Window values as window_values computes them, with the leading coefficient of each part in
+// a vector register (lead[2j]: even part of point j, lead[2j + 1]: odd part), so the first
+// step of each Horner chain reads one scalar operand instead of two (no register move).
+template <typename T, int MH>
+__device__ __forceinline__ void window_values_lead(T z, const T *cf, const T *lead, T (&psi)[2 * MH]) {
+  constexpr int D = Deg<T>::value;
+  constexpr int DE = D - (D & 1), DO = D - 1 + (D & 1);
+  static_assert(DE >= 2 && DO >= 3, "two steps per part at least");
+  const T z2 = z * z;
+#pragma unroll
+  for (int j = 0; j < MH; ++j) {
+    const T *c = cf + j * (D + 1);
+    T e = fma(lead[2 * j], z2, c[DE - 2]);
+#pragma unroll
+    for (int q = DE - 4; q >= 0; q -= 2) e = fma(e, z2, c[q]);
+    T o = fma(lead[2 * j + 1], z2, c[DO - 2]);
+#pragma unroll
+    for (int q = DO - 4; q >= 1; q -= 2) o = fma(o, z2, c[q]);
+    o *= z;
+    psi[j] = e + o;
+    psi[2 * MH - 1 - j] = e - o;
+  }
+}
+
 template <typename T, int MH>
 __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restrict__ xs,
                                                   const int32_t *__restrict__ perm, const OrderParams<T> &op,
@@ -414,8 +464,10 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
   const int l = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
   const int h = l >> 5, j = l & 31, i16 = l & 15, kk = l >> 4;
-  C *SAw = reinterpret_cast<C *>(smem_raw) + (size_t)wv * UB * SR;                                    // UB x SR
-  T *SBw = reinterpret_cast<T *>(smem_raw + (size_t)kTileWaves * UB * SR * sizeof(C)) + (size_t)wv * UB * SR;
+  T *SAw = reinterpret_cast<T *>(smem_raw + (size_t)wv * tile_lds_wave(sizeof(T)));   // UB x SR, axis 0
+  T *SBw = SAw + UB * SR;                                                               // UB x SR, axis 1
+  C *Yw = reinterpret_cast<C *>(SBw + UB * SR);                                         // UB samples
+  T *const myrow = (h ? SBw : SAw) + j * SR;
   const int w = bk.x * kTileWaves + wv;
   if (w >= ta.nwaves) return;   // whole wavefront; the kernel has no workgroup barrier
   const int32_t qbeg = ta.waves[4 * w], qend = ta.waves[4 * w + 1];
@@ -430,6 +482,18 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
   T cf[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) cf[i] = wave_uniform(op.poly[i]);
+  constexpr bool kLead = std::is_same<T, float>::value;   // (FP64 keeps its registers)
+  T lead[2 * MH];
+#pragma unroll
+  for (int i = 0; i < MH; ++i) {
+    constexpr int D = Deg<T>::value;
+    lead[2 * i] = cf[i * (D + 1) + D - (D & 1)];
+    lead[2 * i + 1] = cf[i * (D + 1) + D - 1 + (D & 1)];
+    if constexpr (kLead) {   // held in vector registers from here on
+      asm volatile("" : "+v"(lead[2 * i]));
+      asm volatile("" : "+v"(lead[2 * i + 1]));
+    }
+  }
 
   // Loads are issued unconditionally (positions past the wavefront's range are clamped to
   // its last node), so the wait counts stay exact across the unrolled pipeline.
@@ -455,14 +519,28 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
   };
   auto process = [&](const TileStage<T> &st, int k) {
     const bool valid = qbeg + k * UB + j < qend;
-    int f0, f1;
-    const T r0 = frac_offset<T>(st.x.x, n, f0), r1 = frac_offset<T>(st.x.y, n, f1);
-    const T z = (h ? r1 : r0) * (T)2 - (T)1;
+    // this lane's axis: cell and offset; the other axis: cell only
+    int fh, fo;
+    const T z = frac_offset<T>(h ? st.x.y : st.x.x, n, fh) * (T)2 - (T)1;
+    (void)frac_offset<T>(h ? st.x.x : st.x.y, n, fo);
     T psi[W];
-    window_values<T, MH>(z, cf, psi);
-    const int ty = f0 / TS, tx = f1 / TS;
-    const int tile = valid ? ty * ntile + tx : 0x7fffffff;
-    const int s = h ? f1 - tx * TS : f0 - ty * TS;
+    if constexpr (kLead)
+      window_values_lead<T, MH>(z, cf, lead, psi);
+    else
+      window_values<T, MH>(z, cf, psi);
+    const int ty = div_tile<TS>(h ? fo : fh), tx = div_tile<TS>(h ? fh : fo);
+    const int tile = valid ? (int)__umul24((unsigned)ty, (unsigned)ntile) + tx : 0x7fffffff;
+    const int s = fh - __mul24(h ? tx : ty, TS);
+    // the row: zeros where a window at some offset s in [0, TS) may not reach ([0, 16 - W)
+    // and [W, 16)), then the window values at [s, s + W), over them (a wavefront's LDS
+    // writes take effect in order)
+#pragma unroll
+    for (int q = 0; q < 16 - W; ++q) {
+      myrow[q] = (T)0;
+      myrow[W + q] = (T)0;
+    }
+#pragma unroll
+    for (int a = 0; a < W; ++a) myrow[s + a] = psi[a];
     unsigned long long pending = __ballot(valid);
     while (pending) {
       const int t = __builtin_amdgcn_readlane(tile, __ffsll((long long)pending) - 1);
@@ -471,32 +549,20 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
         if (dirty) store_patch();
         cur_tile = t;
       }
-      if (h == 0) {
-        const T yr = in ? st.y.x : (T)0, yi = in ? st.y.y : (T)0;
-        C *row = SAw + j * SR;
-#pragma unroll
-        for (int a = 0; a < W; ++a) row[s + a] = cmake<T>(psi[a] * yr, psi[a] * yi);
-#pragma unroll
-        for (int q = 0; q < 16 - W; ++q) row[(s + W + q) & 15] = cmake<T>((T)0, (T)0);
-      } else {
-        T *row = SBw + j * SR;
-#pragma unroll
-        for (int a = 0; a < W; ++a) row[s + a] = psi[a];
-#pragma unroll
-        for (int q = 0; q < 16 - W; ++q) row[(s + W + q) & 15] = (T)0;
-      }
+      Yw[j] = in ? st.y : cmake<T>((T)0, (T)0);   // (both halves write the same value)
       wave_lds_sync();
-      C av[UB / 4];
-      T bv[UB / 4];
+      T av[UB / 4], bv[UB / 4];
+      C yv[UB / 4];
 #pragma unroll
       for (int q = 0; q < UB / 4; ++q) {
         av[q] = SAw[(4 * q + kk) * SR + i16];
         bv[q] = SBw[(4 * q + kk) * SR + i16];
+        yv[q] = Yw[4 * q + kk];
       }
 #pragma unroll
       for (int q = 0; q < UB / 4; ++q) {
-        are = MF::run(av[q].x, bv[q], are);
-        aim = MF::run(av[q].y, bv[q], aim);
+        are = MF::run(av[q] * yv[q].x, bv[q], are);
+        aim = MF::run(av[q] * yv[q].y, bv[q], aim);
       }
       wave_lds_sync();
       dirty = true;
