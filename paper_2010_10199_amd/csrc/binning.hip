@@ -93,54 +93,70 @@ __global__ void k_sorted_coords(const T *__restrict__ xT, int64_t Mtot, const De
 
 // Order-2 tile spread work list after a re-binning (gt_plan_update_nodes).  The wavefronts
 // keep their runs [qa, qb) of sorted positions, which depend only on the node counts per
-// (term, dataset); what moves with the nodes is which tiles a run meets.  One workgroup:
-//   1. per wavefront the non-empty tiles its run meets (the tiles ending after qa and
-//      starting before qb), counted into segcnt;
-//   2. an exclusive scan of the counts gives each wavefront's first patch segment
-//      (waves[4w + 2]); the total closes tileseg;
-//   3. each wavefront numbers its tiles' segments again and enters, for the tiles whose first
-//      position lies in its run (it is the first wavefront to meet them), the tile's first
-//      segment into tileseg;
-//   4. tiles without nodes (still -1) take the first segment of the next tile that has nodes
-//      (over all terms and datasets in order, the total after the last): a backward fill in
-//      1024 chunks with the carry between chunks.
+// (term, dataset); what moves with the nodes is which tiles a run meets.  Four launches:
+//   1. k_relist_count, a thread per wavefront: the non-empty tiles its run meets (the tiles
+//      ending after qa and starting before qb), counted into segcnt; every tileseg entry -1;
+//   2. k_relist_scan, one workgroup: an exclusive scan of the counts gives each wavefront's
+//      first patch segment (waves[4w + 2]); the total closes tileseg;
+//   3. k_relist_first, a thread per wavefront: it numbers its tiles' segments again and
+//      enters, for the tiles whose first position lies in its run (it is the first wavefront
+//      to meet them), the tile's first segment into tileseg;
+//   4. k_relist_fill, one workgroup: tiles without nodes (still -1) take the first segment of
+//      the next tile that has nodes (over all terms and datasets in order, the total after
+//      the last): a backward fill in 1024 chunks, the carry into each chunk from a suffix scan
+//      of the chunks' first set entries.
 // waves: nwaves x {qa, qb, first segment, dataset}; cstart absolute positions per key (term
 // tl's keys start at (tl B + b) nkey; tile t of a (term, dataset) spans keys t TT ..).
-__global__ __launch_bounds__(1024) void k_tile_relist(int32_t *__restrict__ waves, int nwaves,
-                                                      const int64_t *__restrict__ cstart, int64_t Mtot, int B,
-                                                      int64_t nkey, int ntiles, int TT, int64_t ntiles_all,
-                                                      int32_t *__restrict__ segcnt, int32_t *__restrict__ tileseg) {
-  __shared__ int32_t part[1024];
-  const int tid = threadIdx.x;
-  auto tiles_of = [&](int w, int64_t &key0, int &t0, int64_t &qa, int64_t &qb) {
-    qa = waves[4 * w];
-    qb = waves[4 * w + 1];
-    const int b = waves[4 * w + 3];
-    const int64_t tl = qa / Mtot;
-    key0 = (tl * B + b) * nkey;
-    int lo = 0, hi = ntiles;   // first tile whose end lies after qa
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (cstart[key0 + (int64_t)(mid + 1) * TT] <= qa) lo = mid + 1; else hi = mid;
-    }
-    t0 = lo;
-  };
-  for (int64_t i = tid; i < ntiles_all; i += 1024) tileseg[i] = -1;
-  for (int w = tid; w < nwaves; w += 1024) {
-    int64_t key0, qa, qb;
-    int t0;
-    tiles_of(w, key0, t0, qa, qb);
-    int c = 0;
-    for (int t = t0; t < ntiles && cstart[key0 + (int64_t)t * TT] < qb; ++t)
-      if (cstart[key0 + (int64_t)(t + 1) * TT] > cstart[key0 + (int64_t)t * TT]) ++c;
-    segcnt[w] = c;
+struct RelistArgs {
+  int32_t *waves;
+  int nwaves;
+  const int64_t *cstart;
+  int64_t Mtot;
+  int B;
+  int64_t nkey;
+  int ntiles, TT;
+  int64_t ntiles_all;
+  int32_t *segcnt, *tileseg;
+};
+
+// Wavefront w's run [qa, qb), its (term, dataset)'s first key and the first tile ending after qa.
+__device__ __forceinline__ void relist_tiles_of(const RelistArgs &a, int w, int64_t &key0, int &t0, int64_t &qa,
+                                                int64_t &qb) {
+  qa = a.waves[4 * w];
+  qb = a.waves[4 * w + 1];
+  const int b = a.waves[4 * w + 3];
+  const int64_t tl = qa / a.Mtot;
+  key0 = (tl * a.B + b) * a.nkey;
+  int lo = 0, hi = a.ntiles;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.cstart[key0 + (int64_t)(mid + 1) * a.TT] <= qa) lo = mid + 1; else hi = mid;
   }
-  __syncthreads();
-  // 2. exclusive scan: chunk sums, scan of the 1024 sums in LDS, then the chunks
+  t0 = lo;
+}
+
+__global__ __launch_bounds__(256) void k_relist_count(RelistArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < a.ntiles_all) a.tileseg[i] = -1;
+  if (i >= a.nwaves) return;
+  const int w = (int)i;
+  int64_t key0, qa, qb;
+  int t0;
+  relist_tiles_of(a, w, key0, t0, qa, qb);
+  int c = 0;
+  for (int t = t0; t < a.ntiles && a.cstart[key0 + (int64_t)t * a.TT] < qb; ++t)
+    if (a.cstart[key0 + (int64_t)(t + 1) * a.TT] > a.cstart[key0 + (int64_t)t * a.TT]) ++c;
+  a.segcnt[w] = c;
+}
+
+__global__ __launch_bounds__(1024) void k_relist_scan(RelistArgs a) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x, nwaves = a.nwaves;
+  // chunk sums, a scan of the 1024 sums in LDS, then the chunks
   const int per = (nwaves + 1023) / 1024;
   const int w0 = tid * per, w1 = min(nwaves, w0 + per);
   int32_t sum = 0;
-  for (int w = w0; w < w1; ++w) sum += segcnt[w];
+  for (int w = w0; w < w1; ++w) sum += a.segcnt[w];
   part[tid] = sum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -151,29 +167,35 @@ __global__ __launch_bounds__(1024) void k_tile_relist(int32_t *__restrict__ wave
   }
   int32_t run = part[tid] - sum;   // exclusive prefix of this chunk
   for (int w = w0; w < w1; ++w) {
-    waves[4 * w + 2] = run;
-    run += segcnt[w];
+    a.waves[4 * w + 2] = run;
+    run += a.segcnt[w];
   }
-  const int32_t total = part[1023];
-  __syncthreads();
-  // 3. first segment of each tile, entered by the first wavefront meeting it
-  for (int w = tid; w < nwaves; w += 1024) {
-    int64_t key0, qa, qb;
-    int t0;
-    tiles_of(w, key0, t0, qa, qb);
-    int32_t seg = waves[4 * w + 2];
-    const int64_t tb0 = key0 / TT;   // (tl B + b) ntiles
-    for (int t = t0; t < ntiles && cstart[key0 + (int64_t)t * TT] < qb; ++t) {
-      const int64_t c0 = cstart[key0 + (int64_t)t * TT];
-      if (cstart[key0 + (int64_t)(t + 1) * TT] <= c0) continue;   // no nodes
-      if (c0 >= qa) tileseg[tb0 + t] = seg;
-      ++seg;
-    }
+  if (tid == 1023) a.tileseg[a.ntiles_all] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_relist_first(RelistArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.nwaves) return;
+  const int w = (int)i;
+  int64_t key0, qa, qb;
+  int t0;
+  relist_tiles_of(a, w, key0, t0, qa, qb);
+  int32_t seg = a.waves[4 * w + 2];
+  const int64_t tb0 = key0 / a.TT;   // (tl B + b) ntiles
+  for (int t = t0; t < a.ntiles && a.cstart[key0 + (int64_t)t * a.TT] < qb; ++t) {
+    const int64_t c0 = a.cstart[key0 + (int64_t)t * a.TT];
+    if (a.cstart[key0 + (int64_t)(t + 1) * a.TT] <= c0) continue;   // no nodes
+    if (c0 >= qa) a.tileseg[tb0 + t] = seg;
+    ++seg;
   }
-  __syncthreads();
-  // 4. backward fill: chunk c holds entries [c per2, (c + 1) per2)
-  const int64_t per2 = (ntiles_all + 1023) / 1024;
-  const int64_t a0 = tid * per2, a1 = min(ntiles_all, a0 + per2);
+}
+
+__global__ __launch_bounds__(1024) void k_relist_fill(RelistArgs a) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x;
+  int32_t *tileseg = a.tileseg;
+  const int64_t per2 = (a.ntiles_all + 1023) / 1024;   // chunk tid holds entries [tid per2, (tid + 1) per2)
+  const int64_t a0 = tid * per2, a1 = min(a.ntiles_all, a0 + per2);
   int32_t first = -1;   // first set entry of the chunk
   for (int64_t i = a0; i < a1; ++i)
     if (tileseg[i] >= 0) {
@@ -182,23 +204,22 @@ __global__ __launch_bounds__(1024) void k_tile_relist(int32_t *__restrict__ wave
     }
   part[tid] = first;
   __syncthreads();
-  if (tid == 0) {   // carry: the first set entry to the right of each chunk
-    int32_t next = total;
-    for (int c = 1023; c >= 0; --c) {
-      const int32_t f = part[c];
-      part[c] = next;
-      if (f >= 0) next = f;
-    }
+  // suffix scan with "the left operand if set, else the right one": part[c] becomes the first
+  // set entry among chunks c, c + 1, ..
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t r = tid + off < 1024 ? part[tid + off] : -1;
+    __syncthreads();
+    if (part[tid] < 0) part[tid] = r;
+    __syncthreads();
   }
-  __syncthreads();
-  int32_t next = part[tid];
+  const int32_t total = tileseg[a.ntiles_all];
+  int32_t next = tid + 1 < 1024 && part[tid + 1] >= 0 ? part[tid + 1] : total;   // carry from the right
   for (int64_t i = a1 - 1; i >= a0; --i) {
     if (tileseg[i] < 0)
       tileseg[i] = next;
     else
       next = tileseg[i];
   }
-  if (tid == 0) tileseg[ntiles_all] = total;
 }
 
 }  // namespace
@@ -207,12 +228,25 @@ int launch_tile_relist(gt_plan *pl, hipStream_t s) {
   OrderHost &o = pl->ord[2];
   if (pl->ds < 2 || o.term_end == o.term_begin || o.nwaves2 == 0) return GT_OK;
   const int B = pl->ragged ? pl->R : 1;
-  const int64_t ntiles_all = (int64_t)(o.term_end - o.term_begin) * B * o.ntile * o.ntile;
-  hipLaunchKernelGGL(k_tile_relist, dim3(1), dim3(1024), 0, s, o.d_waves2, o.nwaves2, (const int64_t *)o.d_cstart,
-                     pl->Mtot, B, o.nkey, o.ntile * o.ntile, o.ts * o.ts, ntiles_all, pl->rebin.segcnt,
-                     o.d_tileseg);
+  RelistArgs a;
+  a.waves = o.d_waves2;
+  a.nwaves = o.nwaves2;
+  a.cstart = (const int64_t *)o.d_cstart;
+  a.Mtot = pl->Mtot;
+  a.B = B;
+  a.nkey = o.nkey;
+  a.ntiles = o.ntile * o.ntile;
+  a.TT = o.ts * o.ts;
+  a.ntiles_all = (int64_t)(o.term_end - o.term_begin) * B * o.ntile * o.ntile;
+  a.segcnt = pl->rebin.segcnt;
+  a.tileseg = o.d_tileseg;
+  const int64_t n1 = std::max<int64_t>(a.nwaves, a.ntiles_all);
+  hipLaunchKernelGGL(k_relist_count, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_relist_scan, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_relist_first, dim3((unsigned)((a.nwaves + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_relist_fill, dim3(1), dim3(1024), 0, s, a);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? GT_OK : hip_fail(e, "k_tile_relist");
+  return e == hipSuccess ? GT_OK : hip_fail(e, "tile relist");
 }
 
 // Key batches of one order: terms in batches bounded to ~2^26 (term, node) pairs.
