@@ -47,7 +47,7 @@ def direct_flops_per_node_term(order: int, N: int, R: int) -> int:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h", "direct.h"):
+    for f in ("kernels_impl.h", "gt_internal.h", "gather.h", "spread.h", "direct.h", "fused.h"):
         with open(os.path.join(ROOT, "paper_2010_10199_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
