@@ -39,6 +39,12 @@ CASES = [
     # column sums of an order-2 term too large for the adjoint DFT's LDS (n = 64, 13 tiles per
     # row): the separate tile-sum fold kernel
     ("unstaged-fold-2d", 2, 2, (4, 32), 800, 1, 6, 2.0),
+    # every window width of the order-2 tile spread (tile sides 13, 9, 7, 3 here; 11, 5 and 1
+    # in the m = 3, 6 and 8 cases), several tiles per row of the 28-point grid
+    ("2d-m2", 3, 2, (16, 14), 3000, 1, 2, 2.0),
+    ("2d-m4", 3, 2, (16, 14), 3000, 2, 4, 2.0),
+    ("2d-m5", 3, 2, (16, 14), 3000, 1, 5, 2.0),
+    ("2d-m7", 3, 2, (16, 14), 3000, 1, 7, 2.0),
 ]
 
 # forward gather path per order of the cell cases: FP32 takes the polynomial gather for
