@@ -325,10 +325,13 @@ def test_update_nodes_matches_oracle(case):
         fresh = lib.Plan(fresh_p, to_dev(xx), keepalive=fresh_k)
         _, fresh_a = run(fresh)
         fresh.close()
-        # the order-2 coefficients (the tile spread's; orders 1 and 3 accumulate with LDS atomics)
-        sel = np.concatenate([np.arange(iset.offsets[i], iset.offsets[i + 1])
-                              for i, u in enumerate(iset.terms) if len(u) == 2])
-        assert np.array_equal(got_a[:, sel], fresh_a[:, sel]), "device-built tile list differs from the host-built one"
+        # the coefficients of orders 1 and 2 (the order-1 spread sums its grid copies in a fixed
+        # order, the tile spread its patches; order 3 adds into one grid with LDS atomics)
+        for order in (1, 2):
+            sel = np.concatenate([np.arange(iset.offsets[i], iset.offsets[i + 1])
+                                  for i, u in enumerate(iset.terms) if len(u) == order] or [np.zeros(0, int)])
+            assert np.array_equal(got_a[:, sel], fresh_a[:, sel]), \
+                f"order {order}: the moved plan differs from a fresh plan for the same nodes"
     s = torch.cuda.Stream()
     plan.tune(s.cuda_stream)
     torch.cuda.synchronize()
