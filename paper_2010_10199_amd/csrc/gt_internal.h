@@ -43,11 +43,6 @@ constexpr int kPolyRows = 3;       // cell rows per workgroup of k_pack_poly2
 // Order-2 spread tiles: TS x TS grid cells whose nodes' windows all fall into one 16 x 16
 // patch (TS + 2m - 1 = 16).
 constexpr int tile_side(int m) { return 17 - 2 * m; }
-// LDS of one wavefront of the order-2 tile spread (reals of `rsize` bytes): the window rows of
-// a batch along both axes (kTileBatch x kTileRow each) and the batch's samples.
-constexpr size_t tile_lds_wave(size_t rsize) {
-  return ((size_t)2 * kTileBatch * kTileRow + (size_t)2 * kTileBatch) * rsize;
-}
 constexpr int kPackBS = 512;   // threads of the pack and adjoint-DFT workgroups
 constexpr int kVecBS = 256;
 
@@ -60,6 +55,16 @@ struct Blk {
 template <typename T> struct Deg;                   // window polynomial degree per precision
 template <> struct Deg<float> { static constexpr int value = 7; };
 template <> struct Deg<double> { static constexpr int value = 14; };
+
+// LDS of one wavefront of the order-2 tile spread (reals of `rsize` bytes): the window rows of
+// a batch along both axes (kTileBatch x kTileRow each), the batch's samples and, in FP64, the
+// window polynomial coefficients of points 0..m-1 (at most kMaxM x 15 values, more than the
+// scalar registers hold).
+constexpr size_t tile_lds_wave(size_t rsize) {
+  return ((size_t)2 * kTileBatch * kTileRow + (size_t)2 * kTileBatch +
+          (rsize == sizeof(double) ? (size_t)kMaxM * (Deg<double>::value + 1) : 0)) *
+         rsize;
+}
 
 template <typename T> struct Cx;
 template <> struct Cx<float> { using type = float2; };

@@ -449,6 +449,28 @@ __device__ __forceinline__ void window_values_lead(T z, const T *cf, const T *le
   }
 }
 
+// Window values as window_values computes them, the coefficients read as vector operands
+// (from a table in LDS: every lane reads the same entries).
+template <typename T, int MH>
+__device__ __forceinline__ void window_values_plain(T z, const T *c0, T (&psi)[2 * MH]) {
+  constexpr int D = Deg<T>::value;
+  constexpr int DE = D - (D & 1), DO = D - 1 + (D & 1);
+  const T z2 = z * z;
+#pragma unroll
+  for (int j = 0; j < MH; ++j) {
+    const T *c = c0 + j * (D + 1);
+    T e = c[DE];
+#pragma unroll
+    for (int q = DE - 2; q >= 0; q -= 2) e = fma(e, z2, c[q]);
+    T o = c[DO];
+#pragma unroll
+    for (int q = DO - 2; q >= 1; q -= 2) o = fma(o, z2, c[q]);
+    o *= z;
+    psi[j] = e + o;
+    psi[2 * MH - 1 - j] = e - o;
+  }
+}
+
 template <typename T, int MH>
 __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restrict__ xs,
                                                   const int32_t *__restrict__ perm, const OrderParams<T> &op,
@@ -477,20 +499,32 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
   const int nbat = (qend - qbeg + UB - 1) / UB;
   const int64_t vbase = (int64_t)r * ta.vstride;
   const int n = op.n, ntile = ta.ntile;
-  // window polynomial coefficients of points 0..m-1 (the others mirror them), in registers
+  // window polynomial coefficients of points 0..m-1 (the others mirror them): FP32 (8 per
+  // point) in scalar registers, with the leading coefficient of each part in a vector
+  // register; FP64 (15 per point, more than the scalar registers hold: the compiler keeps
+  // them in vector-register lanes and reads them back one by one for every batch) in the
+  // wavefront's LDS, read as vector operands where used, up to m = 7 (at m = 8 that form
+  // takes over 300 registers, so it keeps the scalar form)
   constexpr int NC = MH * (Deg<T>::value + 1);
-  T cf[NC];
-#pragma unroll
-  for (int i = 0; i < NC; ++i) cf[i] = wave_uniform(op.poly[i]);
-  constexpr bool kLead = std::is_same<T, float>::value;   // (FP64 keeps its registers)
+  constexpr bool kLead = std::is_same<T, float>::value;
+  constexpr bool kTable = !kLead && MH <= 7;
+  T *const tbl = reinterpret_cast<T *>(Yw + UB);   // (kTable) NC coefficients
+  T cf[kTable ? 1 : NC];
   T lead[2 * MH];
+  if constexpr (kTable) {
+    for (int i = l; i < NC; i += 64) tbl[i] = op.poly[i];
+    wave_lds_sync();
+  } else {
 #pragma unroll
-  for (int i = 0; i < MH; ++i) {
-    constexpr int D = Deg<T>::value;
-    lead[2 * i] = cf[i * (D + 1) + D - (D & 1)];
-    lead[2 * i + 1] = cf[i * (D + 1) + D - 1 + (D & 1)];
-    if constexpr (kLead) {   // held in vector registers from here on
-      asm volatile("" : "+v"(lead[2 * i]));
+    for (int i = 0; i < NC; ++i) cf[i] = wave_uniform(op.poly[i]);
+  }
+  if constexpr (kLead) {
+#pragma unroll
+    for (int i = 0; i < MH; ++i) {
+      constexpr int D = Deg<T>::value;
+      lead[2 * i] = cf[i * (D + 1) + D - (D & 1)];
+      lead[2 * i + 1] = cf[i * (D + 1) + D - 1 + (D & 1)];
+      asm volatile("" : "+v"(lead[2 * i]));   // held in vector registers from here on
       asm volatile("" : "+v"(lead[2 * i + 1]));
     }
   }
@@ -526,6 +560,8 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
     T psi[W];
     if constexpr (kLead)
       window_values_lead<T, MH>(z, cf, lead, psi);
+    else if constexpr (kTable)
+      window_values_plain<T, MH>(z, tbl, psi);
     else
       window_values<T, MH>(z, cf, psi);
     const int ty = div_tile<TS>(h ? fo : fh), tx = div_tile<TS>(h ? fh : fo);
