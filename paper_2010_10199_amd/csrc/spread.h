@@ -586,23 +586,40 @@ __device__ __forceinline__ void spread_tile2_body(const Blk bk, const T *__restr
         cur_tile = t;
       }
       Yw[j] = in ? st.y : cmake<T>((T)0, (T)0);   // (both halves write the same value)
+      // the tile's nodes lie in steps q0 .. q1 (node j in step j / 4; lane j holds node j);
+      // the other steps carry zero samples only and are skipped, which leaves the patch as it is
+      constexpr bool kSkip = std::is_same<T, float>::value || MH == 8;
+      const unsigned long long inm = __ballot(in);
+      const unsigned lo = (unsigned)inm;
+      const int q0 = (__ffs((int)lo) - 1) >> 2, q1 = (31 - __clz((int)lo)) >> 2;
       wave_lds_sync();
-      T av[UB / 4], bv[UB / 4];
-      C yv[UB / 4];
+      // (FP64 below m = 8 runs every step: the second path costs it a wavefront per SIMD)
+      if (!kSkip || (q0 == 0 && q1 == UB / 4 - 1)) {   // every step holds a node of the tile
+        T av[UB / 4], bv[UB / 4];
+        C yv[UB / 4];
 #pragma unroll
-      for (int q = 0; q < UB / 4; ++q) {
-        av[q] = SAw[(4 * q + kk) * SR + i16];
-        bv[q] = SBw[(4 * q + kk) * SR + i16];
-        yv[q] = Yw[4 * q + kk];
-      }
+        for (int q = 0; q < UB / 4; ++q) {
+          av[q] = SAw[(4 * q + kk) * SR + i16];
+          bv[q] = SBw[(4 * q + kk) * SR + i16];
+          yv[q] = Yw[4 * q + kk];
+        }
 #pragma unroll
-      for (int q = 0; q < UB / 4; ++q) {
-        are = MF::run(av[q] * yv[q].x, bv[q], are);
-        aim = MF::run(av[q] * yv[q].y, bv[q], aim);
+        for (int q = 0; q < UB / 4; ++q) {
+          are = MF::run(av[q] * yv[q].x, bv[q], are);
+          aim = MF::run(av[q] * yv[q].y, bv[q], aim);
+        }
+      } else {
+#pragma unroll 1
+        for (int q = q0; q <= q1; ++q) {
+          const T av = SAw[(4 * q + kk) * SR + i16], bv = SBw[(4 * q + kk) * SR + i16];
+          const C yv = Yw[4 * q + kk];
+          are = MF::run(av * yv.x, bv, are);
+          aim = MF::run(av * yv.y, bv, aim);
+        }
       }
       wave_lds_sync();
       dirty = true;
-      pending &= ~__ballot(in);
+      pending &= ~inm;
     }
   };
 
