@@ -31,7 +31,8 @@ __device__ __forceinline__ int cell_of(T x, int n) {
 template <typename T>
 __global__ void k_bin_keys(const T *__restrict__ xT, int64_t Mtot, const DevTerm *__restrict__ terms, int term_begin,
                            int tl0, int tl1, int order, int n, int ts, int ntile, int64_t nkey, int B,
-                           const int64_t *__restrict__ offs, uint32_t *__restrict__ keys, int32_t *__restrict__ vals) {
+                           const int64_t *__restrict__ offs, int cell_only, uint32_t *__restrict__ keys,
+                           int32_t *__restrict__ vals) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)(tl1 - tl0) * Mtot;
   if (idx >= total) return;
@@ -59,7 +60,7 @@ __global__ void k_bin_keys(const T *__restrict__ xT, int64_t Mtot, const DevTerm
     }
     b = lo;
   }
-  keys[idx] = (uint32_t)(((int64_t)tl * B + b) * nkey + cell);
+  keys[idx] = cell_only ? (uint32_t)cell : (uint32_t)(((int64_t)tl * B + b) * nkey + cell);
   vals[idx] = (int32_t)i;
 }
 
@@ -73,6 +74,29 @@ __global__ void k_bin_starts(const uint32_t *__restrict__ skeys, int64_t count, 
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if (skeys[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  cstart[k0 + j] = base + lo;
+}
+
+// The same after a segmented sort whose keys are the cell numbers alone, each (term, dataset)
+// segment of the batch sorted on its own (segment i spans [seg[i], seg[i + 1]) of the batch):
+// key k = (segment) nkey + cell starts at the first position of its segment whose cell is
+// >= cell, which is where the full keys' sort puts it.
+__global__ void k_bin_starts_seg(const uint32_t *__restrict__ scell, int64_t count, uint32_t k0, uint32_t k1,
+                                 int64_t nkey, const int32_t *__restrict__ seg, int nseg, int64_t base,
+                                 int64_t *__restrict__ cstart) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > (int64_t)k1 - k0) return;
+  const int64_t sg = j / nkey;
+  if (sg >= nseg) {   // the end key: the batch's end
+    cstart[k0 + j] = base + count;
+    return;
+  }
+  const uint32_t cell = (uint32_t)(j - sg * nkey);
+  int64_t lo = seg[sg], hi = seg[sg + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (scell[mid] < cell) lo = mid + 1; else hi = mid;
   }
   cstart[k0 + j] = base + lo;
 }
@@ -267,9 +291,18 @@ static int bin_end_bit(const gt_plan *pl, int t) {
 // The launches of one order's binning into o.d_perm, o.d_cstart (and o.d_xs for order 2),
 // given key/value scratch for one batch and the sort's temporary storage (no allocation, no
 // synchronisation).
+// Segmented form (seg != nullptr, ragged plans after a node update): the input is already
+// grouped by (term, dataset), so each segment is sorted on its own by the cell number alone
+// (ceil(log2 nkey) key bits instead of the full key's), stably, which gives the same order.
+static int cell_bits(int64_t nkey) {
+  int b = 1;
+  while ((int64_t(1) << b) < nkey) ++b;
+  return b;
+}
+
 template <typename T>
 static int bin_order(gt_plan *pl, int t, hipStream_t s, const int64_t *d_offs, uint32_t *kin, uint32_t *kout,
-                     int32_t *vin, void *tmp, size_t tmp_bytes) {
+                     int32_t *vin, void *tmp, size_t tmp_bytes, const int32_t *seg = nullptr) {
   OrderHost &o = pl->ord[t];
   const int B = pl->ragged ? pl->R : 1;
   const int nt = o.term_end - o.term_begin;
@@ -279,16 +312,25 @@ static int bin_order(gt_plan *pl, int t, hipStream_t s, const int64_t *d_offs, u
     const int tl1 = std::min(nt, tl0 + tpb);
     const int64_t cnt = (int64_t)(tl1 - tl0) * Mtot;
     hipLaunchKernelGGL((k_bin_keys<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (const T *)pl->d_x,
-                       Mtot, pl->d_terms, o.term_begin, tl0, tl1, t, o.n, o.ts, o.ntile, nkey, B, d_offs, kin, vin);
+                       Mtot, pl->d_terms, o.term_begin, tl0, tl1, t, o.n, o.ts, o.ntile, nkey, B, d_offs,
+                       seg ? 1 : 0, kin, vin);
     size_t tb = tmp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, o.d_perm + (int64_t)tl0 * Mtot,
-                                                       (int)cnt, 0, end_bit, s);
+    const int nseg = (tl1 - tl0) * B;
+    hipError_t e = seg ? hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tb, kin, kout, vin,
+                                                                      o.d_perm + (int64_t)tl0 * Mtot, (int)cnt, nseg,
+                                                                      seg, seg + 1, 0, cell_bits(nkey), s)
+                       : hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, o.d_perm + (int64_t)tl0 * Mtot,
+                                                            (int)cnt, 0, end_bit, s);
     if (e != hipSuccess) return hip_fail(e, "radix sort");
     const uint32_t k0 = (uint32_t)((int64_t)tl0 * B * nkey);
     const uint32_t k1 = (uint32_t)((int64_t)tl1 * B * nkey);   // inclusive end key (start of next batch)
     const int64_t nk = (int64_t)k1 - k0 + 1;
-    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, kout, cnt, k0, k1,
-                       (int64_t)tl0 * Mtot, o.d_cstart);
+    if (seg)
+      hipLaunchKernelGGL(k_bin_starts_seg, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, kout, cnt, k0, k1,
+                         nkey, seg, nseg, (int64_t)tl0 * Mtot, o.d_cstart);
+    else
+      hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, kout, cnt, k0, k1,
+                         (int64_t)tl0 * Mtot, o.d_cstart);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "binning kernels");
   }
@@ -369,17 +411,28 @@ int launch_rebin(gt_plan *pl, hipStream_t s) {
   if (!sc.ready) {
     int64_t cap = 1;
     size_t tmp_bytes = 0;
+    int maxtpb = 1;
     for (int t = 1; t <= pl->ds; ++t) {
       const OrderHost &o = pl->ord[t];
       if (o.term_end == o.term_begin) continue;
       const int64_t c = (int64_t)bin_batch_terms(pl, t) * pl->Mtot;
       cap = std::max(cap, c);
+      maxtpb = std::max(maxtpb, bin_batch_terms(pl, t));
       size_t tb = 0;
       hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                          (int32_t *)nullptr, (int32_t *)nullptr, (int)c, 0,
                                                          bin_end_bit(pl, t), s);
       if (e != hipSuccess) return hip_fail(e, "radix sort sizing");
       tmp_bytes = std::max(tmp_bytes, tb);
+      if (pl->ragged) {
+        const int nseg = bin_batch_terms(pl, t) * pl->R;
+        e = hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                        (int32_t *)nullptr, (int32_t *)nullptr, (int)c, nseg,
+                                                        (const int32_t *)nullptr, (const int32_t *)nullptr, 0,
+                                                        cell_bits(o.nkey), s);
+        if (e != hipSuccess) return hip_fail(e, "segmented radix sort sizing");
+        tmp_bytes = std::max(tmp_bytes, tb);
+      }
     }
     int rc;
     if ((rc = dev_alloc((void **)&sc.kin, cap * sizeof(uint32_t), s)) ||
@@ -390,13 +443,21 @@ int launch_rebin(gt_plan *pl, hipStream_t s) {
       if ((rc = dev_alloc((void **)&sc.offs, pl->offs.size() * sizeof(int64_t), s))) return rc;
       hipError_t e = hipMemcpy(sc.offs, pl->offs.data(), pl->offs.size() * sizeof(int64_t), hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(e, "binning offsets");
+      // segment i = (term tl, dataset b) = (i / R, i % R) of a batch starts at tl Mtot + offs[b]
+      std::vector<int32_t> sg((size_t)maxtpb * pl->R + 1);
+      for (int tl = 0; tl < maxtpb; ++tl)
+        for (int b = 0; b < pl->R; ++b) sg[(size_t)tl * pl->R + b] = (int32_t)(tl * pl->Mtot + pl->offs[b]);
+      sg[(size_t)maxtpb * pl->R] = (int32_t)(maxtpb * pl->Mtot);
+      if ((rc = dev_alloc((void **)&sc.seg, sg.size() * sizeof(int32_t), s))) return rc;
+      e = hipMemcpy(sc.seg, sg.data(), sg.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "segment offsets");
     }
     sc.tmp_bytes = tmp_bytes;
     sc.ready = true;
   }
   for (int t = 1; t <= pl->ds; ++t) {
     if (pl->ord[t].term_end == pl->ord[t].term_begin) continue;
-    if (int rc = bin_order<T>(pl, t, s, sc.offs, sc.kin, sc.kout, sc.vin, sc.tmp, sc.tmp_bytes)) return rc;
+    if (int rc = bin_order<T>(pl, t, s, sc.offs, sc.kin, sc.kout, sc.vin, sc.tmp, sc.tmp_bytes, sc.seg)) return rc;
   }
   return GT_OK;
 }

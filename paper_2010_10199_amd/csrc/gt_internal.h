@@ -180,6 +180,7 @@ struct RebinScratch {
   void *tmp = nullptr;
   size_t tmp_bytes = 0;
   int64_t *offs = nullptr;
+  int32_t *seg = nullptr;      // ragged plans: (term, dataset) segment starts of a key batch
   int32_t *segcnt = nullptr;
   int32_t segcnt_cap = 0;
 };

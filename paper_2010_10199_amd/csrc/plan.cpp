@@ -390,6 +390,7 @@ void free_plan(gt_plan *pl) {
   dev_free(pl->rebin.vin, nullptr);
   dev_free(pl->rebin.tmp, nullptr);
   dev_free(pl->rebin.offs, nullptr);
+  dev_free(pl->rebin.seg, nullptr);
   dev_free(pl->rebin.segcnt, nullptr);
   delete pl;
 }
