@@ -52,7 +52,7 @@ __global__ void k_bin_keys(const T *__restrict__ xT, int64_t Mtot, const DevTerm
     cell = ((int64_t)f0 * n + f1) * n + f2;
   }
   int b = 0;
-  if (offs) {   // dataset of node i: last b with offs[b] <= i
+  if (offs && !cell_only) {   // dataset of node i: last b with offs[b] <= i
     int lo = 0, hi = B;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
