@@ -377,7 +377,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // read it (the same single product as staging it, so the patch does not change), samples of
 // nodes outside the batch or the tile being zero.  The nodes of a batch usually share one
 // tile; when a tile ends inside the batch, the batch is run once per tile with the other
-// tiles' samples zeroed.  At each tile change the wavefront stores its finished patch, with plain
+// tiles' samples zeroed, each run taking only the MFMA steps that hold nodes of its tile (as
+// does a short last batch).  At each tile change the wavefront stores its finished patch, with plain
 // stores, in its next patch slot (slots are numbered per wavefront in tile order); the
 // fold kernel adds the patches into the grids in a fixed order.  Nothing is shared between
 // wavefronts, so there are no atomics and no workgroup barriers.
