@@ -263,6 +263,9 @@ UPDATE_CASES = [
     ("shared-R2-f32", 4, 2, (16, 8), 20000, 2, "f32"),
     ("shared-3d-f64", 4, 3, (8, 6, 4), 6000, 1, "f64"),
     ("ragged-f32", 3, 2, (12, 8), [4000, 0, 9000, 2500], 4, "f32"),
+    # the update's per-(term, dataset) sort: empty datasets first, last and in a row, one-node
+    # datasets
+    ("ragged-many-f64", 3, 2, (12, 8), [0, 1, 0, 0, 37, 5, 1, 2600, 0, 300, 0], 11, "f64"),
 ]
 
 
