@@ -358,6 +358,28 @@ int launch_binning(gt_plan *pl, hipStream_t s) {
     }
   }
   const int64_t Mtot = pl->Mtot;
+  // one set of key/value scratch and sort storage for all orders (sized for the largest batch)
+  int64_t cap = 1;
+  size_t tmp_bytes = 0;
+  for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+    const OrderHost &o = pl->ord[t];
+    if (o.term_end == o.term_begin) continue;
+    const int64_t c = (int64_t)bin_batch_terms(pl, t) * Mtot;
+    cap = std::max(cap, c);
+    size_t tb = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                       (int32_t *)nullptr, (int32_t *)nullptr, (int)c, 0,
+                                                       bin_end_bit(pl, t), s);
+    if (e != hipSuccess) rc = hip_fail(e, "radix sort sizing");
+    tmp_bytes = std::max(tmp_bytes, tb);
+  }
+  uint32_t *kin = nullptr, *kout = nullptr;
+  int32_t *vin = nullptr;
+  void *tmp = nullptr;
+  if (rc == GT_OK) rc = dev_alloc((void **)&kin, cap * sizeof(uint32_t), s);
+  if (rc == GT_OK) rc = dev_alloc((void **)&kout, cap * sizeof(uint32_t), s);
+  if (rc == GT_OK) rc = dev_alloc((void **)&vin, cap * sizeof(int32_t), s);
+  if (rc == GT_OK) rc = dev_alloc(&tmp, std::max<size_t>(tmp_bytes, 1), s);
   for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
     OrderHost &o = pl->ord[t];
     const int nt = o.term_end - o.term_begin;
@@ -370,31 +392,14 @@ int launch_binning(gt_plan *pl, hipStream_t s) {
     if ((rc = dev_alloc((void **)&o.d_perm, (size_t)nt * Mtot * sizeof(int32_t), s))) break;
     if ((rc = dev_alloc((void **)&o.d_cstart, (size_t)(K + 1) * sizeof(int64_t), s))) break;
     if (t == 2 && (rc = dev_alloc(&o.d_xs, (size_t)nt * Mtot * 2 * sizeof(T), s))) break;
-    const int64_t cap = (int64_t)bin_batch_terms(pl, t) * Mtot;
-    uint32_t *kin = nullptr, *kout = nullptr;
-    int32_t *vin = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
-    if ((rc = dev_alloc((void **)&kin, cap * sizeof(uint32_t), s)) ||
-        (rc = dev_alloc((void **)&kout, cap * sizeof(uint32_t), s)) ||
-        (rc = dev_alloc((void **)&vin, cap * sizeof(int32_t), s))) {
-      dev_free(kin, s);
-      dev_free(kout, s);
-      dev_free(vin, s);
-      break;
-    }
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, kin, kout, vin, o.d_perm, (int)cap, 0,
-                                                       bin_end_bit(pl, t), s);
-    if (e == hipSuccess) rc = dev_alloc(&tmp, tmp_bytes, s);
-    else rc = hip_fail(e, "radix sort sizing");
-    if (rc == GT_OK) rc = bin_order<T>(pl, t, s, d_offs, kin, kout, vin, tmp, tmp_bytes);
-    // keep the buffers alive until the stream has used them
-    (void)hipStreamSynchronize(s);
-    dev_free(tmp, s);
-    dev_free(kin, s);
-    dev_free(kout, s);
-    dev_free(vin, s);
+    rc = bin_order<T>(pl, t, s, d_offs, kin, kout, vin, tmp, tmp_bytes);
   }
+  // keep the buffers alive until the stream has used them
+  (void)hipStreamSynchronize(s);
+  dev_free(tmp, s);
+  dev_free(kin, s);
+  dev_free(kout, s);
+  dev_free(vin, s);
   if (d_offs) {
     (void)hipStreamSynchronize(s);
     dev_free(d_offs, s);

@@ -342,13 +342,61 @@ int upload_raw(const std::vector<V> &h, V **d) {
   return GT_OK;
 }
 
+// Idle side streams per device, reused by later plans: creating a stream takes about 0.7 ms
+// on this runtime and every plan takes one, so a plan returns its stream here when it is
+// destroyed (after the stream has drained) and the next plan on that device takes it.
+static std::mutex g_side_mu;
+static std::vector<std::pair<int, hipStream_t>> g_side_pool;
+constexpr size_t kSidePoolMax = 64;
+
+static hipStream_t take_side(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    for (size_t i = g_side_pool.size(); i-- > 0;)
+      if (g_side_pool[i].first == dev) {
+        const hipStream_t st = g_side_pool[i].second;
+        g_side_pool.erase(g_side_pool.begin() + (std::ptrdiff_t)i);
+        return st;
+      }
+  }
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return st;
+}
+
+static void give_side(hipStream_t st) {
+  if (!st) return;
+  (void)hipStreamSynchronize(st);
+  int dev = -1;
+  if (hipStreamGetDevice(st, &dev) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (g_side_pool.size() < kSidePoolMax) {
+      g_side_pool.emplace_back(dev, st);
+      return;
+    }
+  }
+  (void)hipGetLastError();
+  (void)hipStreamDestroy(st);
+}
+
+static void drain_side_pool() {
+  std::vector<std::pair<int, hipStream_t>> all;
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    all.swap(g_side_pool);
+  }
+  for (auto &e : all) (void)hipStreamDestroy(e.second);
+}
+
 void free_plan(gt_plan *pl) {
   if (!pl) return;
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
   drop_graphs(pl);
   if (pl->side) {
-    (void)hipStreamSynchronize(pl->side);
-    (void)hipStreamDestroy(pl->side);
+    give_side(pl->side);
     pl->side = nullptr;
   }
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
@@ -787,11 +835,11 @@ int build_plan(const gt_problem *p, const void *x, hipStream_t s, gt_plan **out)
   constexpr unsigned kSyncEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
   // side stream for independent per-order kernels (non-blocking, default priority); without
   // it everything runs on the caller's stream
-  if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_fork, kSyncEventFlags) != hipSuccess ||
+  pl->side = take_side(dev);
+  if (!pl->side || hipEventCreateWithFlags(&pl->ev_fork, kSyncEventFlags) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_join, kSyncEventFlags) != hipSuccess) {
     (void)hipGetLastError();
-    if (pl->side) (void)hipStreamDestroy(pl->side);
+    give_side(pl->side);
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
     pl->side = nullptr;
     pl->ev_fork = pl->ev_join = nullptr;
@@ -1256,6 +1304,7 @@ int gt_release_all(void) {
     all.swap(g_plans);
   }
   for (gt_plan *pl : all) free_plan(pl);
+  drain_side_pool();
   {
     std::lock_guard<std::mutex> lk(g_tab_mu);
     g_tab.clear();
