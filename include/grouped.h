@@ -366,10 +366,13 @@ int gt_active_set(const gt_problem *p, const double *rho, const double *eps, uin
 int gt_plan_norm_estimate(gt_plan *plan, int32_t iters, double *out, void *stream);
 
 /* ------------------------------------------------------------------ lifetime
- * gt_release_all: destroys every live plan (as gt_plan_destroy would) and clears the
- * process-wide window-table cache.  Handles of released plans become invalid: later calls
- * with them return GT_EINVAL (they are recognised, not dereferenced), as do calls with a
- * destroyed plan.  Synchronises the released plans' streams. */
+ * A destroyed plan's second stream (drained first) is kept per device and given to the
+ * next plan created there (at most 64 kept).
+ * gt_release_all: destroys every live plan (as gt_plan_destroy would), destroys the kept
+ * streams and clears the process-wide window-table and tuning caches.  Handles of released
+ * plans become invalid: later calls with them return GT_EINVAL (they are recognised, not
+ * dereferenced), as do calls with a destroyed plan.  Synchronises the released plans'
+ * streams. */
 int gt_release_all(void);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight serving
