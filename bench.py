@@ -954,6 +954,8 @@ def main():
     ap.add_argument("--draws", type=int, default=1,
                     help="node draws of the test-function experiments (the paper averages 100); means are reported")
     ap.add_argument("--no-c3", action="store_true", help="skip the batched-LSQR workload (d=20, M=500,000)")
+    ap.add_argument("--autograd-only", action="store_true",
+                    help="of the legs after the transform, run only the autograd one (profiles of the node updates)")
     ap.add_argument("--c3-steps", type=int, default=3, help="timed forward + adjoint steps of the d=20 workload")
     ap.add_argument("--c3-all-lambdas", action="store_true",
                     help="time the FP64-plain solve of all 16 lambda values (default: 4 of them)")
@@ -1052,7 +1054,7 @@ def main():
         out["fp64"] = {"value": node_terms * args.steps / (r64["ms"] * 1e-3), "unit": "node-terms/s",
                        "ms_per_step": r64["ms"] / args.steps, "forward_ms": r64["ms_fwd"] / args.steps,
                        "adjoint_ms": r64["ms_adj"] / args.steps, "tuning": r64["tuning"]}
-    if not args.no_solvers:
+    if not args.no_solvers and not args.autograd_only:
         print("[bench] solvers", file=sys.stderr, flush=True)
         out["solvers"] = run_solvers()
         print("[bench] active set", file=sys.stderr, flush=True)
@@ -1070,9 +1072,10 @@ def main():
             out["testfun_fista"]["mean_over_draws"] = {
                 e: {"draws": len(fruns), "best_l2_error": float(np.mean([r[e]["best_l2_error"] for r in fruns])),
                     "active_set_is_printed_U*": sum(r[e]["active_set_is_printed_U*"] for r in fruns)} for e in exps}
+    if not args.no_solvers or args.autograd_only:
         print("[bench] autograd", file=sys.stderr, flush=True)
         out["autograd"] = run_autograd()
-    if not args.no_solvers:
+    if not args.no_solvers and not args.autograd_only:
         print("[bench] cosine basis", file=sys.stderr, flush=True)
         out["cosine"] = run_cosine(max(5, args.steps // 2))
     if not args.no_c3:
