@@ -351,3 +351,45 @@ def test_update_nodes_matches_oracle(case):
     ref_f, ref_a = oracle(x1)
     check("after a rejected update forward", got_f, ref_f, fhat, TOL[prec], max_tol(prec, ds))
     plan.close()
+
+
+def test_side_streams_are_reused_across_plans():
+    """A destroyed plan's second stream goes to the next plan on the device: plans created one
+    after another, two plans alive at once, and a plan created after gt_release_all (which
+    destroys the kept streams) all match the oracle, with order 1 on the second stream."""
+    import torch
+    d, ds, N, M = 4, 2, (12, 6), 2000
+    iset = oidx.grouped_index_set(d, ds, N)
+    x = W.uniform_nodes(W.rng(77, W.P_NODES), M, d, "f64")
+    fhat = W.complex_normal(W.rng(77, W.P_COEFFS), (1, iset.n_coeffs), "f64")
+    y = W.complex_normal(W.rng(77, W.P_SAMPLES), (M,), "f64")
+    ref_f = otr.forward(iset, x, fhat).reshape(-1)
+    ref_a = otr.adjoint(iset, x, y.reshape(1, M)).reshape(-1)
+    xd, fd, yd = to_dev(x), to_dev(fhat.reshape(-1)), to_dev(y)
+
+    def new_plan():
+        p, keep = lib.make_problem(d, ds, N, M=M, R=1, dtype=lib.GT_C128)
+        return lib.Plan(p, xd, keepalive=keep)
+
+    def check_plan(pl, label):
+        f = torch.empty(M, dtype=torch.complex128, device="cuda")
+        a = torch.empty(iset.n_coeffs, dtype=torch.complex128, device="cuda")
+        pl.trafo(fd, f)
+        pl.adjoint(yd, a)
+        torch.cuda.synchronize()
+        check(f"{label} forward", f.cpu().numpy(), ref_f, fhat, TOL["f64"], max_tol("f64", ds))
+        check(f"{label} adjoint", a.cpu().numpy(), ref_a, y, TOL["f64"], max_tol("f64", ds))
+
+    for k in range(3):                      # one after another: each takes the last one's stream
+        pl = new_plan()
+        check_plan(pl, f"sequential {k}")
+        pl.close()
+    p1, p2 = new_plan(), new_plan()         # alive together: two different streams
+    check_plan(p1, "pair 1")
+    check_plan(p2, "pair 2")
+    p1.close()
+    p2.close()
+    lib.release_all()                       # the kept streams destroyed
+    pl = new_plan()
+    check_plan(pl, "after release")
+    pl.close()
