@@ -67,6 +67,19 @@ def counted_bytes(tj: dict, record: str, tuning: dict, khash: str):
     forms = ent.get("forms", {})
     if len(forms) <= 1:
         return ent.get("bytes_per_launch")
+    if record in ("gather_12", "pack_fwd_12"):
+        # shared launches of orders 1 and 2: the forms are template arguments, the gather's
+        # <T, m, order-1 form, order-2 form>, the pack's <T, m> with m = 0 unless order 2 is polynomial
+        code = {"sorted": 0, "cell": 1, "poly": 2}
+        ch = {o: (tuning or {}).get("gather", {}).get(o, {}).get("chosen") for o in ("1", "2")}
+        if record == "gather_12":
+            if ch["1"] not in code or ch["2"] not in code:
+                return None
+            tail = f", {code[ch['1']]}, {code[ch['2']]}>"
+            hit = [e for k, e in forms.items() if k.endswith(tail)]
+        else:
+            hit = [e for k, e in forms.items() if k.endswith(", 0>") == (ch["2"] != "poly")]
+        return hit[0]["bytes_per_launch"] if len(hit) == 1 else None
     order = record.rsplit("_", 1)[-1][:-1]
     chosen = (tuning or {}).get("gather", {}).get(order, {}).get("chosen")
     want = {("gather", "cell"): "k_gather_cell<", ("gather", "sorted"): "k_gather_sorted<",
@@ -81,7 +94,8 @@ def counted_bytes(tj: dict, record: str, tuning: dict, khash: str):
     return None
 
 
-def run_gpu(precision: str, steps: int, warmup: int, profile: bool, launch: str = "tuned"):
+def run_gpu(precision: str, steps: int, warmup: int, profile: bool, launch: str = "tuned",
+            count_forms: bool = False):
     import torch
     import workloads as W
     from paper_2010_10199_amd import lib
@@ -140,6 +154,17 @@ def run_gpu(precision: str, steps: int, warmup: int, profile: bool, launch: str 
             ms_eager = timed(steps)
             kern = lib.prof_report()
             lib.prof_enable(False)
+        if count_forms:                   # one forward in every window-gather form (counter runs)
+            keep_paths = (plan.gather_path(1), plan.gather_path(2))
+            o2 = [lib.GT_GATHER_SORTED, lib.GT_GATHER_CELL] + ([lib.GT_GATHER_POLY] if precision == "f32" else [])
+            for p1 in (lib.GT_GATHER_SORTED, lib.GT_GATHER_CELL):
+                for p2 in o2:
+                    plan.set_gather_path(1, p1)
+                    plan.set_gather_path(2, p2)
+                    plan.trafo(fd, f_out)
+                    torch.cuda.synchronize()
+            plan.set_gather_path(1, keep_paths[0])
+            plan.set_gather_path(2, keep_paths[1])
     plan.close()
     return dict(ms=ms, ms_fwd=ms_fwd, ms_adj=ms_adj, ms_eager=ms_eager, plan_ms=plan_ms, plan_ms_warm=plan_ms_warm,
                 nterms=nterms, tuning=tuning, tune_ms=tune_ms,
@@ -967,6 +992,8 @@ def main():
                          "sees, so profiling runs pin the mode the unprofiled run takes")
     ap.add_argument("--c3-forms", choices=["tune", "direct"], default="tune",
                     help="d=20 transform leg: tuned launch forms, or the direct sums for every order")
+    ap.add_argument("--count-forms", action="store_true",
+                    help="after the timed steps, one forward in every window-gather form (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -986,7 +1013,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print(f"[bench] fp32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    r32 = run_gpu("f32", args.steps, args.warmup, profile=True, launch=args.launch)
+    r32 = run_gpu("f32", args.steps, args.warmup, profile=True, launch=args.launch, count_forms=args.count_forms)
     node_terms = 2 * M * r32["nterms"]
     value = node_terms * args.steps / (r32["ms"] * 1e-3)
     out = {
