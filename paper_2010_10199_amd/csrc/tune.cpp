@@ -8,6 +8,7 @@
 // the fastest; the choice is cached per device and problem signature, so that later plans of
 // the same signature (other node draws of one workload) start from it without timing.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -122,8 +123,10 @@ int time_calls(gt_plan *pl, int dirs, const TuneBufs &b, hipStream_t s, hipEvent
 // Milliseconds per call of the kernels of order t in direction dir (0 forward, 1 adjoint):
 // the calls launch eagerly on one stream with an event pair per launch, and the launches whose
 // names end in "_<t>d" are summed (pack, gather or direct sums; spread, fold, adjoint DFT or
-// direct sums).  One call; when the order took less than 5 ms, one untimed call and then
-// enough calls for about 20 ms (2 to 20).
+// direct sums).  One call; when the order took less than 5 ms, one untimed call (left out when
+// the whole call took over 100 ms) and then enough calls for about 20 ms of the order's work
+// (2 to 20), but no more than about 200 ms of whole calls: every call runs all orders, and on
+// large plans a fast order's repetitions would otherwise cost seconds of the other orders' work.
 int time_order(gt_plan *pl, int dir, int t, const TuneBufs &b, hipStream_t s, double *ms) {
   char suffix[8];
   snprintf(suffix, sizeof(suffix), "_%dd", t);
@@ -141,11 +144,14 @@ int time_order(gt_plan *pl, int dir, int t, const TuneBufs &b, hipStream_t s, do
     return GT_OK;
   };
   double t1 = 0;
+  const auto w0 = std::chrono::steady_clock::now();
   int rc = calls(1, &t1);
+  const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
   if (rc == GT_OK && t1 < 5.0) {
     double warm = 0;
-    rc = calls(1, &warm);
-    if (rc == GT_OK) rc = calls(std::max(2, std::min(20, (int)(20.0 / std::max(1e-3, t1)))), &t1);
+    if (wall <= 100.0) rc = calls(1, &warm);
+    const int reps = std::min(std::min(20, (int)(20.0 / std::max(1e-3, t1))), (int)(200.0 / std::max(1e-3, wall)));
+    if (rc == GT_OK) rc = calls(std::max(2, reps), &t1);
   }
   prof_set(was);
   *ms = t1;
@@ -278,16 +284,19 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
   char tmp[160];
   int rc = GT_OK;
   double fwd_ms = 0, adj_ms = 0, both_ms = 0;
-  // 1. forward gather per order (coordinate descent, order by order)
+  // 1. forward gather per order (coordinate descent, order by order, the highest first: its
+  //    slow forms then run only while it is being timed, not in every call of the lower orders)
   js += ", \"gather\": {";
-  for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+  bool firstg = true;
+  for (int t = pl->ds; t >= 1 && rc == GT_OK; --t) {
     OrderHost &o = pl->ord[t];
     if (o.term_end == o.term_begin) continue;
     const int keep = o.path;
     int best = keep;
     double best_ms = 1e300;
-    snprintf(tmp, sizeof(tmp), "%s\"%d\": {", t > 1 && js.back() != '{' ? ", " : "", t);
+    snprintf(tmp, sizeof(tmp), "%s\"%d\": {", firstg ? "" : ", ", t);
     js += tmp;
+    firstg = false;
     bool first = true;
     for (int p = GT_GATHER_SORTED; p <= GT_GATHER_DIRECT && rc == GT_OK; ++p) {
       if (p == GT_GATHER_POLY && t != 2) continue;
@@ -350,7 +359,7 @@ int tune_plan(gt_plan *pl, hipStream_t s) {
   if (rc == GT_OK) {
     js += ", \"adjoint\": {";
     bool firsto = true;
-    for (int t = 1; t <= pl->ds && rc == GT_OK; ++t) {
+    for (int t = pl->ds; t >= 1 && rc == GT_OK; --t) {   // the highest first, as above
       OrderHost &o = pl->ord[t];
       if (o.term_end == o.term_begin || !direct_adj_ok(pl, t)) continue;
       double ms[2] = {0, 0};
